@@ -1,0 +1,181 @@
+"""Seeded synthetic fringe workloads.
+
+This module only draws inputs; it holds none of the demodulation arithmetic.
+Both sides of every parity check (the GPU library and the FP64 CPU oracle)
+receive the exact bytes produced here.
+
+Fringe model (paper, Sec. 2 and Eq. 1): a time-lapsed stack of carrier
+fringes  I = a + b*cos(carrier + phi) + noise,  where phi is the
+diffusion-induced phase.  The diffusion profile is the classical
+error-function solution of Fick's second law (paper, Appendix, Eq. 16):
+phi(y, t) = A * erf((y - y0) / w_t) with w_t = sqrt(4 D t).
+
+Noise convention: real frames get i.i.d. N(0, s2) with
+s2 = (b^2 / 2) * 10^(-SNR/10), i.e. SNR is measured against the AC fringe
+power.  Complex frames (Eq. 1 directly) get circular noise with
+E|eta|^2 = A^2 * 10^(-SNR/10).
+
+Workload recipes (all seeded):
+  cfg1  one 256x256 FP64 frame, carrier 1/8 cyc/px along x, phi = 2*erf((y-128)/16),
+        SNR 20 dB, seed 0; x windows N=16, L=4.
+  cfg2  100 frames of 1024x1024 FP32, carrier 0.1 cyc/px at 30 degrees,
+        phi = 6*erf((y-512)/w_t), w_t = 8*32^(t/99), SNR 10 dB, seed t;
+        x and y windows N=32, L=6.
+  cfg3  64 frames of mixed sizes 512x512 ... 2048x1536, L in {4,6,8},
+        N = 2L+8, SNR ~ U(5,20) dB, carrier ~ U(1/12,1/6) cyc/px at
+        U(30,60) degrees, w ~ U(16,128) px, seed 3000+k; FP32.
+  cfg4  16 frames of 4096x4096 stored FP16, carrier 1/8 cyc/px at 45 degrees,
+        phi = 6*erf((y-2048)/w_t), w_t = 16*16^(t/15), SNR 10 dB, seed 4000+t;
+        N=32, L=8.
+  cfg5  training lines of 128 samples, random carrier 1/16..1/4 cyc/px,
+        SNR 0..30 dB (surrogate training set).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.special import erf
+
+A_DC = 0.5
+B_AC = 0.4
+
+CFG3_SIZES = [(512, 512), (768, 512), (768, 768), (1024, 768),
+              (1024, 1024), (1536, 1024), (1536, 1536), (2048, 1536)]
+
+
+@dataclass
+class Frame:
+    """One synthetic frame plus the closed-form truth of its local frequency."""
+    data: np.ndarray            # (H, W) row-major; float16/32/64 or complex
+    L: int
+    N: int
+    dirs: str                   # "x", "y" or "xy"
+    truth_wx: object = None     # callable (ys, xs) -> rad/px, or None
+    truth_wy: object = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def width(self) -> int:
+        return self.data.shape[1]
+
+    @property
+    def height(self) -> int:
+        return self.data.shape[0]
+
+
+def _noise_sigma(snr_db: float) -> float:
+    return math.sqrt(B_AC * B_AC / 2.0 * 10.0 ** (-snr_db / 10.0))
+
+
+def erf_fringe(W, H, f0, angle_deg, amp, y0, w, snr_db, seed, dtype):
+    """I = a + b cos(2 pi f0 (x cos t + y sin t) + amp*erf((y-y0)/w)) + noise."""
+    th = math.radians(angle_deg)
+    fx, fy = f0 * math.cos(th), f0 * math.sin(th)
+    y = np.arange(H, dtype=np.float64)[:, None]
+    x = np.arange(W, dtype=np.float64)[None, :]
+    phase = 2.0 * math.pi * (fx * x + fy * y) + amp * erf((y - y0) / w)
+    img = A_DC + B_AC * np.cos(phase)
+    rng = np.random.default_rng(seed)      # an int seed or an existing Generator
+    img = img + rng.standard_normal((H, W)) * _noise_sigma(snr_db)
+    wx = 2.0 * math.pi * fx
+    wy0 = 2.0 * math.pi * fy
+
+    def truth_wx(ys, xs):
+        return np.full(np.broadcast(ys, xs).shape, wx)
+
+    def truth_wy(ys, xs):
+        ys = np.asarray(ys, dtype=np.float64)
+        val = wy0 + amp * 2.0 / math.sqrt(math.pi) * np.exp(-((ys - y0) / w) ** 2) / w
+        return np.broadcast_to(val, np.broadcast(ys, xs).shape)
+
+    return img.astype(dtype), truth_wx, truth_wy
+
+
+def cfg1() -> Frame:
+    """256x256 FP64, carrier 1/8 cyc/px along x, phi = 2 erf((y-128)/16), 20 dB, seed 0."""
+    W = H = 256
+    y = np.arange(H, dtype=np.float64)[:, None]
+    x = np.arange(W, dtype=np.float64)[None, :]
+    img = A_DC + B_AC * np.cos(2.0 * math.pi * x / 8.0 + 2.0 * erf((y - 128.0) / 16.0))
+    img = img + np.random.default_rng(0).standard_normal((H, W)) * _noise_sigma(20.0)
+    return Frame(img.astype(np.float64), L=4, N=16, dirs="x",
+                 truth_wx=lambda ys, xs: np.full(np.broadcast(ys, xs).shape, math.pi / 4),
+                 meta={"cfg": 1})
+
+
+def cfg2_frame(t: int) -> Frame:
+    W = H = 1024
+    w_t = 8.0 * 32.0 ** (t / 99.0)
+    img, twx, twy = erf_fringe(W, H, 0.1, 30.0, 6.0, 512.0, w_t, 10.0, t, np.float32)
+    return Frame(img, L=6, N=32, dirs="xy", truth_wx=twx, truth_wy=twy,
+                 meta={"cfg": 2, "t": t, "w": w_t})
+
+
+def cfg2(frames=range(100)) -> list:
+    return [cfg2_frame(t) for t in frames]
+
+
+def cfg3_frame(k: int) -> Frame:
+    W, H = CFG3_SIZES[k % 8]
+    L = [4, 6, 8][k % 3]
+    rng = np.random.default_rng(3000 + k)
+    snr = rng.uniform(5.0, 20.0)
+    f0 = rng.uniform(1.0 / 12.0, 1.0 / 6.0)
+    ang = rng.uniform(30.0, 60.0)
+    w = rng.uniform(16.0, 128.0)
+    # the noise continues the same generator stream after the four parameter draws
+    img, twx, twy = erf_fringe(W, H, f0, ang, 6.0, H / 2.0, w, snr, rng, np.float32)
+    return Frame(img, L=L, N=2 * L + 8, dirs="xy", truth_wx=twx, truth_wy=twy,
+                 meta={"cfg": 3, "k": k, "snr": snr, "f0": f0, "angle": ang, "w": w})
+
+
+def cfg3(frames=range(64)) -> list:
+    return [cfg3_frame(k) for k in frames]
+
+
+def cfg4_frame(t: int, size: int = 4096) -> Frame:
+    W = H = size
+    w_t = 16.0 * 16.0 ** (t / 15.0)
+    img, twx, twy = erf_fringe(W, H, 1.0 / 8.0, 45.0, 6.0, H / 2.0, w_t, 10.0, 4000 + t, np.float16)
+    return Frame(img, L=8, N=32, dirs="xy", truth_wx=twx, truth_wy=twy,
+                 meta={"cfg": 4, "t": t, "w": w_t})
+
+
+def cfg4(frames=range(16)) -> list:
+    return [cfg4_frame(t) for t in frames]
+
+
+def complex_tone(W, H, wx, wy, alpha=0.3, amp=1.0, snr_db=None, seed=0):
+    """Complex fringe of Eq. 1 with linear phase: A e^{j(alpha + wx x + wy y)} + eta."""
+    y = np.arange(H, dtype=np.float64)[:, None]
+    x = np.arange(W, dtype=np.float64)[None, :]
+    g = amp * np.exp(1j * (alpha + wx * x + wy * y))
+    if snr_db is not None:
+        rng = np.random.default_rng(seed)
+        s = amp * math.sqrt(10.0 ** (-snr_db / 10.0) / 2.0)
+        g = g + s * (rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W)))
+    return g
+
+
+def training_lines(n: int, seed: int, length: int = 128):
+    """Surrogate training lines: 0.5 + 0.4 cos(w n + theta) + noise.
+
+    w ~ U(2 pi/16, 2 pi/4), theta ~ U(0, 2 pi), SNR ~ U(0, 30) dB.
+    Returns (lines[n, length] float64, w[n]).
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(2 * math.pi / 16, 2 * math.pi / 4, n)
+    th = rng.uniform(0, 2 * math.pi, n)
+    snr = rng.uniform(0.0, 30.0, n)
+    m = np.arange(length, dtype=np.float64)[None, :]
+    sig = np.sqrt(B_AC * B_AC / 2.0 * 10.0 ** (-snr / 10.0))[:, None]
+    lines = A_DC + B_AC * np.cos(w[:, None] * m + th[:, None]) + rng.standard_normal((n, length)) * sig
+    return lines, w
+
+
+def random_frame(W, H, seed, dtype=np.float32, snr_db=10.0, f0=0.12, angle=40.0):
+    """Small erf fringe with arbitrary (possibly ragged) size for parity tests."""
+    img, twx, twy = erf_fringe(W, H, f0, angle, 4.0, H / 2.0, max(8.0, H / 6.0), snr_db, seed, dtype)
+    return img
