@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput of sliding-window root-MUSIC demodulation on one MI355X.
+
+Workload (default): 100 time-lapsed 1024x1024 FP32 fringe frames, carrier
+0.1 cyc/px at 30 degrees, erf diffusion phase, SNR 10 dB; local frequency
+along x and y with windows of N=32 samples and L=6 covariances, then FP64
+integration of both maps to phase.  One step = one bosmusic_demodulate call
+over all frames plus the integration of every frame, inputs resident in HBM.
+
+Prints one JSON line: Mpixel/s (frames*W*H / step time), the roofline of the
+dominant root-MUSIC kernel (algorithmic FP32 flops per launch / its mean
+launch duration from HIP events on its stream), the error against the FP64
+oracle on a sample, and the oracle's own throughput on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed), FLOP/s
+PEAK_HBM = 8.0e12
+
+
+def flops_per_window(L: int, N: int, sweeps: float, iters: float) -> dict:
+    """Algorithmic FP32 / FP64 flop count of one window of the HIP kernel.
+
+    FMA = 2 flops; add, mul, compare-free arithmetic, rcp/sqrt/rsq = 1 each.
+    sweeps and iters are the measured mean Jacobi sweeps and root iterations.
+    """
+    K = N - L + 1
+    n = 2 * L - 2
+    cov = K * (4 * L + 8 * L * (L - 1) // 2)
+    build_t = 3 * L * L + L + L * (L + 1) // 2
+    rot = 12 * L + 7
+    jac = sweeps * (L * (L - 1) // 2) * (rot + 2) + L * (L - 1)        # + final convergence test
+    coef = 8 * L * (L + 1) // 2
+    start = 4 * n + 40
+    aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
+    select = 11 * n
+    fp32 = cov + build_t + jac + coef + start + aberth + select + 20
+    fp64 = 3 * ((n + 1) * 32 + 60)
+    return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample, on the host cores
+# ---------------------------------------------------------------------------
+_SAMPLE_FRAMES = {}
+
+
+def _oracle_job(job):
+    import oracle
+    frame_idx, kind, idx, L, N = job
+    f = _SAMPLE_FRAMES[frame_idx]
+    if kind == "x":
+        g = oracle.to_complex_field(f[idx:idx + 1], 1)
+    else:
+        g = oracle.to_complex_field(f[:, idx:idx + 1].T, 1)
+    om = oracle.demod_lines(g, L, N)[0]
+    return job, om
+
+
+def cpu_baseline(frames, sample_frames, lines_per_dir, L, N, workers):
+    """Time the oracle on sampled rows and columns with a process pool.
+
+    Runs before the GPU is touched; the pool forks with the frames already in
+    memory, so the timed region holds oracle work only."""
+    import multiprocessing as mp
+    _SAMPLE_FRAMES.clear()
+    _SAMPLE_FRAMES.update({t: frames[t] for t in sample_frames})
+    jobs = []
+    for t in sample_frames:
+        for i in range(lines_per_dir):
+            r = (37 + i * 1024 // lines_per_dir) % 1024
+            jobs.append((t, "x", r, L, N))
+            jobs.append((t, "y", r, L, N))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_job, jobs[:workers], chunksize=1)        # import warm-up, untimed
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+    windows = sum(int(np.isfinite(om).sum()) for _, om in res)
+    return res, windows, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample: lines per direction per frame")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (frames are independent; "
+              "see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    W = H = 1024
+    L, N = 6, 32
+    nf = args.frames
+    t_gen = time.perf_counter()
+    frames = [wl.cfg2_frame(t).data for t in range(nf)]
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated {nf} frames in {t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    cpu = None
+    sample = None
+    if not args.no_cpu:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        sf = sorted({0, nf // 3, (2 * nf) // 3, nf - 1})
+        res, windows, osec = cpu_baseline(frames, sf, args.cpu_lines, L, N, workers)
+        sample = res
+        px_s = windows / osec / 2.0            # two directions per pixel
+        cpu = {"value": px_s / 1e6, "unit": "Mpixel/s", "cores": workers, "kind": "oracle",
+               "sample": f"cfg2 frames {sf}, {args.cpu_lines} rows + {args.cpu_lines} columns each "
+                         f"({windows} windows, {osec:.1f}s wall on {workers} processes); "
+                         f"Mpixel/s = windows/s / 2 directions"}
+        print(f"# oracle: {windows} windows in {osec:.2f}s on {workers} procs", file=sys.stderr, flush=True)
+
+    import torch
+    import paper_1910_11872_amd as bm
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    d_frames = [torch.from_numpy(f).to(dev) for f in frames]
+    wx = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(nf)]
+    wy = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(nf)]
+    phi = [torch.empty((H, W), dtype=torch.float64, device=dev) for _ in range(nf)]
+    specs = [bm.FrameSpec(d_frames[i], L, N, bm.BM_DIR_X | bm.BM_DIR_Y, wx[i], wy[i]) for i in range(nf)]
+    dem = bm.Demodulator(0, max_width=W, max_height=H, timing=True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        bm.bosmusic_demodulate(dem.h, specs, bm.BM_PLAIN, stream)
+        for i in range(nf):
+            bm.bosmusic_integrate(dem.h, wx[i], wy[i], N, N, 0.0, 0.0, phi[i], stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dem.stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = dem.stats(reset=True)
+    ms = (t1 - t0) * 1e3 / args.steps
+    mpx = nf * W * H / (ms / 1e3) / 1e6
+    print(f"# {args.steps} steps, {ms:.2f} ms/step, {mpx:.1f} Mpixel/s", file=sys.stderr, flush=True)
+
+    # iteration counts of the same workload (stats variant of the kernel, outside the timed region)
+    sdem = bm.Demodulator(0, max_width=W, max_height=H, stats=True)
+    ow = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(2)]
+    for i in sorted({0, nf // 2, nf - 1}):
+        bm.bosmusic_demodulate(sdem.h, [bm.FrameSpec(d_frames[i], L, N, 3, ow[0], ow[1])], bm.BM_PLAIN, stream)
+    ss = sdem.stats(reset=True)
+    sdem.close()
+    mean_sweeps = ss["jacobi_sweeps"] / max(1, ss["windows"])
+    mean_iters = ss["root_iters"] / max(1, ss["windows"])
+    fl = flops_per_window(L, N, mean_sweeps, mean_iters)
+    win_per_launch = H * (W - N + 1)
+    avg_launch_s = st["rm_time_ns"] / max(1, st["rm_launches"]) / 1e9
+    achieved = fl["total"] * win_per_launch / avg_launch_s
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+            "kernel": f"rootmusic_kernel<L=6>, {win_per_launch} windows/launch, "
+                      f"{fl['total']:.0f} flop/window (mean {mean_sweeps:.2f} Jacobi sweeps, "
+                      f"{mean_iters:.2f} root iterations), mean launch {avg_launch_s * 1e3:.3f} ms over "
+                      f"{st['rm_launches']} launches"}
+
+    err = None
+    if sample is not None:
+        ds = []
+        for (t, kind, idx, _, _), om in sample:
+            got = (wx[t][idx] if kind == "x" else wy[t][:, idx]).cpu().numpy().astype(np.float64)
+            m = np.isfinite(om)
+            assert np.array_equal(m, np.isfinite(got))
+            ds.append(np.abs((got[m] - om[m] + np.pi) % (2 * np.pi) - np.pi))
+        d = np.concatenate(ds)
+        err = {"vs_oracle_p999": float(np.quantile(d, 0.999)), "vs_oracle_max": float(d.max()),
+               "vs_oracle_rms": float(np.sqrt(np.mean(d * d))), "windows": int(d.size), "unit": "rad/px"}
+
+    out = {
+        "metric": "Mpixel/s local-frequency demod (plain vs surrogate) at stated rad/px error",
+        "value": mpx,
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{nf} time-lapsed 1024x1024 FP32 fringe frames, carrier 0.1 cyc/px at 30 deg, "
+                               f"6*erf diffusion phase, SNR 10 dB; x and y windows N=32, L=6; plain root-MUSIC "
+                               f"+ FP64 phase integration",
+                   "frames": nf, "width": W, "height": H, "L": L, "N": N, "dirs": "xy", "mode": "plain"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "error": err,
+    }
+    print(json.dumps(out))
+    dem.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,121 @@
+// FP64 trapezoid integration of the local-frequency maps to phase.
+//
+// The paper recovers the global phase from the per-window estimates
+// (Sec. 3, after Eq. 15); here the phase is the path integral of the
+// frequency maps on the window-centre grid:
+//   anchor column xa = floor(Nx/2), anchor row ya = floor(Ny/2), phi(ya,xa) = 0,
+//   phi(y+1, xa) = phi(y, xa) + (wy(y,xa) + wy(y+1,xa))/2 - cy,
+//   phi(y, x+1)  = phi(y, x)  + (wx(y,x)  + wx(y,x+1))/2  - cx.
+// Both scans are block-wide prefix sums in FP64: each thread scans a
+// contiguous chunk held in LDS, the chunk totals are scanned across the
+// block, and the offsets are added back before a coalesced store.
+#include "bm_internal.h"
+
+namespace bm {
+namespace {
+
+constexpr int kAnchorThreads = 1024;
+constexpr int kRowThreads = 256;
+
+// Inclusive block scan (Hillis-Steele) of one double per thread.
+template <int T>
+__device__ double block_scan_exclusive(double v, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < T; off <<= 1) {
+        const double a = (t >= off) ? sh[t - off] : 0.0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    const double incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kAnchorThreads) void anchor_kernel(const float* __restrict__ wy, int W, int xa, int y0,
+                                                                int y1, double cy, double* __restrict__ anchor) {
+    __shared__ double sh[kAnchorThreads];
+    const int nsteps = y1 - y0;
+    const int chunk = (nsteps + kAnchorThreads - 1) / kAnchorThreads;
+    const int t = threadIdx.x;
+    const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const double a = wy[(int64_t)(y0 + i) * W + xa], b = wy[(int64_t)(y0 + i + 1) * W + xa];
+        acc += 0.5 * (a + b) - cy;
+        anchor[y0 + i + 1] = acc;  // local prefix, offset added below
+    }
+    const double off = block_scan_exclusive<kAnchorThreads>(acc, sh);
+    for (int i = i0; i < i1; ++i) anchor[y0 + i + 1] += off;
+    if (t == 0) anchor[y0] = 0.0;
+}
+
+// One block per row.  LDS: row of omega (float, W) + local prefixes (double, W).
+__global__ __launch_bounds__(kRowThreads) void rows_kernel(const float* __restrict__ wx, int W, int H, int x0, int x1,
+                                                           int y0, int y1, double cx, const double* __restrict__ anchor,
+                                                           double* __restrict__ phi) {
+    extern __shared__ double dyn[];
+    __shared__ double sh[kRowThreads];
+    double* sp = dyn;                              // W doubles
+    float* sw = reinterpret_cast<float*>(dyn + W);  // W floats
+    const int y = blockIdx.x;
+    double* out = phi + (int64_t)y * W;
+    const double nan = __builtin_nan("");
+    if (y < y0 || y > y1 || x1 < x0) {
+        for (int x = threadIdx.x; x < W; x += kRowThreads) out[x] = nan;
+        return;
+    }
+    const float* row = wx + (int64_t)y * W;
+    for (int x = threadIdx.x; x < W; x += kRowThreads) sw[x] = row[x];
+    __syncthreads();
+    const int nsteps = x1 - x0;
+    const int chunk = (nsteps + kRowThreads - 1) / kRowThreads;
+    const int t = threadIdx.x;
+    const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        acc += 0.5 * ((double)sw[x0 + i] + (double)sw[x0 + i + 1]) - cx;
+        sp[x0 + i + 1] = acc;
+    }
+    const double off = block_scan_exclusive<kRowThreads>(acc, sh);
+    const double base = anchor ? anchor[y] : 0.0;
+    for (int i = i0; i < i1; ++i) sp[x0 + i + 1] += off;
+    __syncthreads();
+    for (int x = threadIdx.x; x < W; x += kRowThreads) {
+        double v = nan;
+        if (x == x0) v = base;
+        else if (x > x0 && x <= x1) v = base + sp[x];
+        out[x] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_integrate(const float* wx, const float* wy, int W, int H, int Nx, int Ny, double cx, double cy,
+                            double* anchor_ws, double* phi, hipStream_t s) {
+    const int x0 = Nx / 2, x1 = W - Nx + Nx / 2;
+    int y0 = 0, y1 = H - 1;
+    const double* anchor = nullptr;
+    if (wy) {
+        y0 = Ny / 2;
+        y1 = H - Ny + Ny / 2;
+        if (y1 >= y0 && x1 >= x0) {
+            hipLaunchKernelGGL(anchor_kernel, dim3(1), dim3(kAnchorThreads), 0, s, wy, W, x0, y0, y1, cy, anchor_ws);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        anchor = anchor_ws;
+    }
+    const size_t shmem = (size_t)W * (sizeof(double) + sizeof(float));
+    hipLaunchKernelGGL(rows_kernel, dim3(H), dim3(kRowThreads), shmem, s, wx, W, H, x0, x1, y0, y1, cx, anchor, phi);
+    return hipGetLastError();
+}
+
+hipError_t integrate_set_attributes() {
+    return hipFuncSetAttribute((const void*)rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kMaxFFT * (int)(sizeof(double) + sizeof(float)));
+}
+
+}  // namespace bm

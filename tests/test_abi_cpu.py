@@ -1,0 +1,89 @@
+"""CPU-only checks of the C-ABI library: it builds, loads, exports every
+symbol the public header declares, and its host-side paths behave without a
+GPU (no compute is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bosmusic.h")
+
+
+def _lib():
+    import paper_1910_11872_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1910_11872_amd import build
+        build.build()
+    return pkg, pkg.lib()
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bosmusic_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "bosmusic_integrate"):
+        assert name in fns
+
+
+def test_library_exports_every_header_symbol():
+    pkg, L = _lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+    assert set(pkg.ABI_FUNCTIONS) == set(header_functions())
+
+
+def test_version_and_status_strings():
+    pkg, L = _lib()
+    assert pkg.bosmusic_version() == 1
+    assert pkg.bosmusic_status_string(0) == "ok"
+    assert pkg.bosmusic_status_string(-1) == "invalid argument"
+    assert pkg.bosmusic_status_string(-2) == "unsupported"
+    assert pkg.bosmusic_status_string(12345) == "unknown status"
+
+
+def test_struct_layout_matches_header():
+    pkg, _ = _lib()
+    # bosmusic_frame: pointer, 3 x int32, int64, 2 x int32, uint32, 3 pointers
+    assert ctypes.sizeof(pkg.bosmusic_frame) == 72
+    assert pkg.bosmusic_frame.row_stride.offset == 24
+    assert pkg.bosmusic_frame.omega_x.offset == 48
+    assert ctypes.sizeof(pkg.bosmusic_config) == 16
+    assert ctypes.sizeof(pkg.bosmusic_stats) == 48
+
+
+def test_null_arguments_are_rejected_without_device_work():
+    pkg, L = _lib()
+    assert L.bosmusic_create(None, None) == pkg.BM_E_INVALID_ARG
+    assert L.bosmusic_demodulate(None, None, 0, 0, None) == pkg.BM_E_INVALID_ARG
+    assert L.bosmusic_integrate(None, None, None, 1, 1, 1, 1, 0.0, 0.0, None, None) == pkg.BM_E_INVALID_ARG
+    assert L.bosmusic_get_stats(None, None, 0, None) == pkg.BM_E_INVALID_ARG
+    assert L.bosmusic_destroy(None) == pkg.BM_OK
+    cfg = pkg.bosmusic_config(0, 0, 64, 0)
+    h = ctypes.c_void_p()
+    assert L.bosmusic_create(ctypes.byref(cfg), ctypes.byref(h)) == pkg.BM_E_INVALID_ARG
+    assert h.value is None
+    assert "max size" in pkg.bosmusic_last_error(None)
+
+
+def test_create_without_gpu_reports_device_error():
+    from conftest import gpu_available
+    if gpu_available():
+        pytest.skip("a GPU is visible")
+    pkg, L = _lib()
+    cfg = pkg.bosmusic_config(0, 64, 64, 0)
+    h = ctypes.c_void_p()
+    assert L.bosmusic_create(ctypes.byref(cfg), ctypes.byref(h)) == pkg.BM_E_DEVICE
+    assert h.value is None
+
+
+def test_binding_has_no_cpu_fallback():
+    """The package never imports the oracle and fails loudly without its library."""
+    src = open(os.path.join(ROOT, "paper_1910_11872_amd", "__init__.py")).read()
+    assert "oracle" not in src
+    assert "raise ImportError" in src

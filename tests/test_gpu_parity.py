@@ -1,0 +1,286 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU launches span
+several 256-wide window tiles and a ragged tail; full-size workloads are
+compared on sampled lines.  Bar: |d omega| <= 1e-4 rad/px at the 99.9th
+percentile, identical NaN patterns; phi to 1e-9 rad when integrating the same
+omega maps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from parity_util import compare_omega, oracle_cols, oracle_rows, wrap
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def dem(bm, torch):
+    d = bm.Demodulator(0, max_width=4096, max_height=4096, stats=True)
+    yield d
+    d.close()
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def run(dem, torch, img, L, N, dirs):
+    wx, wy = dem.demodulate(to_dev(torch, img), L, N, dirs)
+    torch.cuda.synchronize()
+    return (wx.cpu().numpy() if wx is not None else None, wy.cpu().numpy() if wy is not None else None)
+
+
+# ---------------------------------------------------------------------------
+# cfg1 in full (256x256 FP64, x, L=4, N=16)
+# ---------------------------------------------------------------------------
+def test_cfg1_full(dem, torch):
+    f = wl.cfg1()
+    gx, _ = run(dem, torch, f.data, f.L, f.N, "x")
+    ox, _ = oracle.demodulate(f.data, f.L, f.N, "x")
+    s = compare_omega(gx, ox, "cfg1")
+    print("cfg1", s)
+    # accuracy against the truth is the oracle's, not worse
+    v = np.isfinite(gx)
+    assert math.sqrt(np.mean((gx[v] - math.pi / 4) ** 2)) < 1.1 * math.sqrt(np.mean((ox[v] - math.pi / 4) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Ragged sizes, every L, every real dtype, both directions
+# ---------------------------------------------------------------------------
+CASES = [
+    # (W, H, L, N, dtype)
+    (600, 40, 2, 6, np.float32),
+    (300, 36, 3, 11, np.float64),
+    (640, 30, 4, 16, np.float16),
+    (270, 48, 5, 14, np.float32),
+    (576, 40, 6, 32, np.float32),
+    (250, 45, 7, 20, np.float64),
+    (512, 32, 8, 32, np.float16),
+    (360, 60, 8, 64, np.float32),
+]
+
+
+@pytest.mark.parametrize("W,H,L,N,dt", CASES)
+def test_ragged_frames_both_directions(dem, torch, W, H, L, N, dt):
+    img = wl.random_frame(W, H, seed=W + 7 * H + L, dtype=dt, snr_db=8.0)
+    gx, gy = run(dem, torch, img, L, N, "xy")
+    ox, oy = oracle.demodulate(img, L, N, "xy")
+    print("x", compare_omega(gx, ox, f"x {W}x{H} L{L} N{N} {dt.__name__}"))
+    print("y", compare_omega(gy, oy, f"y {W}x{H} L{L} N{N} {dt.__name__}"))
+
+
+def test_complex_input_tones_exact(dem, torch):
+    """C32 input (Gamma of Eq. 1 given directly): a linear-phase tone is exact to FP32."""
+    W, H = 300, 70
+    for (wx0, wy0) in [(0.7, -0.4), (-2.5, 1.9), (0.05, 3.0)]:
+        g = wl.complex_tone(W, H, wx0, wy0).astype(np.complex64)
+        gx, gy = run(dem, torch, g, 6, 20, "xy")
+        assert np.nanmax(np.abs(wrap(gx - wx0))) < 2e-5
+        assert np.nanmax(np.abs(wrap(gy - wy0))) < 2e-5
+        ox, oy = oracle.demodulate(g, 6, 20, "xy")
+        compare_omega(gx, ox, "tone x")
+        compare_omega(gy, oy, "tone y")
+
+
+def test_chirp_matches_derivative_at_window_centre(dem, torch):
+    W, H = 512, 8
+    m = np.arange(W)
+    c = 1.5e-3
+    g = np.exp(1j * (0.4 * m + c * m * m))[None, :].repeat(H, 0).astype(np.complex64)
+    for L, N in [(4, 16), (8, 32), (5, 13)]:
+        gx, _ = run(dem, torch, g, L, N, "x")
+        lo, hi = oracle.valid_range(W, N)
+        centre = np.arange(lo, hi + 1) - N // 2 + (N - 1) / 2
+        err = np.abs(wrap(gx[:, lo:hi + 1] - (0.4 + 2 * c * centre)))
+        assert err.max() < 5e-5, (L, N, err.max())
+
+
+def test_noisy_complex_low_snr(dem, torch):
+    """0 dB complex tones, small K: the regime where the selection is least stable."""
+    g = wl.complex_tone(400, 60, 0.9, 0.3, snr_db=0.0, seed=11).astype(np.complex64)
+    for L, N in [(4, 8), (4, 16), (8, 32)]:
+        gx, gy = run(dem, torch, g, L, N, "xy")
+        ox, oy = oracle.demodulate(g, L, N, "xy")
+        print(L, N, compare_omega(gx, ox, f"0dB x L{L} N{N}"), compare_omega(gy, oy, f"0dB y L{L} N{N}"))
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, sampled lines
+# ---------------------------------------------------------------------------
+def test_cfg2_frame_full_size_sampled(dem, torch):
+    f = wl.cfg2_frame(50)
+    gx, gy = run(dem, torch, f.data, f.L, f.N, "xy")
+    rows = list(range(3, 1024, 97))
+    cols = list(range(5, 1024, 101))
+    print("x", compare_omega(gx[rows], oracle_rows(f.data, rows, f.L, f.N), "cfg2 x"))
+    print("y", compare_omega(gy[:, cols].T, oracle_cols(f.data, cols, f.L, f.N), "cfg2 y"))
+
+
+def test_cfg3_uneven_sampled(dem, torch):
+    for k in (0, 4, 7, 11):
+        f = wl.cfg3_frame(k)
+        gx, gy = run(dem, torch, f.data, f.L, f.N, "xy")
+        rows = list(range(1, f.height, f.height // 6))
+        cols = list(range(2, f.width, f.width // 6))
+        compare_omega(gx[rows], oracle_rows(f.data, rows, f.L, f.N), f"cfg3 k{k} x")
+        compare_omega(gy[:, cols].T, oracle_cols(f.data, cols, f.L, f.N), f"cfg3 k{k} y")
+
+
+def test_cfg4_frame_fp16_full_size_sampled(dem, torch):
+    f = wl.cfg4_frame(15)
+    gx, gy = run(dem, torch, f.data, f.L, f.N, "xy")
+    rows = [7, 1500, 2047, 2048, 3999]
+    cols = [9, 2048, 4000]
+    print("x", compare_omega(gx[rows], oracle_rows(f.data, rows, f.L, f.N), "cfg4 x"))
+    print("y", compare_omega(gy[:, cols].T, oracle_cols(f.data, cols, f.L, f.N), "cfg4 y"))
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+def test_zero_frame_and_oversized_window_are_nan(dem, torch):
+    z = np.zeros((40, 300), np.float32)
+    gx, gy = run(dem, torch, z, 4, 12, "xy")
+    assert np.all(np.isnan(gx)) and np.all(np.isnan(gy))
+    img = wl.random_frame(30, 20, seed=3)
+    gx, gy = run(dem, torch, img, 4, 32, "xy")        # N > W and N > H
+    assert np.all(np.isnan(gx)) and np.all(np.isnan(gy))
+
+
+def test_window_equal_to_L_and_nan_pixel(dem, torch):
+    img = wl.random_frame(96, 24, seed=5, dtype=np.float64)
+    gx, _ = run(dem, torch, img, 4, 4, "x")            # K = 1
+    ox, _ = oracle.demodulate(img, 4, 4, "x")
+    compare_omega(gx, ox, "K=1")
+    g = wl.complex_tone(120, 4, 0.6, 0.0).astype(np.complex64)
+    g[1, 50] = np.nan
+    gx, _ = run(dem, torch, g, 3, 10, "x")
+    ox, _ = oracle.demodulate(g, 3, 10, "x")
+    compare_omega(gx, ox, "nan pixel")
+    assert np.isnan(gx[1, 50]) and np.isfinite(gx[0, 50])
+
+
+def test_max_fft_length_line(dem, torch, bm):
+    d = bm.Demodulator(0, max_width=8192, max_height=16)
+    img = wl.random_frame(8192, 3, seed=9)
+    wx, _ = d.demodulate(to_dev(torch, img), 6, 24, "x")
+    torch.cuda.synchronize()
+    ox, _ = oracle.demodulate(img, 6, 24, "x")
+    compare_omega(wx.cpu().numpy(), ox, "8192 line")
+    d.close()
+
+
+def test_flags_mark_borders(dem, torch):
+    img = wl.random_frame(300, 40, seed=2)
+    wx, wy, fl = dem.demodulate(to_dev(torch, img), 4, 16, "xy", flags=True)
+    torch.cuda.synchronize()
+    fl = fl.cpu().numpy()
+    wx, wy = wx.cpu().numpy(), wy.cpu().numpy()
+    assert np.array_equal((fl & 1) != 0, np.isnan(wx))
+    assert np.array_equal((fl & 16) != 0, np.isnan(wy))
+
+
+def test_deterministic_reruns(dem, torch):
+    img = to_dev(torch, wl.random_frame(576, 64, seed=4))
+    a = dem.demodulate(img, 6, 32, "xy")
+    b = dem.demodulate(img, 6, 32, "xy")
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(torch.nan_to_num(u, 7.0), torch.nan_to_num(v, 7.0))
+
+
+def test_invalid_arguments_enqueue_nothing(dem, torch, bm):
+    img = to_dev(torch, wl.random_frame(64, 64, seed=1))
+    wx = torch.full((64, 64), 5.0, device="cuda")
+    bad = [
+        bm.FrameSpec(img, 1, 16, bm.BM_DIR_X, wx),       # L < 2
+        bm.FrameSpec(img, 9, 16, bm.BM_DIR_X, wx),       # L > 8
+        bm.FrameSpec(img, 6, 5, bm.BM_DIR_X, wx),        # N < L
+        bm.FrameSpec(img, 6, 65, bm.BM_DIR_X, wx),       # N > 64
+        bm.FrameSpec(img, 6, 16, 0, wx),                 # no direction
+        bm.FrameSpec(img, 6, 16, bm.BM_DIR_Y, wx, None),  # omega_y missing
+    ]
+    good = bm.FrameSpec(img, 6, 16, bm.BM_DIR_X, wx)
+    for b in bad:
+        with pytest.raises(bm.BosmusicError) as ei:
+            bm.bosmusic_demodulate(dem.h, [good, b])
+        assert ei.value.status == bm.BM_E_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(wx == 5.0)          # the valid first frame was not run either
+    odd = to_dev(torch, wl.random_frame(77, 64, seed=1))
+    with pytest.raises(bm.BosmusicError) as ei:
+        bm.bosmusic_demodulate(dem.h, [bm.FrameSpec(odd, 6, 16, bm.BM_DIR_X, torch.empty((64, 77), device="cuda"))])
+    assert ei.value.status == bm.BM_E_UNSUPPORTED
+    big = torch.zeros((10, 5000), device="cuda")
+    with pytest.raises(bm.BosmusicError) as ei:
+        bm.bosmusic_demodulate(dem.h, [bm.FrameSpec(big, 6, 16, bm.BM_DIR_X, torch.empty((10, 5000), device="cuda"))])
+    assert ei.value.status == bm.BM_E_INVALID_ARG
+    with pytest.raises(bm.BosmusicError) as ei:
+        bm.bosmusic_demodulate(dem.h, [good], mode=bm.BM_SURROGATE)
+    assert ei.value.status == bm.BM_E_UNSUPPORTED
+
+
+def test_stats_count_windows(dem, torch):
+    dem.stats(reset=True)
+    img = wl.random_frame(300, 20, seed=8)
+    dem.demodulate(to_dev(torch, img), 5, 20, "xy")
+    s = dem.stats(reset=True)
+    nx = 20 * (300 - 20 + 1)
+    ny = 300 * (20 - 20 + 1)
+    assert s["windows"] == nx + ny
+    assert s["jacobi_sweeps"] >= s["windows"] and s["root_iters"] >= s["windows"]
+    print(s)
+
+
+# ---------------------------------------------------------------------------
+# Integration
+# ---------------------------------------------------------------------------
+def test_integrate_matches_oracle_on_same_omega(dem, torch):
+    f = wl.cfg2_frame(10)
+    img = to_dev(torch, f.data[:512, :600])
+    wx, wy = dem.demodulate(img, 6, 32, "xy")
+    phi = dem.integrate(wx, wy, 32, 32, 0.3, 0.1)
+    torch.cuda.synchronize()
+    wxn, wyn = wx.cpu().numpy(), wy.cpu().numpy()
+    ref = oracle.integrate(wxn, wyn, 32, 32, 0.3, 0.1)
+    got = phi.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    m = np.isfinite(ref)
+    assert np.max(np.abs(got[m] - ref[m])) < 1e-9
+    # without omega_y
+    phi2 = dem.integrate(wx, None, 32, 0)
+    torch.cuda.synchronize()
+    ref2 = oracle.integrate(wxn, None, 32, 0)
+    got2 = phi2.cpu().numpy()
+    assert np.array_equal(np.isnan(got2), np.isnan(ref2))
+    m = np.isfinite(ref2)
+    assert np.max(np.abs(got2[m] - ref2[m])) < 1e-9
+
+
+def test_integrate_end_to_end_linear_phase(dem, torch):
+    W, H = 240, 96
+    wx0, wy0 = 2 * np.pi * 23 / W, 2 * np.pi * 9 / H
+    x = np.arange(W)[None, :]
+    y = np.arange(H)[:, None]
+    img = (0.5 + 0.4 * np.cos(wx0 * x + wy0 * y + 0.2)).astype(np.float64)
+    wx, wy = dem.demodulate(to_dev(torch, img), 5, 16, "xy")
+    phi = dem.integrate(wx, wy, 16, 16).cpu().numpy()
+    x0, _ = oracle.valid_range(W, 16)
+    y0, _ = oracle.valid_range(H, 16)
+    ref = np.broadcast_to(wx0 * (x - x0) + wy0 * (y - y0), (H, W))
+    m = np.isfinite(phi)
+    assert m.sum() == (W - 15) * (H - 15)
+    assert np.max(np.abs(phi[m] - ref[m])) < 2e-3
