@@ -32,23 +32,25 @@ PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed), F
 PEAK_HBM = 8.0e12
 
 
-def flops_per_window(L: int, N: int, sweeps: float, iters: float) -> dict:
-    """Algorithmic FP32 / FP64 flop count of one window of the HIP kernel.
+def flops_per_window(L: int, N: int, newton: float, iters: float) -> dict:
+    """Algorithmic flop count of one window of the root-MUSIC kernel.
 
-    FMA = 2 flops; add, mul, compare-free arithmetic, rcp/sqrt/rsq = 1 each.
-    sweeps and iters are the measured mean Jacobi sweeps and root iterations.
+    FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` and
+    `iters` are the measured mean Newton steps (largest eigenvalue) and
+    simultaneous root iterations per window.
     """
     K = N - L + 1
     n = 2 * L - 2
-    cov = K * (4 * L + 8 * L * (L - 1) // 2)
-    build_t = 3 * L * L + L + L * (L + 1) // 2
-    rot = 12 * L + 7
-    jac = sweeps * (L * (L - 1) // 2) * (rot + 2) + L * (L - 1)        # + final convergence test
-    coef = 8 * L * (L + 1) // 2
+    lag = K * L * 8                                   # lag sums, complex MAC = 4 FMA
+    build_t = 3 * L * L + L + L * (L + 1) // 2        # T from R, trace normalisation
+    house = sum(2 * l * l + 2 * l * (l + 1) + 9 * l for l in range(2, L))
+    newton_f = newton * 8 * L
+    inverse = 6 * L + 2 * 8 * L + sum(4 * l for l in range(2, L))
+    coef = 2 * L + 8 * L * (L + 1) // 2
     start = 4 * n + 40
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
-    fp32 = cov + build_t + jac + coef + start + aberth + select + 20
+    fp32 = lag + build_t + house + newton_f + inverse + coef + start + aberth + select + 20
     fp64 = 3 * ((n + 1) * 32 + 60)
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
@@ -102,7 +104,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample: lines per direction per frame")
+    ap.add_argument("--cpu-lines", type=int, default=64, help="oracle sample: lines per direction per frame")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (frames are independent; "
@@ -144,6 +148,15 @@ def main():
     dem = bm.Demodulator(0, max_width=W, max_height=H, timing=True)
     stream = torch.cuda.current_stream()
 
+    if args.copy_mib > 0:
+        nel = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     def step():
         bm.bosmusic_demodulate(dem.h, specs, bm.BM_PLAIN, stream)
         for i in range(nf):
@@ -171,16 +184,16 @@ def main():
         bm.bosmusic_demodulate(sdem.h, [bm.FrameSpec(d_frames[i], L, N, 3, ow[0], ow[1])], bm.BM_PLAIN, stream)
     ss = sdem.stats(reset=True)
     sdem.close()
-    mean_sweeps = ss["jacobi_sweeps"] / max(1, ss["windows"])
+    mean_newton = ss["eig_iters"] / max(1, ss["windows"])
     mean_iters = ss["root_iters"] / max(1, ss["windows"])
-    fl = flops_per_window(L, N, mean_sweeps, mean_iters)
+    fl = flops_per_window(L, N, mean_newton, mean_iters)
     win_per_launch = H * (W - N + 1)
     avg_launch_s = st["rm_time_ns"] / max(1, st["rm_launches"]) / 1e9
     achieved = fl["total"] * win_per_launch / avg_launch_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
             "kernel": f"rootmusic_kernel<L=6>, {win_per_launch} windows/launch, "
-                      f"{fl['total']:.0f} flop/window (mean {mean_sweeps:.2f} Jacobi sweeps, "
+                      f"{fl['total']:.0f} flop/window (mean {mean_newton:.2f} Newton steps, "
                       f"{mean_iters:.2f} root iterations), mean launch {avg_launch_s * 1e3:.3f} ms over "
                       f"{st['rm_launches']} launches"}
 

@@ -79,6 +79,7 @@ enum { BM_PLAIN = 0, BM_SURROGATE = 1 };
 enum {
     BM_OPT_STATS = 1u,  /* count Jacobi sweeps and root iterations per call */
     BM_OPT_TIMING = 2u, /* time every root-MUSIC kernel launch with HIP events on its stream */
+    BM_OPT_JACOBI = 4u, /* signal subspace by cyclic Jacobi instead of the tridiagonal solver */
 };
 
 /* per-pixel flag bits (optional output); bits 0-3 for x, 4-7 for y */
@@ -110,7 +111,7 @@ typedef struct {
 
 typedef struct {
     uint64_t windows;       /* windows demodulated since the last reset */
-    uint64_t jacobi_sweeps; /* sum over windows of Jacobi sweeps */
+    uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI) */
     uint64_t root_iters;    /* sum over windows of simultaneous root iterations */
     uint64_t polish_fail;   /* windows whose FP64 pair polish did not converge */
     uint64_t rm_launches;   /* root-MUSIC kernel launches timed (BM_OPT_TIMING) */

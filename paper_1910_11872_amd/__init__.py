@@ -23,6 +23,7 @@ BM_DIR_X, BM_DIR_Y = 1, 2
 BM_PLAIN, BM_SURROGATE = 0, 1
 BM_OPT_STATS = 1
 BM_OPT_TIMING = 2
+BM_OPT_JACOBI = 4
 BM_FLAG_UNDEFINED, BM_FLAG_NO_POLISH = 1, 2
 
 ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "bosmusic_integrate",
@@ -40,7 +41,7 @@ class bosmusic_frame(ctypes.Structure):
 
 
 class bosmusic_stats(ctypes.Structure):
-    _fields_ = [("windows", c_uint64), ("jacobi_sweeps", c_uint64), ("root_iters", c_uint64),
+    _fields_ = [("windows", c_uint64), ("eig_iters", c_uint64), ("root_iters", c_uint64),
                 ("polish_fail", c_uint64), ("rm_launches", c_uint64), ("rm_time_ns", c_uint64)]
 
 
@@ -177,10 +178,11 @@ def bosmusic_get_stats(h, reset: bool = False, stream=None) -> dict:
 # ----------------------------------------------------------------------------
 class Demodulator:
     def __init__(self, device: int = 0, max_width: int = 4096, max_height: int = 4096, stats: bool = False,
-                 timing: bool = False):
+                 timing: bool = False, jacobi: bool = False):
         self.device = device
         self.h = bosmusic_create(device, max_width, max_height,
-                                 (BM_OPT_STATS if stats else 0) | (BM_OPT_TIMING if timing else 0))
+                                 (BM_OPT_STATS if stats else 0) | (BM_OPT_TIMING if timing else 0) |
+                                 (BM_OPT_JACOBI if jacobi else 0))
 
     def close(self):
         if self.h is not None and self.h.value:

@@ -13,6 +13,7 @@ constexpr int kMaxL = 8;
 constexpr int kMaxN = 64;
 constexpr int kMaxFFT = 8192;
 constexpr int kMaxRadixPasses = 20;
+constexpr int kStatSlots = 64;   // counter slots of the statistics buffer (4 counters each)
 
 // Mixed-radix plan of one DFT length (radices 4, 2, 3, 5 in pass order).
 struct FftPlan {
@@ -45,7 +46,8 @@ struct RootMusicArgs {
     uint8_t* flags;        // optional per-pixel flags
     int flag_shift;        // 0 for x, 4 for y
     int flag_or;           // 1: OR into existing flags, 0: overwrite
-    unsigned long long* stats;  // 4 counters or nullptr
+    unsigned long long* stats;  // kStatSlots x 4 counters, or nullptr
+    int jacobi;            // 1: cyclic Jacobi eigen-split instead of the tridiagonal solver
     RootTemplate tmpl;
 };
 

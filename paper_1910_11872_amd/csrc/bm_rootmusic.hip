@@ -1,17 +1,23 @@
 // Per-window root-MUSIC local-frequency kernel for gfx950.
 //
 // One lane owns one window (one output pixel of one direction).  A block of
-// 256 lanes covers 256 consecutive window positions of one line; the
-// overlapping windows are staged once in LDS with coalesced loads.  Per lane,
-// entirely in registers:
+// 256 lanes covers kBlock-(L-1) consecutive window positions of one line; the
+// overlapping windows are staged once in LDS with coalesced loads.  Steps:
 //
-//   covariance  R_ij = sum_k g[k+i] conj(g[k+j])          (paper Eq. 4)
+//   lag sums    S_d(m) = sum_k g[m+k] conj(g[m+k+d]), d < L, one start m per
+//               lane, shared through LDS: the covariance of the window that
+//               starts at s is R_ij = S_{j-i}(s+i)             (paper Eq. 4)
 //   FB average + unitary real transform: T = Q^H R_fb Q is real symmetric
 //               (Q the sparse centro-symmetric unitary matrix), built in
 //               closed form from R without forming R_fb
-//   eigen-split cyclic Jacobi on T; the eigenvector of the largest
-//               eigenvalue v gives the signal subspace u1 = Q v
-//               (paper Eq. 6-11, one-dimensional signal subspace)
+//   eigen-split the eigenvector v of the largest eigenvalue of T gives the
+//               signal subspace u1 = Q v (paper Eq. 6-11, one-dimensional
+//               signal subspace).  Default solver: Householder reduction to
+//               tridiagonal form, Newton's method from above on the
+//               characteristic polynomial (monotone for real-rooted
+//               polynomials) for the largest eigenvalue, one shifted inverse
+//               iteration for its eigenvector, back-transformation.  The
+//               cyclic Jacobi solver is kept as a selectable alternative.
 //   polynomial  c_k = sum_i C[i,i+k] with C = I - u1 u1^H = Un Un^H
 //               (paper Eq. 12-14)
 //   roots       Aberth-Ehrlich simultaneous iteration in FP32 from the roots
@@ -33,19 +39,52 @@
 namespace bm {
 namespace {
 
+// Tunables (overridable at compile time for tuning sweeps).
+#ifndef BM_JACOBI_TOL2
+#define BM_JACOBI_TOL2 1e-12f   // squared off-diagonal mass of the trace-normalised matrix
+#endif
+#ifndef BM_ROOT_TOL2
+#define BM_ROOT_TOL2 1e-4f      // squared relative root step that ends the root iteration
+#endif
+#ifndef BM_MAX_ROOT_ITERS
+#define BM_MAX_ROOT_ITERS 16
+#endif
+#ifndef BM_POLISH_ITERS
+#define BM_POLISH_ITERS 3
+#endif
+#ifndef BM_NEWTON_ITERS
+#define BM_NEWTON_ITERS 12
+#endif
+#ifndef BM_INVERSE_ITERS
+#define BM_INVERSE_ITERS 2
+#endif
+
 constexpr int kBlock = 256;
 constexpr int kMaxJacobiSweeps = 10;
-constexpr float kJacobiTol2 = 1e-12f;   // squared off-diagonal mass, trace-normalised
-constexpr int kMaxRootIters = 16;
-constexpr float kRootTol2 = 1e-6f;     // squared relative root step
-constexpr int kPolishIters = 3;
+constexpr float kJacobiTol2 = BM_JACOBI_TOL2;
+constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
+constexpr float kRootTol2 = BM_ROOT_TOL2;
+constexpr int kPolishIters = BM_POLISH_ITERS;
+constexpr int kNewtonIters = BM_NEWTON_ITERS;
+constexpr int kInverseIters = BM_INVERSE_ITERS;
+
+// windows per block: the lag sums of kBlock starts cover kBlock-(L-1) windows
+template <int L>
+constexpr int windows_per_block() { return kBlock - (L - 1); }
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
 
-// Hermitian accessor of the upper-triangle covariance store.
+// Symmetric L x L matrix, upper triangle stored (compile-time indices only).
+template <int L>
+struct Sym {
+    float a[L][L];
+    __device__ __forceinline__ float& at(int i, int j) { return i <= j ? a[i][j] : a[j][i]; }
+};
+
+// Hermitian covariance, upper triangle stored.
 template <int L>
 struct Cov {
     float re[L][L];
@@ -54,85 +93,286 @@ struct Cov {
     __device__ __forceinline__ float gi(int i, int j) const { return i <= j ? im[i][j] : -im[j][i]; }
 };
 
+// T = Q^H R_fb Q, real symmetric.  With F = R + J conj(R) J = 2 R_fb, m = L/2,
+// o = L - m, and i, j < m:
+//   T[i][j]     = Re(F[i][j] + F[i][L-1-j])
+//   T[i][o+j]   = Im F[i][L-1-j] - Im F[i][j]
+//   T[o+i][o+j] = Re(F[i][j] - F[i][L-1-j])
+// and for odd L: T[i][m] = sqrt2 Re F[i][m], T[m][m] = Re F[m][m],
+// T[m][o+j] = -sqrt2 Im F[m][j].
 template <int L>
-struct Sym {
-    float a[L][L];
-    __device__ __forceinline__ float& at(int i, int j) { return i <= j ? a[i][j] : a[j][i]; }
-};
+__device__ __forceinline__ void build_T(const Cov<L>& R, Sym<L>& T) {
+    constexpr int m = L / 2;
+    constexpr int o = L - m;
+    constexpr float kSqrt2 = 1.41421356237309515f;
+    auto Fr = [&](int i, int j) { return R.gr(i, j) + R.gr(L - 1 - i, L - 1 - j); };
+    auto Fi = [&](int i, int j) { return R.gi(i, j) - R.gi(L - 1 - i, L - 1 - j); };
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            if (j >= i) {
+                T.a[i][j] = Fr(i, j) + Fr(i, L - 1 - j);
+                T.a[o + i][o + j] = Fr(i, j) - Fr(i, L - 1 - j);
+            }
+            T.a[i][o + j] = Fi(i, L - 1 - j) - Fi(i, j);
+        }
+        if (L & 1) T.a[i][m] = kSqrt2 * Fr(i, m);
+    }
+    if (L & 1) {
+        T.a[m][m] = Fr(m, m);
+#pragma unroll
+        for (int j = 0; j < m; ++j) T.a[m][o + j] = -kSqrt2 * Fi(m, j);
+    }
+}
 
-template <int L, bool STATS>
+// Eigenvector of the largest eigenvalue of the trace-normalised symmetric T:
+// Householder tridiagonalisation, Newton from above on det(xI - T_tri),
+// shifted inverse iteration on the tridiagonal matrix, back-transformation.
+template <int L>
+__device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int& its) {
+    float hv[L][L];   // reflector k lives in hv[k][k+1 .. L-1]
+    float hb[L];
+    float e[L];
+#pragma unroll
+    for (int k = 0; k < L - 2; ++k) {
+        float nrm2 = 0.f;
+#pragma unroll
+        for (int j = k + 1; j < L; ++j) {
+            hv[k][j] = T.at(j, k);
+            nrm2 = fmaf(hv[k][j], hv[k][j], nrm2);
+        }
+        const float nrm = fsqrt(nrm2);
+        const float alpha = hv[k][k + 1] >= 0.f ? -nrm : nrm;
+        hv[k][k + 1] -= alpha;
+        float vtv = 0.f;
+#pragma unroll
+        for (int j = k + 1; j < L; ++j) vtv = fmaf(hv[k][j], hv[k][j], vtv);
+        const float beta = vtv > 0.f ? 2.f * frcp(vtv) : 0.f;
+        hb[k] = beta;
+        e[k] = alpha;
+        float p[L];
+#pragma unroll
+        for (int i = k + 1; i < L; ++i) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = k + 1; j < L; ++j) acc = fmaf(T.at(i, j), hv[k][j], acc);
+            p[i] = beta * acc;
+        }
+        float pv = 0.f;
+#pragma unroll
+        for (int i = k + 1; i < L; ++i) pv = fmaf(p[i], hv[k][i], pv);
+        const float Kf = 0.5f * beta * pv;
+#pragma unroll
+        for (int i = k + 1; i < L; ++i) p[i] = fmaf(-Kf, hv[k][i], p[i]);   // w
+#pragma unroll
+        for (int i = k + 1; i < L; ++i)
+#pragma unroll
+            for (int j = i; j < L; ++j) T.a[i][j] -= fmaf(hv[k][i], p[j], p[i] * hv[k][j]);
+    }
+    float d[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) d[i] = T.a[i][i];
+    e[L - 2] = T.a[L - 2][L - 1];
+    float e2[L];
+#pragma unroll
+    for (int i = 0; i < L - 1; ++i) e2[i] = e[i] * e[i];
+    // start above the largest eigenvalue: T is positive semidefinite with trace 1
+    float g = 0.f;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        float r = d[i];
+        if (i > 0) r += fabsf(e[i - 1]);
+        if (i < L - 1) r += fabsf(e[i]);
+        g = fmaxf(g, r);
+    }
+    float x = fminf(g, 1.f) * 1.000001f + 1e-30f;
+    for (int it = 0; it < kNewtonIters; ++it) {
+        ++its;
+        float q0 = 1.f, q1 = x - d[0], dq0 = 0.f, dq1 = 1.f;
+#pragma unroll
+        for (int i = 1; i < L; ++i) {
+            const float xi = x - d[i];
+            const float q2 = fmaf(xi, q1, -e2[i - 1] * q0);
+            const float dq2 = fmaf(xi, dq1, fmaf(-e2[i - 1], dq0, q1));
+            q0 = q1; q1 = q2; dq0 = dq1; dq1 = dq2;
+        }
+        const float step = q1 * frcp(dq1);
+        if (!finitef(step)) break;
+        x -= step;
+        if (!(fabsf(step) > 1e-7f * x)) break;
+    }
+    // (sigma I - T_tri) y = y_prev, LDL^T without pivoting; sigma just above lambda_1
+    const float sigma = x * 1.000002f + 1e-30f;
+    float y[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) y[i] = 1.f;
+    float Dg[L], l[L];
+    Dg[0] = sigma - d[0];
+#pragma unroll
+    for (int i = 0; i < L - 1; ++i) {
+        const float Di = Dg[i] != 0.f ? Dg[i] : 1e-30f;
+        l[i] = -e[i] * frcp(Di);
+        Dg[i + 1] = fmaf(-l[i] * l[i], Di, sigma - d[i + 1]);
+    }
+    float Dinv[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) Dinv[i] = frcp(Dg[i] != 0.f ? Dg[i] : 1e-30f);
+#pragma unroll
+    for (int it = 0; it < kInverseIters; ++it) {
+#pragma unroll
+        for (int i = 1; i < L; ++i) y[i] = fmaf(-l[i - 1], y[i - 1], y[i]);
+#pragma unroll
+        for (int i = 0; i < L; ++i) y[i] *= Dinv[i];
+#pragma unroll
+        for (int i = L - 2; i >= 0; --i) y[i] = fmaf(-l[i], y[i + 1], y[i]);
+        float n2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < L; ++i) n2 = fmaf(y[i], y[i], n2);
+        const float in = frsq(n2);
+#pragma unroll
+        for (int i = 0; i < L; ++i) y[i] *= in;
+    }
+#pragma unroll
+    for (int k = L - 3; k >= 0; --k) {
+        float sp = 0.f;
+#pragma unroll
+        for (int j = k + 1; j < L; ++j) sp = fmaf(hv[k][j], y[j], sp);
+        sp *= hb[k];
+#pragma unroll
+        for (int j = k + 1; j < L; ++j) y[j] = fmaf(-sp, hv[k][j], y[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) v[i] = y[i];
+}
+
+// Same eigenvector by cyclic Jacobi rotations (selectable alternative).
+template <int L>
+__device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int& sweeps) {
+    float V[L][L];
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = 0; j < L; ++j) V[i][j] = (i == j) ? 1.f : 0.f;
+    for (int sw = 0; sw < kMaxJacobiSweeps; ++sw) {
+        float off = 0.f;
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int j = i + 1; j < L; ++j) off = fmaf(T.a[i][j], T.a[i][j], off);
+        if (!(off > kJacobiTol2)) break;
+        ++sweeps;
+#pragma unroll
+        for (int pp = 0; pp < L - 1; ++pp) {
+#pragma unroll
+            for (int qq = pp + 1; qq < L; ++qq) {
+                const float apq = T.a[pp][qq];
+                const float th = T.a[qq][qq] - T.a[pp][pp];
+                const float sgn = th >= 0.f ? 1.f : -1.f;
+                const float den = fabsf(th) + fsqrt(fmaf(th, th, 4.f * apq * apq));
+                const float tt = den > 0.f ? 2.f * apq * sgn * frcp(den) : 0.f;
+                const float c = frsq(fmaf(tt, tt, 1.f));
+                const float s = tt * c;
+                T.a[pp][pp] = fmaf(-tt, apq, T.a[pp][pp]);
+                T.a[qq][qq] = fmaf(tt, apq, T.a[qq][qq]);
+                T.a[pp][qq] = 0.f;
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    if (k == pp || k == qq) continue;
+                    const float akp = T.at(k, pp), akq = T.at(k, qq);
+                    T.at(k, pp) = c * akp - s * akq;
+                    T.at(k, qq) = s * akp + c * akq;
+                }
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    const float vkp = V[k][pp], vkq = V[k][qq];
+                    V[k][pp] = c * vkp - s * vkq;
+                    V[k][qq] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    float best = T.a[0][0];
+#pragma unroll
+    for (int i = 0; i < L; ++i) v[i] = V[i][0];
+#pragma unroll
+    for (int k = 1; k < L; ++k) {
+        const bool b = T.a[k][k] > best;
+        best = b ? T.a[k][k] : best;
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = b ? V[i][k] : v[i];
+    }
+}
+
+template <int L, bool STATS, bool JACOBI>
 __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
     constexpr int n = 2 * L - 2;            // polynomial degree
     constexpr int m = L / 2;
-    constexpr int o = L - m;                // first column of the imaginary block of Q
+    constexpr int o = L - m;
+    constexpr int WPB = windows_per_block<L>();
     __shared__ float2 sg[kBlock + kMaxN];
+    __shared__ float2 sS[L][kBlock];
 
     const int line = blockIdx.y;
-    const int p0 = blockIdx.x * kBlock;
+    const int p0 = blockIdx.x * WPB;
     const int t = threadIdx.x;
     const int N = A.N;
     const int half = N >> 1;
     const int K = N - L + 1;
     const float2* g = A.gamma + (int64_t)line * A.gamma_ls;
 
+    // window of pixel p0+t starts at base+t
     const int base = p0 - half;
     for (int i = t; i < kBlock + N - 1; i += kBlock) {
         const int q = base + i;
         sg[i] = (q >= 0 && q < A.len) ? g[q] : make_float2(0.f, 0.f);
     }
     __syncthreads();
+    // ---- lag sums S_d(base+t), d < L (every lane) -------------------------
+    {
+        float sr[L], si[L];
+#pragma unroll
+        for (int d = 0; d < L; ++d) { sr[d] = 0.f; si[d] = 0.f; }
+        float2 win[L];
+#pragma unroll
+        for (int d = 0; d < L - 1; ++d) win[d + 1] = sg[t + d];
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int d = 0; d < L - 1; ++d) win[d] = win[d + 1];
+            win[L - 1] = sg[t + k + L - 1];
+            // products g[k] conj(g[k+d]) with g[k] = win[0]
+#pragma unroll
+            for (int d = 0; d < L; ++d) {
+                sr[d] = fmaf(win[0].x, win[d].x, fmaf(win[0].y, win[d].y, sr[d]));
+                si[d] = fmaf(win[0].y, win[d].x, fmaf(-win[0].x, win[d].y, si[d]));
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < L; ++d) sS[d][t] = make_float2(sr[d], si[d]);
+    }
+    __syncthreads();
 
     const int p = p0 + t;
-    const bool inside_line = p < A.len;
+    const bool inside_line = (t < WPB) && (p < A.len);
     const bool valid = inside_line && (p - half >= 0) && (p - half + N <= A.len);
 
     float omega = __builtin_nanf("");
     unsigned flag = 0;
-    int sweeps = 0, iters = 0, pfail = 0, counted = 0;
+    int eig_its = 0, iters = 0, pfail = 0, counted = 0;
 
     if (valid) {
-        const float2* w = sg + t;
-        // ---- covariance of the sub-snapshots (Eq. 4), upper triangle -------
+        // ---- covariance R_ij = S_{j-i}(s+i) (Eq. 4, up to the 1/K scale) ---
         Cov<L> R;
 #pragma unroll
         for (int i = 0; i < L; ++i)
 #pragma unroll
-            for (int j = i; j < L; ++j) { R.re[i][j] = 0.f; R.im[i][j] = 0.f; }
-        for (int k = 0; k < K; ++k) {
-            float2 s[L];
-#pragma unroll
-            for (int i = 0; i < L; ++i) s[i] = w[k + i];
-#pragma unroll
-            for (int i = 0; i < L; ++i)
-#pragma unroll
-                for (int j = i; j < L; ++j) {
-                    R.re[i][j] = fmaf(s[i].x, s[j].x, fmaf(s[i].y, s[j].y, R.re[i][j]));
-                    if (i != j) R.im[i][j] = fmaf(s[i].y, s[j].x, fmaf(-s[i].x, s[j].y, R.im[i][j]));
-                }
-        }
-        // ---- T = Q^H R_fb Q (real symmetric), with F = 2 R_fb --------------
-        // F(i,j) = R(i,j) + conj(R(L-1-i, L-1-j))
-        auto Fr = [&](int i, int j) { return R.gr(i, j) + R.gr(L - 1 - i, L - 1 - j); };
-        auto Fi = [&](int i, int j) { return R.gi(i, j) - R.gi(L - 1 - i, L - 1 - j); };
-        Sym<L> T;
-        constexpr float kSqrt2 = 1.41421356237309515f;
-#pragma unroll
-        for (int i = 0; i < m; ++i) {
-#pragma unroll
-            for (int j = 0; j < m; ++j) {
-                if (j >= i) {
-                    T.a[i][j] = Fr(i, j) + Fr(i, L - 1 - j);
-                    T.a[o + i][o + j] = Fr(i, j) - Fr(i, L - 1 - j);
-                }
-                T.a[i][o + j] = Fi(i, L - 1 - j) - Fi(i, j);
+            for (int j = i; j < L; ++j) {
+                const float2 v = sS[j - i][t + i];
+                R.re[i][j] = v.x;
+                R.im[i][j] = (i == j) ? 0.f : v.y;
             }
-            if (L & 1) T.a[i][m] = kSqrt2 * Fr(i, m);
-        }
-        if (L & 1) {
-            T.a[m][m] = Fr(m, m);
-#pragma unroll
-            for (int j = 0; j < m; ++j) T.a[m][o + j] = -kSqrt2 * Fi(m, j);
-        }
+        Sym<L> T;
+        build_T<L>(R, T);
         float tr = 0.f;
 #pragma unroll
         for (int i = 0; i < L; ++i) tr += T.a[i][i];
@@ -145,62 +385,10 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
 #pragma unroll
                 for (int j = i; j < L; ++j) T.a[i][j] *= itr;
 
-            // ---- cyclic Jacobi on T (eigen-split, Eq. 6-11) ----------------
-            float V[L][L];
-#pragma unroll
-            for (int i = 0; i < L; ++i)
-#pragma unroll
-                for (int j = 0; j < L; ++j) V[i][j] = (i == j) ? 1.f : 0.f;
-            for (int sw = 0; sw < kMaxJacobiSweeps; ++sw) {
-                float off = 0.f;
-#pragma unroll
-                for (int i = 0; i < L; ++i)
-#pragma unroll
-                    for (int j = i + 1; j < L; ++j) off = fmaf(T.a[i][j], T.a[i][j], off);
-                if (!(off > kJacobiTol2)) break;
-                ++sweeps;
-#pragma unroll
-                for (int pp = 0; pp < L - 1; ++pp) {
-#pragma unroll
-                    for (int qq = pp + 1; qq < L; ++qq) {
-                        const float apq = T.a[pp][qq];
-                        const float th = T.a[qq][qq] - T.a[pp][pp];
-                        const float sgn = th >= 0.f ? 1.f : -1.f;
-                        const float den = fabsf(th) + fsqrt(fmaf(th, th, 4.f * apq * apq));
-                        const float tt = den > 0.f ? 2.f * apq * sgn * frcp(den) : 0.f;
-                        const float c = frsq(fmaf(tt, tt, 1.f));
-                        const float s = tt * c;
-                        T.a[pp][pp] = fmaf(-tt, apq, T.a[pp][pp]);
-                        T.a[qq][qq] = fmaf(tt, apq, T.a[qq][qq]);
-                        T.a[pp][qq] = 0.f;
-#pragma unroll
-                        for (int k = 0; k < L; ++k) {
-                            if (k == pp || k == qq) continue;
-                            const float akp = T.at(k, pp), akq = T.at(k, qq);
-                            T.at(k, pp) = c * akp - s * akq;
-                            T.at(k, qq) = s * akp + c * akq;
-                        }
-#pragma unroll
-                        for (int k = 0; k < L; ++k) {
-                            const float vkp = V[k][pp], vkq = V[k][qq];
-                            V[k][pp] = c * vkp - s * vkq;
-                            V[k][qq] = s * vkp + c * vkq;
-                        }
-                    }
-                }
-            }
-            // eigenvector of the largest eigenvalue
+            // ---- signal subspace (Eq. 6-11) ------------------------------
             float v[L];
-            float best = T.a[0][0];
-#pragma unroll
-            for (int i = 0; i < L; ++i) v[i] = V[i][0];
-#pragma unroll
-            for (int k = 1; k < L; ++k) {
-                const bool b = T.a[k][k] > best;
-                best = b ? T.a[k][k] : best;
-#pragma unroll
-                for (int i = 0; i < L; ++i) v[i] = b ? V[i][k] : v[i];
-            }
+            if (JACOBI) top_eigvec_jacobi<L>(T, v, eig_its);
+            else top_eigvec_tridiag<L>(T, v, eig_its);
             // u1 = Q v
             float ur[L], ui[L];
             constexpr float kS = 0.70710678118654752f;
@@ -411,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
         }
     }
     if (STATS) {
-        unsigned long long a0 = counted, a1 = sweeps, a2 = iters, a3 = pfail;
+        unsigned long long a0 = counted, a1 = eig_its, a2 = iters, a3 = pfail;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             a0 += __shfl_xor(a0, off);
@@ -420,22 +608,30 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
             a3 += __shfl_xor(a3, off);
         }
         if ((t & 63) == 0) {
-            atomicAdd(A.stats + 0, a0);
-            atomicAdd(A.stats + 1, a1);
-            atomicAdd(A.stats + 2, a2);
-            atomicAdd(A.stats + 3, a3);
+            // spread the counters over kStatSlots slots to avoid one hot address
+            unsigned long long* sl = A.stats + 4 * ((blockIdx.x + blockIdx.y * gridDim.x + (t >> 6)) % kStatSlots);
+            atomicAdd(sl + 0, a0);
+            atomicAdd(sl + 1, a1);
+            atomicAdd(sl + 2, a2);
+            atomicAdd(sl + 3, a3);
         }
     }
 }
 
+template <int L, bool JACOBI>
+hipError_t launch_LJ(const RootMusicArgs& a, hipStream_t s) {
+    constexpr int WPB = windows_per_block<L>();
+    dim3 grid((a.len + WPB - 1) / WPB, a.nlines);
+    if (a.stats)
+        hipLaunchKernelGGL((rootmusic_kernel<L, true, JACOBI>), grid, dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((rootmusic_kernel<L, false, JACOBI>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int L>
 hipError_t launch_L(const RootMusicArgs& a, hipStream_t s) {
-    dim3 grid((a.len + kBlock - 1) / kBlock, a.nlines);
-    if (a.stats)
-        hipLaunchKernelGGL((rootmusic_kernel<L, true>), grid, dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((rootmusic_kernel<L, false>), grid, dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return a.jacobi ? launch_LJ<L, true>(a, s) : launch_LJ<L, false>(a, s);
 }
 
 }  // namespace

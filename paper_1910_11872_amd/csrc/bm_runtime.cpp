@@ -211,6 +211,7 @@ bm_status run_frame(bosmusic_s* h, const bosmusic_frame& f, hipStream_t s) {
     a.N = f.N;
     a.flags = f.flags;
     a.stats = (h->options & BM_OPT_STATS) ? h->stats : nullptr;
+    a.jacobi = (h->options & BM_OPT_JACOBI) ? 1 : 0;
     a.tmpl = h->tmpl[f.L];
     bm_status st;
     if (f.dirs & BM_DIR_X) {
@@ -311,7 +312,7 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         if (!cfg) return fail(nullptr, BM_E_INVALID_ARG, "cfg is NULL");
         if (cfg->max_width < 1 || cfg->max_height < 1 || cfg->max_width > 65536 || cfg->max_height > 65536)
             return fail(nullptr, BM_E_INVALID_ARG, "max size %dx%d", cfg->max_width, cfg->max_height);
-        if (cfg->options & ~(uint32_t)(BM_OPT_STATS | BM_OPT_TIMING)) return fail(nullptr, BM_E_INVALID_ARG, "options %u", cfg->options);
+        if (cfg->options & ~(uint32_t)(BM_OPT_STATS | BM_OPT_TIMING | BM_OPT_JACOBI)) return fail(nullptr, BM_E_INVALID_ARG, "options %u", cfg->options);
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
             return fail(nullptr, BM_E_DEVICE, "no HIP device available");
@@ -329,12 +330,12 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         if (hipMalloc(&h->gx, px * sizeof(float2)) != hipSuccess || hipMalloc(&h->gy, px * sizeof(float2)) != hipSuccess ||
             hipMalloc(&h->treal, px * sizeof(float)) != hipSuccess ||
             hipMalloc(&h->anchor, (size_t)cfg->max_height * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->stats, 4 * sizeof(unsigned long long)) != hipSuccess) {
+            hipMalloc(&h->stats, 4 * bm::kStatSlots * sizeof(unsigned long long)) != hipSuccess) {
             release(h);
             (void)hipGetLastError();
             return fail(nullptr, BM_E_NOMEM, "workspace for %dx%d", cfg->max_width, cfg->max_height);
         }
-        if (hipMemset(h->stats, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        if (hipMemset(h->stats, 0, 4 * bm::kStatSlots * sizeof(unsigned long long)) != hipSuccess ||
             bm::analytic_set_attributes() != hipSuccess || bm::integrate_set_attributes() != hipSuccess) {
             release(h);
             return fail(nullptr, BM_E_DEVICE, "device set-up failed");
@@ -412,11 +413,14 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
     try {
         DeviceGuard dg(h->device);
         hipStream_t s = (hipStream_t)stream;
+        unsigned long long slots[4 * bm::kStatSlots];
         unsigned long long v[4] = {0, 0, 0, 0};
         bm_status st;
         if ((st = check(h, hipStreamSynchronize(s), "sync"))) return st;
-        if ((st = check(h, hipMemcpy(v, h->stats, sizeof(v), hipMemcpyDeviceToHost), "stats copy"))) return st;
-        if (reset && (st = check(h, hipMemset(h->stats, 0, sizeof(v)), "stats reset"))) return st;
+        if ((st = check(h, hipMemcpy(slots, h->stats, sizeof(slots), hipMemcpyDeviceToHost), "stats copy")))
+            return st;
+        for (int i = 0; i < 4 * bm::kStatSlots; ++i) v[i % 4] += slots[i];
+        if (reset && (st = check(h, hipMemset(h->stats, 0, sizeof(slots)), "stats reset"))) return st;
         for (auto& e : h->ev_pending) {
             float ms = 0.f;
             if ((st = check(h, hipEventElapsedTime(&ms, e.first, e.second), "event time"))) return st;
@@ -426,7 +430,7 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
         }
         h->ev_pending.clear();
         out->windows = v[0];
-        out->jacobi_sweeps = v[1];
+        out->eig_iters = v[1];
         out->root_iters = v[2];
         out->polish_fail = v[3];
         out->rm_launches = h->rm_launches;
