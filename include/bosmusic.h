@@ -80,6 +80,8 @@ enum {
     BM_OPT_STATS = 1u,  /* count Jacobi sweeps and root iterations per call */
     BM_OPT_TIMING = 2u, /* time every root-MUSIC kernel launch with HIP events on its stream */
     BM_OPT_JACOBI = 4u, /* signal subspace by cyclic Jacobi instead of the tridiagonal solver */
+    BM_OPT_GRAPH = 8u,  /* capture each distinct batch once into a hipGraph and replay it;
+                           ignored when BM_OPT_TIMING is set */
 };
 
 /* per-pixel flag bits (optional output); bits 0-3 for x, 4-7 for y */
@@ -89,10 +91,14 @@ enum {
 };
 
 typedef struct {
-    int32_t device;     /* HIP device ordinal */
-    int32_t max_width;  /* workspace sizing: frames larger than this are rejected */
+    int32_t device;           /* HIP device ordinal */
+    int32_t max_width;        /* frames wider or taller than this are rejected */
     int32_t max_height;
-    uint32_t options;   /* BM_OPT_* */
+    uint32_t options;         /* BM_OPT_* */
+    int64_t max_batch_pixels; /* workspace: pixels of frames processed together in one
+                                 launch group (20 B each); 0 = max_width * max_height.
+                                 Larger batches are split into groups that fit. */
+    const char* tune_cache;   /* autotuner cache file (JSON lines) or NULL: no cache */
 } bosmusic_config;
 
 typedef struct {
@@ -127,6 +133,13 @@ bm_status bosmusic_destroy(bosmusic_t h);
 
 /* Demodulate n_frames frames (paper Sec. 3, Eq. 2-15, per pixel and per
  * requested direction) into their omega maps, enqueued on `stream`.
+ * Frames may differ in size, dtype, L and N.  Frames are grouped so that each
+ * group fits the workspace; per group the work runs as one batched transpose
+ * launch, one batched analytic-signal launch and one root-MUSIC launch per
+ * distinct L (with BM_OPT_GRAPH: one replay of a cached hipGraph holding them,
+ * the per-L launches on forked streams).  The job tables of a group are
+ * uploaded from pinned host memory on `stream`; the call may wait for the
+ * previous call's upload to finish before reusing that buffer.
  * mode: BM_PLAIN (BM_SURROGATE returns BM_E_UNSUPPORTED in this build).
  * Requirements per frame: 2 <= L <= 8, L <= N <= 64, width/height within
  * the handle's maximum, row_stride >= width; for real dtypes the length of
@@ -152,6 +165,17 @@ bm_status bosmusic_integrate(bosmusic_t h, const float* omega_x, const float* om
  * synchronising `stream`; reset = 1 zeroes them afterwards.  Counters of an
  * option that is not set read zero. */
 bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, void* stream);
+
+/* Autotune the root-MUSIC launch for covariance size L and window N on the
+ * handle's device: times every candidate tile shape (128 or 256 lanes per
+ * block) and grid size (one block per work item, or 1..16 resident blocks
+ * per compute unit walking the work list) with HIP events on a synthetic
+ * line set of `lines` lines x `width` samples, keeps the fastest for later
+ * bosmusic_demodulate calls with this (L, N), and appends it to the handle's
+ * tune cache file if one was given.  Results do not depend on the choice.
+ * Synchronises `stream`.  *best_us (optional) receives the best time. */
+bm_status bosmusic_autotune(bosmusic_t h, int32_t L, int32_t N, int32_t width, int32_t lines,
+                            double* best_us, void* stream);
 
 /* Static text for a status code. */
 const char* bosmusic_status_string(bm_status s);

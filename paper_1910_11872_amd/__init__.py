@@ -24,14 +24,17 @@ BM_PLAIN, BM_SURROGATE = 0, 1
 BM_OPT_STATS = 1
 BM_OPT_TIMING = 2
 BM_OPT_JACOBI = 4
+BM_OPT_GRAPH = 8
 BM_FLAG_UNDEFINED, BM_FLAG_NO_POLISH = 1, 2
 
 ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "bosmusic_integrate",
-                 "bosmusic_get_stats", "bosmusic_status_string", "bosmusic_last_error", "bosmusic_version")
+                 "bosmusic_autotune", "bosmusic_get_stats", "bosmusic_status_string", "bosmusic_last_error",
+                 "bosmusic_version")
 
 
 class bosmusic_config(ctypes.Structure):
-    _fields_ = [("device", c_int32), ("max_width", c_int32), ("max_height", c_int32), ("options", c_uint32)]
+    _fields_ = [("device", c_int32), ("max_width", c_int32), ("max_height", c_int32), ("options", c_uint32),
+                ("max_batch_pixels", c_int64), ("tune_cache", c_char_p)]
 
 
 class bosmusic_frame(ctypes.Structure):
@@ -70,6 +73,8 @@ def lib():
         L.bosmusic_integrate.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                          c_double, c_double, c_void_p, c_void_p]
         L.bosmusic_integrate.restype = c_int32
+        L.bosmusic_autotune.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, POINTER(c_double), c_void_p]
+        L.bosmusic_autotune.restype = c_int32
         L.bosmusic_get_stats.argtypes = [c_void_p, POINTER(bosmusic_stats), c_int32, c_void_p]
         L.bosmusic_get_stats.restype = c_int32
         L.bosmusic_status_string.argtypes = [c_int32]
@@ -118,8 +123,10 @@ def bosmusic_last_error(h=None) -> str:
     return lib().bosmusic_last_error(h).decode()
 
 
-def bosmusic_create(device: int = 0, max_width: int = 4096, max_height: int = 4096, options: int = 0):
-    cfg = bosmusic_config(device, max_width, max_height, options)
+def bosmusic_create(device: int = 0, max_width: int = 4096, max_height: int = 4096, options: int = 0,
+                    max_batch_pixels: int = 0, tune_cache: str | None = None):
+    cfg = bosmusic_config(device, max_width, max_height, options, max_batch_pixels,
+                          tune_cache.encode() if tune_cache else None)
     h = c_void_p()
     _check(lib().bosmusic_create(byref(cfg), byref(h)), None)
     return h
@@ -167,6 +174,13 @@ def bosmusic_integrate(h, omega_x, omega_y, Nx: int, Ny: int, carrier_x: float, 
                                     c_void_p(phi.data_ptr()), _stream_ptr(stream)), h)
 
 
+def bosmusic_autotune(h, L: int, N: int, width: int = 1024, lines: int = 512, stream=None) -> float:
+    """Tune the root-MUSIC launch for (L, N); returns the best time in microseconds."""
+    us = c_double(0.0)
+    _check(lib().bosmusic_autotune(h, L, N, width, lines, byref(us), _stream_ptr(stream)), h)
+    return us.value
+
+
 def bosmusic_get_stats(h, reset: bool = False, stream=None) -> dict:
     s = bosmusic_stats()
     _check(lib().bosmusic_get_stats(h, byref(s), int(reset), _stream_ptr(stream)), h)
@@ -178,11 +192,13 @@ def bosmusic_get_stats(h, reset: bool = False, stream=None) -> dict:
 # ----------------------------------------------------------------------------
 class Demodulator:
     def __init__(self, device: int = 0, max_width: int = 4096, max_height: int = 4096, stats: bool = False,
-                 timing: bool = False, jacobi: bool = False):
+                 timing: bool = False, jacobi: bool = False, graph: bool = False, max_batch_pixels: int = 0,
+                 tune_cache: str | None = None):
         self.device = device
         self.h = bosmusic_create(device, max_width, max_height,
                                  (BM_OPT_STATS if stats else 0) | (BM_OPT_TIMING if timing else 0) |
-                                 (BM_OPT_JACOBI if jacobi else 0))
+                                 (BM_OPT_JACOBI if jacobi else 0) | (BM_OPT_GRAPH if graph else 0),
+                                 max_batch_pixels, tune_cache)
 
     def close(self):
         if self.h is not None and self.h.value:
@@ -219,3 +235,6 @@ class Demodulator:
 
     def stats(self, reset: bool = False, stream=None) -> dict:
         return bosmusic_get_stats(self.h, reset, stream)
+
+    def autotune(self, L: int, N: int, width: int = 1024, lines: int = 512, stream=None) -> float:
+        return bosmusic_autotune(self.h, L, N, width, lines, stream)

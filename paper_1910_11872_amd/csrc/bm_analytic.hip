@@ -16,9 +16,6 @@ namespace {
 constexpr int kFftThreads = 256;
 constexpr int kTile = 32;
 
-__device__ __forceinline__ float to_f32(_Float16 v) { return (float)v; }
-__device__ __forceinline__ float to_f32(float v) { return v; }
-__device__ __forceinline__ float to_f32(double v) { return (float)v; }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -101,18 +98,38 @@ __device__ float2* fft_forward(float2* a, float2* b, int n, const FftPlan& plan,
     return a;
 }
 
-template <typename Tin>
-__global__ __launch_bounds__(kFftThreads) void analytic_kernel(const Tin* __restrict__ src, int64_t src_ls,
-                                                               FftPlan plan, const float2* __restrict__ tw,
-                                                               float2* __restrict__ dst) {
+// Index of the job that owns work item w: prefix[j] <= w < prefix[j+1].
+__device__ __forceinline__ int find_job(const int* prefix, int njobs, int w) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float load_real(const void* base, int64_t idx, int elem) {
+    if (elem == (int)Elem::F16) return (float)static_cast<const _Float16*>(base)[idx];
+    if (elem == (int)Elem::F64) return (float)static_cast<const double*>(base)[idx];
+    return static_cast<const float*>(base)[idx];
+}
+
+// One block per line of any job.
+__global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B) {
     extern __shared__ float2 lds[];
-    const int n = plan.n;
+    const int j = find_job(B.prefix, B.njobs, blockIdx.x);
+    const FftJob& J = B.jobs[j];
+    const int line = blockIdx.x - B.prefix[j];
+    const int n = J.plan.n;
+    const int elem = J.elem;
     float2* a = lds;
     float2* b = lds + n;
-    const Tin* x = src + (int64_t)blockIdx.x * src_ls;
-    for (int i = threadIdx.x; i < n; i += kFftThreads) a[i] = make_float2(to_f32(x[i]), 0.f);
+    const int64_t off = (int64_t)line * J.src_ls;
+    for (int i = threadIdx.x; i < n; i += kFftThreads) a[i] = make_float2(load_real(J.src, off + i, elem), 0.f);
     __syncthreads();
-    float2* X = fft_forward(a, b, n, plan, tw);
+    const FftPlan& plan = J.plan;
+    float2* X = fft_forward(a, b, n, plan, J.tw);
     float2* other = (X == a) ? b : a;
     // one-sided mask and 1/n, then conjugate so that a forward DFT inverts
     const float sc = 2.0f / (float)n;
@@ -122,96 +139,92 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(const Tin* __rest
         X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    float2* Y = fft_forward(X, other, n, plan, tw);
-    float2* out = dst + (int64_t)blockIdx.x * n;
+    float2* Y = fft_forward(X, other, n, plan, J.tw);
+    float2* out = J.dst + (int64_t)line * n;
     for (int i = threadIdx.x; i < n; i += kFftThreads) {
         const float2 v = Y[i];
         out[i] = make_float2(v.x, -v.y);
     }
 }
 
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kTile * 8) void transpose_kernel(const Tin* __restrict__ src, int64_t src_ls, int rows,
-                                                              int cols, Tout* __restrict__ dst) {
-    __shared__ Tout tile[kTile][kTile + 1];
-    const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+// One block per 32 x 32 tile of any job; real input -> float, C32 -> float2.
+__global__ __launch_bounds__(kTile * 8) void transpose_kernel(TrBatch B) {
+    __shared__ float2 tile[kTile][kTile + 1];
+    const int j = find_job(B.prefix, B.njobs, blockIdx.x);
+    const TrJob& J = B.jobs[j];
+    const int tid = blockIdx.x - B.prefix[j];
+    const int bx = (tid % J.tiles_x) * kTile, by = (tid / J.tiles_x) * kTile;
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    const int rows = J.rows, cols = J.cols, elem = J.elem;
+    const bool cplx = elem == (int)Elem::C32;
 #pragma unroll
-    for (int j = 0; j < kTile; j += 8) {
-        const int r = by + ty + j, c = bx + tx;
+    for (int jj = 0; jj < kTile; jj += 8) {
+        const int r = by + ty + jj, c = bx + tx;
         if (r < rows && c < cols) {
-            if constexpr (__is_same(Tout, float2))
-                tile[ty + j][tx] = src[(int64_t)r * src_ls + c];
-            else
-                tile[ty + j][tx] = to_f32(src[(int64_t)r * src_ls + c]);
+            const int64_t idx = (int64_t)r * J.src_ls + c;
+            tile[ty + jj][tx] = cplx ? static_cast<const float2*>(J.src)[idx]
+                                     : make_float2(load_real(J.src, idx, elem), 0.f);
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kTile; j += 8) {
-        const int c = bx + ty + j, r = by + tx;
-        if (r < rows && c < cols) dst[(int64_t)c * rows + r] = tile[tx][ty + j];
+    for (int jj = 0; jj < kTile; jj += 8) {
+        const int c = bx + ty + jj, r = by + tx;
+        if (r < rows && c < cols) {
+            const int64_t idx = (int64_t)c * rows + r;
+            if (cplx) static_cast<float2*>(J.dst)[idx] = tile[tx][ty + jj];
+            else static_cast<float*>(J.dst)[idx] = tile[tx][ty + jj].x;
+        }
     }
-}
-
-template <typename Tin>
-hipError_t launch_analytic_t(const void* src, int64_t ls, int nlines, const FftPlan& plan, const float2* tw,
-                             float2* dst, hipStream_t s) {
-    const size_t shmem = 2u * (size_t)plan.n * sizeof(float2);
-    hipLaunchKernelGGL(analytic_kernel<Tin>, dim3(nlines), dim3(kFftThreads), shmem, s,
-                       (const Tin*)src, ls, plan, tw, dst);
-    return hipGetLastError();
-}
-
-template <typename Tin>
-hipError_t set_attr() {
-    return hipFuncSetAttribute((const void*)analytic_kernel<Tin>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               2 * kMaxFFT * (int)sizeof(float2));
 }
 
 }  // namespace
 
 hipError_t analytic_set_attributes() {
-    hipError_t e = set_attr<_Float16>();
-    if (e == hipSuccess) e = set_attr<float>();
-    if (e == hipSuccess) e = set_attr<double>();
-    return e;
+    return hipFuncSetAttribute((const void*)analytic_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               2 * kMaxFFT * (int)sizeof(float2));
 }
 
-hipError_t launch_analytic(Elem e, const void* src, int64_t src_ls, int nlines, const FftPlan& plan,
-                           const float2* twiddle, float2* dst, hipStream_t s) {
-    if (nlines <= 0) return hipSuccess;
-    switch (e) {
-        case Elem::F16: return launch_analytic_t<_Float16>(src, src_ls, nlines, plan, twiddle, dst, s);
-        case Elem::F32: return launch_analytic_t<float>(src, src_ls, nlines, plan, twiddle, dst, s);
-        case Elem::F64: return launch_analytic_t<double>(src, src_ls, nlines, plan, twiddle, dst, s);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
+    if (b.total <= 0) return hipSuccess;
+    const size_t shmem = 2u * (size_t)b.max_n * sizeof(float2);
+    hipLaunchKernelGGL(analytic_kernel, dim3(b.total), dim3(kFftThreads), shmem, s, b);
+    return hipGetLastError();
 }
 
-hipError_t launch_transpose(Elem e, const void* src, int64_t src_ls, int rows, int cols, void* dst,
-                            hipStream_t s) {
-    if (rows <= 0 || cols <= 0) return hipSuccess;
-    dim3 grid((cols + kTile - 1) / kTile, (rows + kTile - 1) / kTile);
-    dim3 block(kTile * 8);
-    switch (e) {
-        case Elem::F16:
-            hipLaunchKernelGGL((transpose_kernel<_Float16, float>), grid, block, 0, s, (const _Float16*)src, src_ls,
-                               rows, cols, (float*)dst);
-            break;
-        case Elem::F32:
-            hipLaunchKernelGGL((transpose_kernel<float, float>), grid, block, 0, s, (const float*)src, src_ls, rows,
-                               cols, (float*)dst);
-            break;
-        case Elem::F64:
-            hipLaunchKernelGGL((transpose_kernel<double, float>), grid, block, 0, s, (const double*)src, src_ls,
-                               rows, cols, (float*)dst);
-            break;
-        case Elem::C32:
-            hipLaunchKernelGGL((transpose_kernel<float2, float2>), grid, block, 0, s, (const float2*)src, src_ls,
-                               rows, cols, (float2*)dst);
-            break;
-    }
+hipError_t launch_transpose(const TrBatch& b, hipStream_t s) {
+    if (b.total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(transpose_kernel, dim3(b.total), dim3(kTile * 8), 0, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace bm
+
+namespace bm {
+namespace {
+
+// Deterministic test signal for the autotuner: a complex tone of frequency
+// w0 plus hashed uniform noise of amplitude `noise`.
+__global__ void synth_kernel(float2* g, int64_t n, float w0, float noise) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const float u1 = (float)(h & 0xffff) * (1.f / 65536.f) - 0.5f;
+    const float u2 = (float)(h >> 16) * (1.f / 65536.f) - 0.5f;
+    float s, c;
+    sincosf(w0 * (float)(i % 4096), &s, &c);
+    g[i] = make_float2(c + noise * u1, s + noise * u2);
+}
+
+}  // namespace
+
+hipError_t launch_synth(float2* g, int64_t n, float w0, float noise, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(synth_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, n, w0, noise);
     return hipGetLastError();
 }
 

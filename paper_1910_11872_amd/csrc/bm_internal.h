@@ -34,31 +34,79 @@ struct RootTemplate {
     float im[2 * kMaxL - 2];
 };
 
-struct RootMusicArgs {
+// One direction of one frame for the root-MUSIC kernel: `nlines` lines of
+// `len` complex samples, `bpl` window blocks per line.
+struct RmJob {
     const float2* gamma;   // line-major complex signal
     int64_t gamma_ls;      // complex elements between line starts
-    int len;               // samples per line (window positions)
-    int nlines;
-    int N;                 // window length
     float* out;            // omega
     int64_t out_es;        // output stride along the line (elements)
     int64_t out_ls;        // output stride between lines (elements)
     uint8_t* flags;        // optional per-pixel flags
+    int len;
+    int nlines;
+    int N;                 // window length
+    int bpl;               // window blocks per line
     int flag_shift;        // 0 for x, 4 for y
     int flag_or;           // 1: OR into existing flags, 0: overwrite
-    unsigned long long* stats;  // kStatSlots x 4 counters, or nullptr
+};
+
+// All root-MUSIC work of one L: jobs[j] owns work items prefix[j] .. prefix[j+1)-1.
+struct RmBatch {
+    const RmJob* jobs;
+    const int* prefix;     // njobs + 1 entries
+    int njobs;
+    int total;             // prefix[njobs]
     int jacobi;            // 1: cyclic Jacobi eigen-split instead of the tridiagonal solver
+    unsigned long long* stats;  // kStatSlots x 4 counters, or nullptr
     RootTemplate tmpl;
 };
 
-// Launchers (enqueue only; return the launch error).
-hipError_t launch_rootmusic(int L, const RootMusicArgs& a, hipStream_t s);
+// Lines of one frame direction for the analytic-signal kernel (one block per line).
+struct FftJob {
+    const void* src;       // real lines, src_ls elements apart
+    int64_t src_ls;
+    float2* dst;           // complex lines, plan.n apart
+    const float2* tw;      // twiddles e^{-2 pi i m / n}, m < n
+    int elem;              // Elem of src
+    int nlines;
+    FftPlan plan;
+};
 
-hipError_t launch_transpose(Elem e, const void* src, int64_t src_ls, int rows, int cols,
-                            void* dst, hipStream_t s);
+struct FftBatch {
+    const FftJob* jobs;
+    const int* prefix;     // lines: njobs + 1 entries
+    int njobs;
+    int total;
+    int max_n;
+};
 
-hipError_t launch_analytic(Elem e, const void* src, int64_t src_ls, int nlines, const FftPlan& plan,
-                           const float2* twiddle, float2* dst, hipStream_t s);
+// Transpose of one frame (rows x cols, src_ls elements per row) to cols x rows.
+struct TrJob {
+    const void* src;
+    int64_t src_ls;
+    void* dst;             // float (real input) or float2 (C32)
+    int rows, cols;
+    int tiles_x;           // 32-wide tiles along cols
+    int elem;
+};
+
+struct TrBatch {
+    const TrJob* jobs;
+    const int* prefix;     // tiles: njobs + 1 entries
+    int njobs;
+    int total;
+};
+
+// Launchers (enqueue only; return the launch error).  `block` is 128 or 256
+// threads; `grid` is the number of blocks of the grid-stride loop (<= 0: one
+// block per work item).
+hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStream_t s);
+int rootmusic_windows_per_block(int L, int block);
+hipError_t launch_transpose(const TrBatch& b, hipStream_t s);
+hipError_t launch_analytic(const FftBatch& b, hipStream_t s);
+
+hipError_t launch_synth(float2* g, int64_t n, float w0, float noise, hipStream_t s);
 
 hipError_t launch_integrate(const float* wx, const float* wy, int W, int H, int Nx, int Ny,
                             double cx, double cy, double* anchor_ws, double* phi, hipStream_t s);

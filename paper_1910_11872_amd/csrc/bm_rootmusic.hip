@@ -1,7 +1,7 @@
 // Per-window root-MUSIC local-frequency kernel for gfx950.
 //
 // One lane owns one window (one output pixel of one direction).  A block of
-// 256 lanes covers kBlock-(L-1) consecutive window positions of one line; the
+// BLOCK lanes (128 or 256) covers BLOCK-(L-1) consecutive window positions of one line; the
 // overlapping windows are staged once in LDS with coalesced loads.  Steps:
 //
 //   lag sums    S_d(m) = sum_k g[m+k] conj(g[m+k+d]), d < L, one start m per
@@ -59,7 +59,6 @@ namespace {
 #define BM_INVERSE_ITERS 2
 #endif
 
-constexpr int kBlock = 256;
 constexpr int kMaxJacobiSweeps = 10;
 constexpr float kJacobiTol2 = BM_JACOBI_TOL2;
 constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
@@ -67,10 +66,6 @@ constexpr float kRootTol2 = BM_ROOT_TOL2;
 constexpr int kPolishIters = BM_POLISH_ITERS;
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
 constexpr int kInverseIters = BM_INVERSE_ITERS;
-
-// windows per block: the lag sums of kBlock starts cover kBlock-(L-1) windows
-template <int L>
-constexpr int windows_per_block() { return kBlock - (L - 1); }
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -304,28 +299,31 @@ __device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int&
     }
 }
 
-template <int L, bool STATS, bool JACOBI>
-__global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
+// Counters a lane accumulates over the windows it owns.
+struct LaneStats {
+    int counted = 0, eig_its = 0, iters = 0, pfail = 0;
+};
+
+// One block of windows: BLOCK-(L-1) consecutive pixels p0.. of one line of job J.
+template <int L, int BLOCK, bool JACOBI>
+__device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg, float2 (*sS)[BLOCK],
+                                                const RootTemplate& tmpl, LaneStats& ls) {
     constexpr int n = 2 * L - 2;            // polynomial degree
     constexpr int m = L / 2;
     constexpr int o = L - m;
-    constexpr int WPB = windows_per_block<L>();
-    __shared__ float2 sg[kBlock + kMaxN];
-    __shared__ float2 sS[L][kBlock];
-
-    const int line = blockIdx.y;
-    const int p0 = blockIdx.x * WPB;
+    constexpr int WPB = BLOCK - (L - 1);
     const int t = threadIdx.x;
-    const int N = A.N;
+    const int N = J.N;
     const int half = N >> 1;
     const int K = N - L + 1;
-    const float2* g = A.gamma + (int64_t)line * A.gamma_ls;
+    const float2* g = J.gamma + (int64_t)line * J.gamma_ls;
+    const int len = J.len;
 
     // window of pixel p0+t starts at base+t
     const int base = p0 - half;
-    for (int i = t; i < kBlock + N - 1; i += kBlock) {
+    for (int i = t; i < BLOCK + N - 1; i += BLOCK) {
         const int q = base + i;
-        sg[i] = (q >= 0 && q < A.len) ? g[q] : make_float2(0.f, 0.f);
+        sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     // ---- lag sums S_d(base+t), d < L (every lane) -------------------------
@@ -353,8 +351,8 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
     __syncthreads();
 
     const int p = p0 + t;
-    const bool inside_line = (t < WPB) && (p < A.len);
-    const bool valid = inside_line && (p - half >= 0) && (p - half + N <= A.len);
+    const bool inside_line = (t < WPB) && (p < len);
+    const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
 
     float omega = __builtin_nanf("");
     unsigned flag = 0;
@@ -434,8 +432,8 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
             float zr[n], zi[n];
 #pragma unroll
             for (int i = 0; i < n; ++i) {
-                zr[i] = A.tmpl.re[i] * cw0 - A.tmpl.im[i] * sw0;
-                zi[i] = A.tmpl.re[i] * sw0 + A.tmpl.im[i] * cw0;
+                zr[i] = tmpl.re[i] * cw0 - tmpl.im[i] * sw0;
+                zi[i] = tmpl.re[i] * sw0 + tmpl.im[i] * cw0;
             }
             for (int it = 0; it < kMaxRootIters; ++it) {
                 ++iters;
@@ -590,16 +588,46 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
     }
 
     if (inside_line) {
-        const int64_t oidx = (int64_t)p * A.out_es + (int64_t)line * A.out_ls;
-        A.out[oidx] = omega;
-        if (A.flags) {
-            const uint8_t f = (uint8_t)(flag << A.flag_shift);
-            if (A.flag_or) A.flags[oidx] |= f;
-            else A.flags[oidx] = f;
+        const int64_t oidx = (int64_t)p * J.out_es + (int64_t)line * J.out_ls;
+        J.out[oidx] = omega;
+        if (J.flags) {
+            const uint8_t f = (uint8_t)(flag << J.flag_shift);
+            if (J.flag_or) J.flags[oidx] |= f;
+            else J.flags[oidx] = f;
         }
     }
+    ls.counted += counted;
+    ls.eig_its += eig_its;
+    ls.iters += iters;
+    ls.pfail += pfail;
+}
+
+// Grid-stride loop over the work items of every job of one L: item w is
+// block (w - prefix[j]) of job j, i.e. line (w - prefix[j]) / bpl and window
+// block (w - prefix[j]) % bpl.  A grid of one block per item runs each item
+// once; a smaller (persistent) grid walks the list.
+template <int L, int BLOCK, bool STATS, bool JACOBI>
+__global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
+    constexpr int WPB = BLOCK - (L - 1);
+    __shared__ float2 sg[BLOCK + kMaxN];
+    __shared__ float2 sS[L][BLOCK];
+    LaneStats ls;
+    for (int w = blockIdx.x; w < B.total; w += gridDim.x) {
+        int lo = 0, hi = B.njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.prefix[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const RmJob J = B.jobs[lo];
+        const int local = w - B.prefix[lo];
+        const int line = local / J.bpl;
+        const int bx = local - line * J.bpl;
+        rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, ls);
+        __syncthreads();
+    }
     if (STATS) {
-        unsigned long long a0 = counted, a1 = eig_its, a2 = iters, a3 = pfail;
+        unsigned long long a0 = ls.counted, a1 = ls.eig_its, a2 = ls.iters, a3 = ls.pfail;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             a0 += __shfl_xor(a0, off);
@@ -607,9 +635,9 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
             a2 += __shfl_xor(a2, off);
             a3 += __shfl_xor(a3, off);
         }
-        if ((t & 63) == 0) {
+        if ((threadIdx.x & 63) == 0) {
             // spread the counters over kStatSlots slots to avoid one hot address
-            unsigned long long* sl = A.stats + 4 * ((blockIdx.x + blockIdx.y * gridDim.x + (t >> 6)) % kStatSlots);
+            unsigned long long* sl = B.stats + 4 * ((blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) % kStatSlots);
             atomicAdd(sl + 0, a0);
             atomicAdd(sl + 1, a1);
             atomicAdd(sl + 2, a2);
@@ -618,34 +646,38 @@ __global__ __launch_bounds__(kBlock) void rootmusic_kernel(RootMusicArgs A) {
     }
 }
 
-template <int L, bool JACOBI>
-hipError_t launch_LJ(const RootMusicArgs& a, hipStream_t s) {
-    constexpr int WPB = windows_per_block<L>();
-    dim3 grid((a.len + WPB - 1) / WPB, a.nlines);
-    if (a.stats)
-        hipLaunchKernelGGL((rootmusic_kernel<L, true, JACOBI>), grid, dim3(kBlock), 0, s, a);
+template <int L, int BLOCK, bool JACOBI>
+hipError_t launch_LBJ(const RmBatch& b, int grid, hipStream_t s) {
+    if (b.stats)
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, true, JACOBI>), dim3(grid), dim3(BLOCK), 0, s, b);
     else
-        hipLaunchKernelGGL((rootmusic_kernel<L, false, JACOBI>), grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI>), dim3(grid), dim3(BLOCK), 0, s, b);
     return hipGetLastError();
 }
 
 template <int L>
-hipError_t launch_L(const RootMusicArgs& a, hipStream_t s) {
-    return a.jacobi ? launch_LJ<L, true>(a, s) : launch_LJ<L, false>(a, s);
+hipError_t launch_L(const RmBatch& b, int block, int grid, hipStream_t s) {
+    if (block == 128)
+        return b.jacobi ? launch_LBJ<L, 128, true>(b, grid, s) : launch_LBJ<L, 128, false>(b, grid, s);
+    return b.jacobi ? launch_LBJ<L, 256, true>(b, grid, s) : launch_LBJ<L, 256, false>(b, grid, s);
 }
 
 }  // namespace
 
-hipError_t launch_rootmusic(int L, const RootMusicArgs& a, hipStream_t s) {
-    if (a.len <= 0 || a.nlines <= 0) return hipSuccess;
+int rootmusic_windows_per_block(int L, int block) { return block - (L - 1); }
+
+hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStream_t s) {
+    if (b.total <= 0 || b.njobs <= 0) return hipSuccess;
+    if (block != 128 && block != 256) return hipErrorInvalidValue;
+    if (grid <= 0 || grid > b.total) grid = b.total;
     switch (L) {
-        case 2: return launch_L<2>(a, s);
-        case 3: return launch_L<3>(a, s);
-        case 4: return launch_L<4>(a, s);
-        case 5: return launch_L<5>(a, s);
-        case 6: return launch_L<6>(a, s);
-        case 7: return launch_L<7>(a, s);
-        case 8: return launch_L<8>(a, s);
+        case 2: return launch_L<2>(b, block, grid, s);
+        case 3: return launch_L<3>(b, block, grid, s);
+        case 4: return launch_L<4>(b, block, grid, s);
+        case 5: return launch_L<5>(b, block, grid, s);
+        case 6: return launch_L<6>(b, block, grid, s);
+        case 7: return launch_L<7>(b, block, grid, s);
+        case 8: return launch_L<8>(b, block, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -53,7 +53,8 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(pkg.bosmusic_frame) == 72
     assert pkg.bosmusic_frame.row_stride.offset == 24
     assert pkg.bosmusic_frame.omega_x.offset == 48
-    assert ctypes.sizeof(pkg.bosmusic_config) == 16
+    assert ctypes.sizeof(pkg.bosmusic_config) == 32
+    assert pkg.bosmusic_config.tune_cache.offset == 24
     assert ctypes.sizeof(pkg.bosmusic_stats) == 48
 
 
@@ -64,7 +65,7 @@ def test_null_arguments_are_rejected_without_device_work():
     assert L.bosmusic_integrate(None, None, None, 1, 1, 1, 1, 0.0, 0.0, None, None) == pkg.BM_E_INVALID_ARG
     assert L.bosmusic_get_stats(None, None, 0, None) == pkg.BM_E_INVALID_ARG
     assert L.bosmusic_destroy(None) == pkg.BM_OK
-    cfg = pkg.bosmusic_config(0, 0, 64, 0)
+    cfg = pkg.bosmusic_config(0, 0, 64, 0, 0, None)
     h = ctypes.c_void_p()
     assert L.bosmusic_create(ctypes.byref(cfg), ctypes.byref(h)) == pkg.BM_E_INVALID_ARG
     assert h.value is None
@@ -76,7 +77,7 @@ def test_create_without_gpu_reports_device_error():
     if gpu_available():
         pytest.skip("a GPU is visible")
     pkg, L = _lib()
-    cfg = pkg.bosmusic_config(0, 64, 64, 0)
+    cfg = pkg.bosmusic_config(0, 64, 64, 0, 0, None)
     h = ctypes.c_void_p()
     assert L.bosmusic_create(ctypes.byref(cfg), ctypes.byref(h)) == pkg.BM_E_DEVICE
     assert h.value is None
