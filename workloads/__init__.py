@@ -179,3 +179,77 @@ def random_frame(W, H, seed, dtype=np.float32, snr_db=10.0, f0=0.12, angle=40.0)
     """Small erf fringe with arbitrary (possibly ragged) size for parity tests."""
     img, twx, twy = erf_fringe(W, H, f0, angle, 4.0, H / 2.0, max(8.0, H / 6.0), snr_db, seed, dtype)
     return img
+
+
+# ---------------------------------------------------------------------------
+# Counter-based generator for the surrogate training lines
+# ---------------------------------------------------------------------------
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32(ctr, key, rounds: int = 10):
+    """Philox4x32 (Salmon, Moraes, Dror and Shaw, SC'11) on arrays of counters.
+
+    ctr: (..., 4) uint32, key: (..., 2) uint32.  Each round multiplies words 0
+    and 2 by the round constants, crosses the high halves with words 1 and 3
+    and the key, and the key is bumped by the Weyl constants between rounds.
+    """
+    c = [np.asarray(ctr[..., i], dtype=np.uint64) for i in range(4)]
+    k0 = np.asarray(key[..., 0], dtype=np.uint64)
+    k1 = np.asarray(key[..., 1], dtype=np.uint64)
+    mask = np.uint64(0xFFFFFFFF)
+    for r in range(rounds):
+        if r:
+            k0 = (k0 + np.uint64(PHILOX_W0)) & mask
+            k1 = (k1 + np.uint64(PHILOX_W1)) & mask
+        p0 = np.uint64(PHILOX_M0) * c[0]
+        p1 = np.uint64(PHILOX_M1) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return np.stack([x.astype(np.uint32) for x in c], axis=-1)
+
+
+def _uniform(u32):
+    """(u + 0.5) / 2^32: uniform in (0, 1), never 0 or 1."""
+    return (u32.astype(np.float64) + 0.5) * (1.0 / 4294967296.0)
+
+
+TRAIN_LINE_LEN = 128
+
+
+def philox_training_lines(line_ids, seed: int):
+    """Training lines drawn by counter: the GPU generator draws the same numbers.
+
+    Line i uses counter (i, 0, 0, 0) for its parameters
+        w = 2 pi/16 + u0 (2 pi/4 - 2 pi/16),  theta = 2 pi u1,  SNR = 30 u2 dB,
+    and counters (i, b+1, 0, 0), b < 32, for the noise of samples 4b..4b+3
+    (two Box-Muller pairs per call).  Sample n is
+        0.5 + 0.4 cos(w n + theta) + sqrt(0.08 10^(-SNR/10)) z_n.
+    Returns (lines[M, 128] float64, w[M]).
+    """
+    ids = np.asarray(line_ids, dtype=np.uint64)
+    M = ids.size
+    key = np.broadcast_to(np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], np.uint32), (M, 2))
+    ctr = np.zeros((M, 4), np.uint32)
+    ctr[:, 0] = ids.astype(np.uint32)
+    p = philox4x32(ctr, key)
+    u = _uniform(p)
+    w = 2 * math.pi / 16 + u[:, 0] * (2 * math.pi / 4 - 2 * math.pi / 16)
+    th = 2 * math.pi * u[:, 1]
+    snr = 30.0 * u[:, 2]
+    nb = TRAIN_LINE_LEN // 4
+    ctr2 = np.zeros((M, nb, 4), np.uint32)
+    ctr2[:, :, 0] = ids.astype(np.uint32)[:, None]
+    ctr2[:, :, 1] = np.arange(1, nb + 1, dtype=np.uint32)[None, :]
+    q = _uniform(philox4x32(ctr2, np.broadcast_to(key[:, None, :], (M, nb, 2))))
+    r0 = np.sqrt(-2.0 * np.log(q[..., 0]))
+    r1 = np.sqrt(-2.0 * np.log(q[..., 2]))
+    z = np.stack([r0 * np.cos(2 * math.pi * q[..., 1]), r0 * np.sin(2 * math.pi * q[..., 1]),
+                  r1 * np.cos(2 * math.pi * q[..., 3]), r1 * np.sin(2 * math.pi * q[..., 3])], axis=-1)
+    z = z.reshape(M, TRAIN_LINE_LEN)
+    n = np.arange(TRAIN_LINE_LEN, dtype=np.float64)[None, :]
+    sig = np.sqrt(B_AC * B_AC / 2.0 * 10.0 ** (-snr / 10.0))[:, None]
+    lines = A_DC + B_AC * np.cos(w[:, None] * n + th[:, None]) + sig * z
+    return lines, w
