@@ -73,7 +73,7 @@ def _oracle_job(job):
     return job, om
 
 
-def cpu_baseline(frames, sample_frames, lines_per_dir, L, N, workers):
+def cpu_baseline(frames, meta, sample_frames, lines_per_dir, workers):
     """Time the oracle on sampled rows and columns with a process pool.
 
     Runs before the GPU is touched; the pool forks with the frames already in
@@ -83,10 +83,10 @@ def cpu_baseline(frames, sample_frames, lines_per_dir, L, N, workers):
     _SAMPLE_FRAMES.update({t: frames[t] for t in sample_frames})
     jobs = []
     for t in sample_frames:
+        H, W = frames[t].shape
         for i in range(lines_per_dir):
-            r = (37 + i * 1024 // lines_per_dir) % 1024
-            jobs.append((t, "x", r, L, N))
-            jobs.append((t, "y", r, L, N))
+            jobs.append((t, "x", (37 + i * H // lines_per_dir) % H, meta[t].L, meta[t].N))
+            jobs.append((t, "y", (37 + i * W // lines_per_dir) % W, meta[t].L, meta[t].N))
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         pool.map(_oracle_job, jobs[:workers], chunksize=1)        # import warm-up, untimed
@@ -97,14 +97,42 @@ def cpu_baseline(frames, sample_frames, lines_per_dir, L, N, workers):
     return res, windows, dt
 
 
+def workload(name, nframes):
+    """Frames (numpy), per-frame (L, N, dirs) and a description of the workload."""
+    if name == "cfg2":
+        fr = [wl.cfg2_frame(t) for t in range(nframes or 100)]
+        desc = (f"{len(fr)} time-lapsed 1024x1024 FP32 fringe frames, carrier 0.1 cyc/px at 30 deg, 6*erf "
+                f"diffusion phase, SNR 10 dB; x and y windows N=32, L=6; plain root-MUSIC + FP64 phase integration")
+    elif name == "cfg3":
+        fr = [wl.cfg3_frame(k) for k in range(nframes or 64)]
+        desc = (f"{len(fr)} uneven FP32 frames 512x512..2048x1536 ({sum(f.width * f.height for f in fr)} px), "
+                f"L in {{4,6,8}}, N=2L+8, SNR 5-20 dB; one cached hipGraph replay per step, autotuned tiles; "
+                f"plain root-MUSIC + FP64 phase integration")
+    elif name in ("cfg4", "cfg5"):
+        fr = [wl.cfg4_frame(t) for t in range(nframes or 16)]
+        desc = (f"{len(fr)} 4096x4096 frames stored FP16, carrier 1/8 cyc/px at 45 deg, SNR 10 dB; x and y, "
+                f"L=8, N=32; FP32 covariance/eigen/rooting, FP64 polish and phase prefix sums")
+        if name == "cfg5":
+            desc = ("surrogate MLP 32-64-64-2 (GELU, BF16 MFMA, FP32 accumulate) trained on the GPU on 10M "
+                    "method-generated windows (carrier 1/16-1/4 cyc/px, SNR 0-30 dB, root-MUSIC L=8 N=32 labels), "
+                    "then surrogate + pseudospectrum check + root-MUSIC fallback on " + desc)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return fr, desc
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--train-windows", type=int, default=10_000_000, help="cfg5: training set size")
+    ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: Adam steps")
+    ap.add_argument("--train-batch", type=int, default=16384, help="cfg5: minibatch")
+    ap.add_argument("--frames", type=int, default=0, help="number of frames (0: the workload's own)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-lines", type=int, default=64, help="oracle sample: lines per direction per frame")
+    ap.add_argument("--cpu-lines", type=int, default=512, help="oracle sample: lines per direction per frame")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -113,24 +141,24 @@ def main():
               "see the sharding notes in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
 
-    W = H = 1024
-    L, N = 6, 32
-    nf = args.frames
     t_gen = time.perf_counter()
-    frames = [wl.cfg2_frame(t).data for t in range(nf)]
+    fr, desc = workload(args.workload, args.frames)
+    frames = [f.data for f in fr]
+    nf = len(fr)
+    total_px = sum(f.width * f.height for f in fr)
     t_gen = time.perf_counter() - t_gen
-    print(f"# generated {nf} frames in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    print(f"# generated {nf} frames ({total_px} px) in {t_gen:.1f}s", file=sys.stderr, flush=True)
 
     cpu = None
     sample = None
     if not args.no_cpu:
         workers = max(1, min(16, os.cpu_count() or 1))
         sf = sorted({0, nf // 3, (2 * nf) // 3, nf - 1})
-        res, windows, osec = cpu_baseline(frames, sf, args.cpu_lines, L, N, workers)
+        res, windows, osec = cpu_baseline(frames, fr, sf, args.cpu_lines, workers)
         sample = res
         px_s = windows / osec / 2.0            # two directions per pixel
         cpu = {"value": px_s / 1e6, "unit": "Mpixel/s", "cores": workers, "kind": "oracle",
-               "sample": f"cfg2 frames {sf}, {args.cpu_lines} rows + {args.cpu_lines} columns each "
+               "sample": f"{args.workload} frames {sf}, {args.cpu_lines} rows + {args.cpu_lines} columns each "
                          f"({windows} windows, {osec:.1f}s wall on {workers} processes); "
                          f"Mpixel/s = windows/s / 2 directions"}
         print(f"# oracle: {windows} windows in {osec:.2f}s on {workers} procs", file=sys.stderr, flush=True)
@@ -140,12 +168,20 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    d_frames = [torch.from_numpy(f).to(dev) for f in frames]
-    wx = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(nf)]
-    wy = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(nf)]
-    phi = [torch.empty((H, W), dtype=torch.float64, device=dev) for _ in range(nf)]
-    specs = [bm.FrameSpec(d_frames[i], L, N, bm.BM_DIR_X | bm.BM_DIR_Y, wx[i], wy[i]) for i in range(nf)]
-    dem = bm.Demodulator(0, max_width=W, max_height=H, timing=True)
+    maxw = max(f.width for f in fr)
+    maxh = max(f.height for f in fr)
+    d_frames = [torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in frames]
+    wx = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in frames]
+    wy = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in frames]
+    phi = [torch.empty(f.shape, dtype=torch.float64, device=dev) for f in frames]
+    specs = [bm.FrameSpec(d_frames[i], fr[i].L, fr[i].N, bm.BM_DIR_X | bm.BM_DIR_Y, wx[i], wy[i]) for i in range(nf)]
+    use_graph = args.workload == "cfg3"
+    tuned = {}
+    if use_graph:
+        tdem = bm.Demodulator(0, max_width=maxw, max_height=maxh)
+        for (L, N) in sorted({(f.L, f.N) for f in fr}):
+            tdem.autotune(L, N, width=1024, lines=512)
+        tdem.close()
     stream = torch.cuda.current_stream()
 
     if args.copy_mib > 0:
@@ -157,45 +193,70 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
-        bm.bosmusic_demodulate(dem.h, specs, bm.BM_PLAIN, stream)
+    def make(**kw):
+        return bm.Demodulator(0, max_width=maxw, max_height=maxh, max_batch_pixels=total_px, **kw)
+
+    def step(dm):
+        bm.bosmusic_demodulate(dm.h, specs, bm.BM_PLAIN, stream)
         for i in range(nf):
-            bm.bosmusic_integrate(dem.h, wx[i], wy[i], N, N, 0.0, 0.0, phi[i], stream)
+            bm.bosmusic_integrate(dm.h, wx[i], wy[i], fr[i].N, fr[i].N, 0.0, 0.0, phi[i], stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    dem.stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = dem.stats(reset=True)
-    ms = (t1 - t0) * 1e3 / args.steps
-    mpx = nf * W * H / (ms / 1e3) / 1e6
-    print(f"# {args.steps} steps, {ms:.2f} ms/step, {mpx:.1f} Mpixel/s", file=sys.stderr, flush=True)
+    def timed(dm):
+        for _ in range(args.warmup):
+            step(dm)
+        torch.cuda.synchronize()
+        dm.stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(dm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / args.steps, dm.stats(reset=True)
 
-    # iteration counts of the same workload (stats variant of the kernel, outside the timed region)
-    sdem = bm.Demodulator(0, max_width=W, max_height=H, stats=True)
-    ow = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(2)]
-    for i in sorted({0, nf // 2, nf - 1}):
-        bm.bosmusic_demodulate(sdem.h, [bm.FrameSpec(d_frames[i], L, N, 3, ow[0], ow[1])], bm.BM_PLAIN, stream)
-    ss = sdem.stats(reset=True)
-    sdem.close()
-    mean_newton = ss["eig_iters"] / max(1, ss["windows"])
-    mean_iters = ss["root_iters"] / max(1, ss["windows"])
-    fl = flops_per_window(L, N, mean_newton, mean_iters)
-    win_per_launch = H * (W - N + 1)
-    avg_launch_s = st["rm_time_ns"] / max(1, st["rm_launches"]) / 1e9
-    achieved = fl["total"] * win_per_launch / avg_launch_s
+    # the production path (graph replay for the uneven batch), then the same
+    # steps with HIP events around every root-MUSIC launch for the roofline
+    if use_graph:
+        gdem = make(graph=True)
+        ms, _ = timed(gdem)
+        gdem.close()
+        dem = make(timing=True)
+        ms_ev, st = timed(dem)
+    else:
+        dem = make(timing=True)
+        ms, st = timed(dem)
+        ms_ev = ms
+    mpx = total_px / (ms / 1e3) / 1e6
+    print(f"# {args.steps} steps, {ms:.2f} ms/step, {mpx:.1f} Mpixel/s (event-timed pass {ms_ev:.2f} ms/step)",
+          file=sys.stderr, flush=True)
+
+    # iteration counts per L (counting variant of the kernel, outside the timed region)
+    flops_step = 0.0
+    per_L = {}
+    for L in sorted({f.L for f in fr}):
+        idx = [i for i in range(nf) if fr[i].L == L]
+        sdem = bm.Demodulator(0, max_width=maxw, max_height=maxh, stats=True)
+        sub = [specs[i] for i in idx[:3]]
+        bm.bosmusic_demodulate(sdem.h, sub, bm.BM_PLAIN, stream)
+        ss = sdem.stats(reset=True)
+        sdem.close()
+        newton = ss["eig_iters"] / max(1, ss["windows"])
+        iters = ss["root_iters"] / max(1, ss["windows"])
+        wins = 0
+        for i in idx:
+            W, H, N = fr[i].width, fr[i].height, fr[i].N
+            wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
+        fl = flops_per_window(L, fr[idx[0]].N, newton, iters)
+        flops_step += fl["total"] * wins
+        per_L[L] = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2), "root_iters": round(iters, 2),
+                    "windows_per_step": wins}
+    rm_s = st["rm_time_ns"] / 1e9 / args.steps          # root-MUSIC time per step
+    achieved = flops_step / rm_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-            "kernel": f"rootmusic_kernel<L=6>, {win_per_launch} windows/launch, "
-                      f"{fl['total']:.0f} flop/window (mean {mean_newton:.2f} Newton steps, "
-                      f"{mean_iters:.2f} root iterations), mean launch {avg_launch_s * 1e3:.3f} ms over "
-                      f"{st['rm_launches']} launches"}
+            "kernel": f"rootmusic_kernel, {st['rm_launches'] // args.steps} launch(es)/step, mean launch "
+                      f"{st['rm_time_ns'] / max(1, st['rm_launches']) / 1e6:.3f} ms (HIP events on its stream), "
+                      f"per L: {json.dumps(per_L)}"}
 
     err = None
     if sample is not None:
@@ -222,10 +283,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{nf} time-lapsed 1024x1024 FP32 fringe frames, carrier 0.1 cyc/px at 30 deg, "
-                               f"6*erf diffusion phase, SNR 10 dB; x and y windows N=32, L=6; plain root-MUSIC "
-                               f"+ FP64 phase integration",
-                   "frames": nf, "width": W, "height": H, "L": L, "N": N, "dirs": "xy", "mode": "plain"},
+        "config": {"workload": desc, "name": args.workload, "frames": nf, "pixels": total_px,
+                   "dirs": "xy", "mode": "plain", "graph": use_graph},
         "roofline": roof,
         "cpu_baseline": cpu,
         "error": err,

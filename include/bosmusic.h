@@ -120,6 +120,8 @@ typedef struct {
     uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI) */
     uint64_t root_iters;    /* sum over windows of simultaneous root iterations */
     uint64_t polish_fail;   /* windows whose FP64 pair polish did not converge */
+    uint64_t sur_accepted;  /* BM_SURROGATE: windows whose surrogate estimate was accepted */
+    uint64_t sur_rejected;  /* BM_SURROGATE: windows sent to the plain fallback */
     uint64_t rm_launches;   /* root-MUSIC kernel launches timed (BM_OPT_TIMING) */
     uint64_t rm_time_ns;    /* their summed duration between HIP events, ns */
 } bosmusic_stats;
@@ -140,7 +142,8 @@ bm_status bosmusic_destroy(bosmusic_t h);
  * the per-L launches on forked streams).  The job tables of a group are
  * uploaded from pinned host memory on `stream`; the call may wait for the
  * previous call's upload to finish before reusing that buffer.
- * mode: BM_PLAIN (BM_SURROGATE returns BM_E_UNSUPPORTED in this build).
+ * mode: BM_PLAIN, or BM_SURROGATE (needs loaded parameters unless the
+ * lag-1 predictor is configured, and N >= 16 for every frame).
  * Requirements per frame: 2 <= L <= 8, L <= N <= 64, width/height within
  * the handle's maximum, row_stride >= width; for real dtypes the length of
  * every requested direction must factor into 2, 3 and 5 and be <= 8192
@@ -165,6 +168,80 @@ bm_status bosmusic_integrate(bosmusic_t h, const float* omega_x, const float* om
  * synchronising `stream`; reset = 1 zeroes them afterwards.  Counters of an
  * option that is not set read zero. */
 bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, void* stream);
+
+/* ---- learned surrogate (BM_SURROGATE) -------------------------------------
+ * An MLP 32 -> 64 -> 64 -> 2 (exact-erf GELU) maps the normalised window (16
+ * central samples de-rotated by the central sample's phase, divided by the
+ * window's RMS magnitude, [Re(16), Im(16)]) to (cos w, sin w).  Its estimate
+ * seeds a power iteration for the signal subspace and Newton iterations on
+ * the quadratic factor of the root-MUSIC polynomial (paper Eq. 12); the
+ * window is accepted when the factor converged with a root within 0.05 of
+ * the unit circle and the MUSIC null spectrum 1 - |u1^H a(w)|^2 / L at the
+ * refined w is below tau; every other window is finished by the plain path.
+ * Parameters are FP32, in this order, row-major: W1[32][64], b1[64],
+ * W2[64][64], b2[64], W3[64][2], b3[2] (6402 floats); the kernels use
+ * bfloat16 copies (round to nearest even) and FP32 accumulation. */
+#define BOSMUSIC_MLP_PARAMS 6402
+
+/* Load FP32 parameters from host memory (n must be BOSMUSIC_MLP_PARAMS).
+ * Synchronous. */
+bm_status bosmusic_surrogate_load(bosmusic_t h, const float* params, int64_t n);
+
+/* Copy the current FP32 parameters to host memory. Synchronous. */
+bm_status bosmusic_surrogate_save(bosmusic_t h, float* params, int64_t n);
+
+/* Acceptance bound tau on the null spectrum (default 1e-3) and predictor:
+ * 0 = the MLP, 1 = the lag-1 phase of the covariance (a non-learned
+ * predictor, for comparison). */
+bm_status bosmusic_surrogate_config(bosmusic_t h, float tau, int32_t predictor);
+
+/* Y[M][2] = MLP(X[M][32]) on the device (X, Y device pointers, FP32), with
+ * the same bfloat16 arithmetic as BM_SURROGATE.  Enqueued on `stream`. */
+bm_status bosmusic_surrogate_forward(bosmusic_t h, const float* X, float* Y, int32_t M, void* stream);
+
+/* ---- surrogate training ----------------------------------------------------
+ * The network is trained on windows and labels the method produces itself.
+ * Training line i (0 <= i < 2^32) has 128 samples
+ *     0.5 + 0.4 cos(w n + theta) + sqrt(0.08 * 10^(-SNR/10)) z_n,
+ * w = 2 pi/16 + u0 (2 pi/4 - 2 pi/16), theta = 2 pi u1, SNR = 30 u2 dB, with
+ * (u0, u1, u2) from Philox4x32-10 (Salmon et al., SC'11) at counter
+ * (i, 0, 0, 0) and key (seed low, seed high), u = (x + 0.5) / 2^32, and the
+ * Gaussian noise z of samples 4b..4b+3 from counter (i, b+1, 0, 0) by two
+ * Box-Muller pairs (r cos, r sin of words 0,1 and of words 2,3).  Its label is
+ * the plain root-MUSIC frequency (Sec. 3, Eq. 15) of the window N = 32,
+ * L = 8 centred on sample 64 of the line's analytic signal (Eq. 1); its
+ * features are those of that window, its target (cos, sin) of the label. */
+
+/* Generate lines first_line .. first_line+count-1: X[count][32] features,
+ * T[count][2] targets and, when omega is not NULL, omega[count] labels, all
+ * device pointers (FP32) owned by the caller.  Works on `stream` and
+ * returns after synchronising it. */
+bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t count, uint64_t seed, float* X,
+                                     float* T, float* omega, void* stream);
+
+/* Gradient of the mean over the M samples (M a positive multiple of 64) of
+ * the squared error |MLP(X_m) - T_m|^2 with respect to the parameters at the
+ * current weights (bfloat16 operands, FP32 accumulation, the bfloat16
+ * roundings taken as identity).  grad[BOSMUSIC_MLP_PARAMS] in the parameter
+ * order and loss[1] (may be NULL) are device pointers.  Enqueued on `stream`;
+ * the result does not depend on scheduling (fixed summation order). */
+bm_status bosmusic_surrogate_grad(bosmusic_t h, const float* X, const float* T, int32_t M, float* grad, float* loss,
+                                  void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * count since the last bosmusic_surrogate_load) on the FP32 parameters with
+ * the device gradient grad[BOSMUSIC_MLP_PARAMS]; refreshes the bfloat16
+ * copies.  Enqueued on `stream`. */
+bm_status bosmusic_surrogate_step(bosmusic_t h, const float* grad, float lr, void* stream);
+
+/* `steps` Adam steps of minibatch training over X[M][32], T[M][2] (device):
+ * step s uses the batch of `batch` samples (a multiple of 64) starting at
+ * ((s mod (M / batch)) * batch), continuing the handle's step count.  With
+ * `losses` (host, `steps` floats) non-NULL, receives the loss of each step
+ * before its update and returns after synchronising `stream`; otherwise
+ * only enqueues. */
+bm_status bosmusic_surrogate_train(bosmusic_t h, const float* X, const float* T, int64_t M, int32_t batch,
+                                   int32_t steps, float lr, float* losses, void* stream);
 
 /* Autotune the root-MUSIC launch for covariance size L and window N on the
  * handle's device: times every candidate tile shape (128 or 256 lanes per

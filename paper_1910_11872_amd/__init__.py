@@ -29,7 +29,10 @@ BM_FLAG_UNDEFINED, BM_FLAG_NO_POLISH = 1, 2
 
 ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "bosmusic_integrate",
                  "bosmusic_autotune", "bosmusic_get_stats", "bosmusic_status_string", "bosmusic_last_error",
-                 "bosmusic_version")
+                 "bosmusic_version", "bosmusic_surrogate_load", "bosmusic_surrogate_save",
+                 "bosmusic_surrogate_config", "bosmusic_surrogate_forward", "bosmusic_surrogate_dataset",
+                 "bosmusic_surrogate_grad", "bosmusic_surrogate_step", "bosmusic_surrogate_train")
+MLP_PARAMS = 6402
 
 
 class bosmusic_config(ctypes.Structure):
@@ -45,7 +48,8 @@ class bosmusic_frame(ctypes.Structure):
 
 class bosmusic_stats(ctypes.Structure):
     _fields_ = [("windows", c_uint64), ("eig_iters", c_uint64), ("root_iters", c_uint64),
-                ("polish_fail", c_uint64), ("rm_launches", c_uint64), ("rm_time_ns", c_uint64)]
+                ("polish_fail", c_uint64), ("sur_accepted", c_uint64), ("sur_rejected", c_uint64),
+                ("rm_launches", c_uint64), ("rm_time_ns", c_uint64)]
 
 
 class BosmusicError(RuntimeError):
@@ -77,6 +81,24 @@ def lib():
         L.bosmusic_autotune.restype = c_int32
         L.bosmusic_get_stats.argtypes = [c_void_p, POINTER(bosmusic_stats), c_int32, c_void_p]
         L.bosmusic_get_stats.restype = c_int32
+        L.bosmusic_surrogate_load.argtypes = [c_void_p, c_void_p, c_int64]
+        L.bosmusic_surrogate_load.restype = c_int32
+        L.bosmusic_surrogate_save.argtypes = [c_void_p, c_void_p, c_int64]
+        L.bosmusic_surrogate_save.restype = c_int32
+        L.bosmusic_surrogate_config.argtypes = [c_void_p, ctypes.c_float, c_int32]
+        L.bosmusic_surrogate_config.restype = c_int32
+        L.bosmusic_surrogate_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+        L.bosmusic_surrogate_forward.restype = c_int32
+        L.bosmusic_surrogate_dataset.argtypes = [c_void_p, c_int64, c_int64, ctypes.c_uint64, c_void_p, c_void_p,
+                                                 c_void_p, c_void_p]
+        L.bosmusic_surrogate_dataset.restype = c_int32
+        L.bosmusic_surrogate_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+        L.bosmusic_surrogate_grad.restype = c_int32
+        L.bosmusic_surrogate_step.argtypes = [c_void_p, c_void_p, ctypes.c_float, c_void_p]
+        L.bosmusic_surrogate_step.restype = c_int32
+        L.bosmusic_surrogate_train.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int32,
+                                               ctypes.c_float, c_void_p, c_void_p]
+        L.bosmusic_surrogate_train.restype = c_int32
         L.bosmusic_status_string.argtypes = [c_int32]
         L.bosmusic_status_string.restype = c_char_p
         L.bosmusic_last_error.argtypes = [c_void_p]
@@ -181,6 +203,69 @@ def bosmusic_autotune(h, L: int, N: int, width: int = 1024, lines: int = 512, st
     return us.value
 
 
+def _flat_params(params):
+    import numpy as np
+    if isinstance(params, dict):
+        params = np.concatenate([np.asarray(params[k], np.float32).reshape(-1)
+                                 for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    a = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    if a.size != MLP_PARAMS:
+        raise ValueError(f"need {MLP_PARAMS} parameters, got {a.size}")
+    return a
+
+
+def bosmusic_surrogate_load(h, params) -> None:
+    """params: flat FP32 array (W1, b1, W2, b2, W3, b3 row-major) or a dict of them."""
+    a = _flat_params(params)
+    _check(lib().bosmusic_surrogate_load(h, a.ctypes.data_as(c_void_p), a.size), h)
+
+
+def bosmusic_surrogate_save(h):
+    import numpy as np
+    a = np.empty(MLP_PARAMS, np.float32)
+    _check(lib().bosmusic_surrogate_save(h, a.ctypes.data_as(c_void_p), a.size), h)
+    return a
+
+
+def bosmusic_surrogate_config(h, tau: float = 1e-3, predictor: int = 0) -> None:
+    _check(lib().bosmusic_surrogate_config(h, tau, predictor), h)
+
+
+def bosmusic_surrogate_forward(h, X, Y, stream=None) -> None:
+    """Y[M, 2] = MLP(X[M, 32]); X, Y contiguous FP32 device tensors."""
+    _check(lib().bosmusic_surrogate_forward(h, c_void_p(X.data_ptr()), c_void_p(Y.data_ptr()), X.shape[0],
+                                            _stream_ptr(stream)), h)
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(None)
+
+
+def bosmusic_surrogate_dataset(h, first_line: int, X, T, omega=None, seed: int = 0, stream=None) -> None:
+    """Fill X[M, 32], T[M, 2] (and omega[M]) with training lines first_line .. first_line+M-1."""
+    _check(lib().bosmusic_surrogate_dataset(h, first_line, X.shape[0], seed, _ptr(X), _ptr(T), _ptr(omega),
+                                            _stream_ptr(stream)), h)
+
+
+def bosmusic_surrogate_grad(h, X, T, grad, loss=None, stream=None) -> None:
+    _check(lib().bosmusic_surrogate_grad(h, _ptr(X), _ptr(T), X.shape[0], _ptr(grad), _ptr(loss),
+                                         _stream_ptr(stream)), h)
+
+
+def bosmusic_surrogate_step(h, grad, lr: float, stream=None) -> None:
+    _check(lib().bosmusic_surrogate_step(h, _ptr(grad), lr, _stream_ptr(stream)), h)
+
+
+def bosmusic_surrogate_train(h, X, T, batch: int, steps: int, lr: float, want_losses: bool = True, stream=None):
+    """Minibatch Adam over (X, T); returns the per-step losses (host) when want_losses."""
+    import numpy as np
+    losses = np.empty(max(steps, 1), np.float32) if want_losses else None
+    _check(lib().bosmusic_surrogate_train(h, _ptr(X), _ptr(T), X.shape[0], batch, steps, lr,
+                                          losses.ctypes.data_as(c_void_p) if want_losses else c_void_p(None),
+                                          _stream_ptr(stream)), h)
+    return losses[:steps] if want_losses else None
+
+
 def bosmusic_get_stats(h, reset: bool = False, stream=None) -> dict:
     s = bosmusic_stats()
     _check(lib().bosmusic_get_stats(h, byref(s), int(reset), _stream_ptr(stream)), h)
@@ -211,7 +296,8 @@ class Demodulator:
         except Exception:
             pass
 
-    def demodulate(self, frame, L: int, N: int, dirs: str = "xy", flags: bool = False, stream=None):
+    def demodulate(self, frame, L: int, N: int, dirs: str = "xy", flags: bool = False, stream=None,
+                   mode: int = BM_PLAIN):
         """Returns (omega_x or None, omega_y or None[, flags]) for one device frame."""
         import torch
         H, W = frame.shape
@@ -219,7 +305,7 @@ class Demodulator:
         wx = torch.empty((H, W), dtype=torch.float32, device=frame.device) if "x" in dirs else None
         wy = torch.empty((H, W), dtype=torch.float32, device=frame.device) if "y" in dirs else None
         fl = torch.empty((H, W), dtype=torch.uint8, device=frame.device) if flags else None
-        bosmusic_demodulate(self.h, [FrameSpec(frame, L, N, d, wx, wy, fl)], BM_PLAIN, stream)
+        bosmusic_demodulate(self.h, [FrameSpec(frame, L, N, d, wx, wy, fl)], mode, stream)
         return (wx, wy, fl) if flags else (wx, wy)
 
     def demodulate_many(self, specs, stream=None):

@@ -13,7 +13,9 @@ constexpr int kMaxL = 8;
 constexpr int kMaxN = 64;
 constexpr int kMaxFFT = 8192;
 constexpr int kMaxRadixPasses = 20;
-constexpr int kStatSlots = 64;   // counter slots of the statistics buffer (4 counters each)
+constexpr int kStatSlots = 64;   // counter slots of the statistics buffer
+constexpr int kStatFields = 8;   // counters per slot (6 used)
+constexpr int kGatherBlock = 256;
 
 // Mixed-radix plan of one DFT length (radices 4, 2, 3, 5 in pass order).
 struct FftPlan {
@@ -58,7 +60,7 @@ struct RmBatch {
     int njobs;
     int total;             // prefix[njobs]
     int jacobi;            // 1: cyclic Jacobi eigen-split instead of the tridiagonal solver
-    unsigned long long* stats;  // kStatSlots x 4 counters, or nullptr
+    unsigned long long* stats;  // kStatSlots x kStatFields counters, or nullptr
     RootTemplate tmpl;
 };
 
@@ -103,6 +105,59 @@ struct TrBatch {
 // block per work item).
 hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStream_t s);
 int rootmusic_windows_per_block(int L, int block);
+// Plain root-MUSIC on the *count windows of `list` ({job, line << 16 | pixel}),
+// grid-stride over `grid` blocks of kGatherBlock lanes.
+hipError_t launch_rootmusic_gather(int L, const RmBatch& b, const int2* list, const int* count, int grid,
+                                   hipStream_t s);
+
+// Surrogate MLP 32 -> 64 -> 64 -> 2 (GELU), bfloat16 weights stored
+// transposed (out x in) for the MFMA A operand, FP32 biases.
+struct MlpWeights {
+    const __bf16* w1t;     // [64][32]
+    const __bf16* w2t;     // [64][64]
+    const __bf16* w3t;     // [16][64], rows 2..15 zero
+    const float* b1;       // [64]
+    const float* b2;       // [64]
+    const float* b3;       // [2]
+};
+constexpr int kMlpIn = 32, kMlpHidden = 64, kMlpOut = 2;
+constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpHidden * kMlpOut + kMlpOut;   // 6402
+
+struct SurBatch {
+    RmBatch rm;            // the windows (jobs of one L)
+    MlpWeights w;
+    int2* rejects;         // windows sent to the plain fallback
+    int* reject_count;
+    int predictor;         // 0: MLP, 1: lag-1 phase of the covariance (no learning)
+    float tau;             // acceptance bound on the null spectrum at the refined frequency
+};
+
+// Surrogate pass over every window of b.rm (256 lanes per block, one block
+// per work item); windows it cannot accept are appended to b.rejects.
+hipError_t launch_surrogate(int L, const SurBatch& b, hipStream_t s);
+// Y[M x 2] = MLP(X[M x 32]) with the kernel's bfloat16 arithmetic.
+hipError_t launch_mlp_forward(const MlpWeights& w, const float* X, float* Y, int M, hipStream_t s);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+
+// Surrogate training.  Lines of 128 samples drawn by counter (Philox4x32-10)
+// for ids first .. first+count-1; label windows {job = i >> 16, line = i & 0xFFFF,
+// pixel 64}; features and targets of the centre window of each line.
+hipError_t launch_gen_lines(float* lines, long long first, int count, unsigned long long seed, hipStream_t s);
+hipError_t launch_label_entries(int2* list, int count, hipStream_t s);
+hipError_t launch_train_features(const float2* gamma, int count, const float* labels, float* X, float* T,
+                                 hipStream_t s);
+int mlp_train_blocks(int M);
+int mlp_partial_stride();
+// Per-block gradient partials of the mean squared error over M samples (M % 64 == 0).
+hipError_t launch_mlp_train(const MlpWeights& w, const __bf16* w2, const float* X, const float* T, int M, float* part,
+                            int nblocks, hipStream_t s);
+// Fixed-order sums of the partials into grad (optional) and loss (optional),
+// then with adam != 0 one Adam step (bias corrections c1 = 1/(1-b1^t),
+// c2 = 1/(1-b2^t)) on master with bfloat16 copies written to wts
+// (W1^T | W2^T | W3^T | W2).
+hipError_t launch_mlp_reduce_adam(const float* part, int nblocks, float* master, float* m, float* v, float* grad,
+                                  float* loss, __bf16* wts, int adam, float lr, float c1, float c2, hipStream_t s);
 hipError_t launch_transpose(const TrBatch& b, hipStream_t s);
 hipError_t launch_analytic(const FftBatch& b, hipStream_t s);
 

@@ -66,6 +66,25 @@ struct bosmusic_s {
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kMaxForks] = {};
     hipStream_t last_graph_stream = nullptr;
+    // surrogate
+    float* sur_master = nullptr;   // FP32 parameters (BOSMUSIC_MLP_PARAMS)
+    __bf16* sur_w = nullptr;       // bfloat16 W1^T [64][32] | W2^T [64][64] | W3^T [16][64] | W2 [64][64]
+    bool sur_loaded = false;
+    float sur_tau = 1e-3f;
+    int sur_predictor = 0;
+    int2* rejects = nullptr;
+    size_t rejects_cap = 0;
+    int* reject_count = nullptr;
+    // surrogate training
+    float* adam_m = nullptr;       // Adam moments (BOSMUSIC_MLP_PARAMS each)
+    float* adam_v = nullptr;
+    int64_t adam_t = 0;            // Adam steps since the last load
+    float* part = nullptr;         // per-block gradient partials
+    int part_blocks = 0;
+    float* losses = nullptr;       // per-step losses of a train call
+    int losses_cap = 0;
+    char* ds = nullptr;            // dataset generation buffers
+    size_t ds_bytes = 0;
     std::string err;
 };
 
@@ -245,6 +264,7 @@ struct RmSet {
 };
 
 struct GroupPlan {
+    int mode = BM_PLAIN;
     std::vector<bm::TrJob> tr;
     std::vector<int> tr_prefix;
     std::vector<bm::FftJob> fft;
@@ -265,7 +285,7 @@ size_t append(std::vector<char>& blob, const std::vector<T>& v) {
     return off;
 }
 
-bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1, GroupPlan& gp) {
+bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1, int mode, GroupPlan& gp) {
     size_t cur = 0;
     std::map<std::pair<int, int>, RmSet> sets;   // (L, pass) -> set
     bool any_flags = false;
@@ -368,6 +388,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         int nmax = 0;
         for (auto& j : s.jobs) nmax = std::max(nmax, j.N);
         s.tune = h->tune[s.L][nmax];
+        if (mode == BM_SURROGATE) s.tune = Tune{};   // the surrogate kernel runs 256 lanes, one block per item
         const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block);
         s.prefix.assign(1, 0);
         for (auto& j : s.jobs) {
@@ -376,6 +397,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         }
         gp.rm.push_back(s);
     }
+    gp.mode = mode;
     gp.blob.clear();
     gp.tr_off = append(gp.blob, gp.tr);
     gp.trp_off = append(gp.blob, gp.tr_prefix);
@@ -415,10 +437,64 @@ int grid_for(const bosmusic_s* h, const Tune& t, int total) {
     return std::min(total, t.grid_per_cu * h->cu_count);
 }
 
+bm::MlpWeights mlp_weights(const bosmusic_s* h) {
+    bm::MlpWeights w;
+    w.w1t = h->sur_w;
+    w.w2t = h->sur_w + bm::kMlpHidden * bm::kMlpIn;
+    w.w3t = h->sur_w + bm::kMlpHidden * bm::kMlpIn + bm::kMlpHidden * bm::kMlpHidden;
+    w.b1 = h->sur_master + bm::kMlpIn * bm::kMlpHidden;
+    w.b2 = h->sur_master + bm::kMlpIn * bm::kMlpHidden + bm::kMlpHidden + bm::kMlpHidden * bm::kMlpHidden;
+    w.b3 = h->sur_master + bm::kMlpParams - bm::kMlpOut;
+    return w;
+}
+
+// Windows of a set (upper bound on the reject list it can produce).
+size_t set_windows(const RmSet& s) {
+    size_t n = 0;
+    for (auto& j : s.jobs) n += (size_t)j.nlines * (size_t)j.len;
+    return n;
+}
+
+bm_status ensure_rejects(bosmusic_s* h, size_t n, hipStream_t st) {
+    if (n <= h->rejects_cap && h->reject_count) return BM_OK;
+    bm_status r;
+    if ((r = check(h, hipStreamSynchronize(st), "sync before growing the reject list"))) return r;
+    (void)hipFree(h->rejects);
+    h->rejects = nullptr;
+    h->rejects_cap = 0;
+    if (!h->reject_count && hipMalloc(&h->reject_count, sizeof(int)) != hipSuccess)
+        return fail(h, BM_E_NOMEM, "reject counter");
+    if (hipMalloc(&h->rejects, std::max<size_t>(n, 1) * sizeof(int2)) != hipSuccess)
+        return fail(h, BM_E_NOMEM, "reject list of %zu windows", n);
+    h->rejects_cap = n;
+    return BM_OK;
+}
+
+// Surrogate pass over a set, then the plain path on the windows it rejected.
+bm_status launch_sur(bosmusic_s* h, const RmSet& s, hipStream_t st) {
+    bm_status r;
+    bm::SurBatch sb;
+    sb.rm = s.batch;
+    sb.w = mlp_weights(h);
+    sb.rejects = h->rejects;
+    sb.reject_count = h->reject_count;
+    sb.predictor = h->sur_predictor;
+    sb.tau = h->sur_tau;
+    if ((r = check(h, bm::launch_fill_int(h->reject_count, 1, 0, st), "reject counter"))) return r;
+    if ((r = check(h, bm::launch_surrogate(s.L, sb, st), "surrogate"))) return r;
+    const size_t cap = set_windows(s);
+    const int grid = (int)std::min<size_t>((size_t)4 * h->cu_count, (cap + bm::kGatherBlock - 1) / bm::kGatherBlock);
+    return check(h, bm::launch_rootmusic_gather(s.L, s.batch, h->rejects, h->reject_count, std::max(grid, 1), st),
+                 "fallback");
+}
+
 // Root-MUSIC launch, bracketed by HIP events on the same stream when timing.
-bm_status launch_rm(bosmusic_s* h, const RmSet& s, hipStream_t st, bool timing) {
+bm_status launch_rm(bosmusic_s* h, const RmSet& s, hipStream_t st, bool timing, int mode) {
     const int grid = grid_for(h, s.tune, s.batch.total);
-    if (!timing) return check(h, bm::launch_rootmusic(s.L, s.batch, s.tune.block, grid, st), "rootmusic");
+    if (!timing) {
+        if (mode == BM_SURROGATE) return launch_sur(h, s, st);
+        return check(h, bm::launch_rootmusic(s.L, s.batch, s.tune.block, grid, st), "rootmusic");
+    }
     std::pair<hipEvent_t, hipEvent_t> ev;
     bm_status r;
     if (!h->ev_free.empty()) {
@@ -433,7 +509,11 @@ bm_status launch_rm(bosmusic_s* h, const RmSet& s, hipStream_t st, bool timing) 
     }
     h->ev_pending.push_back(ev);
     if ((r = check(h, hipEventRecord(ev.first, st), "event record"))) return r;
-    if ((r = check(h, bm::launch_rootmusic(s.L, s.batch, s.tune.block, grid, st), "rootmusic"))) return r;
+    if (mode == BM_SURROGATE) {
+        if ((r = launch_sur(h, s, st))) return r;
+    } else if ((r = check(h, bm::launch_rootmusic(s.L, s.batch, s.tune.block, grid, st), "rootmusic"))) {
+        return r;
+    }
     return check(h, hipEventRecord(ev.second, st), "event record");
 }
 
@@ -466,6 +546,11 @@ bm_status ensure_upload_buffers(bosmusic_s* h, size_t bytes, hipStream_t st) {
 bm_status run_group_eager(bosmusic_s* h, GroupPlan& gp, hipStream_t st) {
     bm_status r;
     if ((r = ensure_upload_buffers(h, gp.blob.size(), st))) return r;
+    if (gp.mode == BM_SURROGATE) {
+        size_t mx = 0;
+        for (auto& s : gp.rm) mx = std::max(mx, set_windows(s));
+        if ((r = ensure_rejects(h, mx, st))) return r;
+    }
     if (h->pin_pending && (r = check(h, hipEventSynchronize(h->pin_ev), "upload wait"))) return r;
     std::memcpy(h->pin, gp.blob.data(), gp.blob.size());
     if ((r = check(h, hipMemcpyAsync(h->djobs, h->pin, gp.blob.size(), hipMemcpyHostToDevice, st), "job upload")))
@@ -476,13 +561,18 @@ bm_status run_group_eager(bosmusic_s* h, GroupPlan& gp, hipStream_t st) {
     if ((r = launch_front(h, gp, st))) return r;
     const bool timing = (h->options & BM_OPT_TIMING) != 0;
     for (auto& s : gp.rm)
-        if ((r = launch_rm(h, s, st, timing))) return r;
+        if ((r = launch_rm(h, s, st, timing, gp.mode))) return r;
     return BM_OK;
 }
 
 // Signature of a call: every frame field, mode-relevant options and tuning.
-std::string signature(const bosmusic_s* h, const bosmusic_frame* frames, int n) {
+std::string signature(const bosmusic_s* h, const bosmusic_frame* frames, int n, int mode) {
     std::string key;
+    key.append((const char*)&mode, sizeof(mode));
+    if (mode == BM_SURROGATE) {
+        key.append((const char*)&h->sur_tau, sizeof(h->sur_tau));
+        key.append((const char*)&h->sur_predictor, sizeof(h->sur_predictor));
+    }
     key.append((const char*)frames, (size_t)n * sizeof(bosmusic_frame));
     key.append((const char*)&h->options, sizeof(h->options));
     for (int i = 0; i < n; ++i) key.append((const char*)&h->tune[frames[i].L][frames[i].N], sizeof(Tune));
@@ -497,13 +587,16 @@ void destroy_graph(GraphEntry& g) {
 }
 
 bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
-                      const std::vector<std::pair<int, int>>& groups, GraphEntry& ge) {
+                      const std::vector<std::pair<int, int>>& groups, int mode, hipStream_t st, GraphEntry& ge) {
     bm_status r;
     std::vector<GroupPlan> plans(groups.size());
     size_t total = 0;
     std::vector<size_t> offs;
     for (size_t g = 0; g < groups.size(); ++g) {
-        if ((r = plan_group(h, frames, groups[g].first, groups[g].second, plans[g]))) return r;
+        if ((r = plan_group(h, frames, groups[g].first, groups[g].second, mode, plans[g]))) return r;
+        if (mode == BM_SURROGATE)
+            for (auto& s : plans[g].rm)
+                if ((r = ensure_rejects(h, set_windows(s), st))) return r;
         offs.push_back(align_up(total, 256));
         total = offs.back() + plans[g].blob.size();
     }
@@ -520,7 +613,7 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
     for (auto& gp : plans) {
         if ((lr = launch_front(h, gp, c0))) break;
         if (gp.rm.size() == 1) {
-            if ((lr = launch_rm(h, gp.rm[0], c0, false))) break;
+            if ((lr = launch_rm(h, gp.rm[0], c0, false, mode))) break;
             continue;
         }
         // fork: each distinct L on its own capture stream; a y pass stays on
@@ -537,7 +630,7 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
                 break;
         if (lr) break;
         for (auto& s : gp.rm)
-            if ((lr = launch_rm(h, s, h->cap[lane_of_L[s.L]], false))) break;
+            if ((lr = launch_rm(h, s, h->cap[lane_of_L[s.L]], false, mode))) break;
         if (lr) break;
         for (auto& kv : lane_of_L) {
             if (kv.second == 0) continue;
@@ -559,8 +652,8 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
 }
 
 bm_status run_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
-                    const std::vector<std::pair<int, int>>& groups, hipStream_t st) {
-    const std::string key = signature(h, frames, n);
+                    const std::vector<std::pair<int, int>>& groups, int mode, hipStream_t st) {
+    const std::string key = signature(h, frames, n, mode);
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         if ((int)h->graphs.size() >= kMaxGraphs) {
@@ -574,7 +667,7 @@ bm_status run_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
             h->graphs.erase(victim);
         }
         GraphEntry ge;
-        bm_status r = build_graph(h, frames, n, groups, ge);
+        bm_status r = build_graph(h, frames, n, groups, mode, st, ge);
         if (r != BM_OK) {
             destroy_graph(ge);
             return r;
@@ -610,6 +703,288 @@ void load_tune_cache(bosmusic_s* h) {
     std::fclose(fp);
 }
 
+
+// bfloat16 of an FP32 value, round to nearest even.
+uint16_t to_bf16_bits(float f) {
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+bm_status bosmusic_surrogate_load(bosmusic_t h, const float* params, int64_t n) {
+    if (!h) return BM_E_INVALID_ARG;
+    try {
+        h->err.clear();
+        if (!params || n != bm::kMlpParams) return fail(h, BM_E_INVALID_ARG, "need %d parameters", bm::kMlpParams);
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(params[i])) return fail(h, BM_E_INVALID_ARG, "parameter %lld is not finite", (long long)i);
+        const int H = bm::kMlpHidden, I = bm::kMlpIn;
+        const float* W1 = params;
+        const float* W2 = params + I * H + H;
+        const float* W3 = W2 + H * H + H;
+        std::vector<uint16_t> w((size_t)H * I + 2 * (size_t)H * H + 16 * (size_t)H, 0);
+        for (int i = 0; i < I; ++i)
+            for (int o = 0; o < H; ++o) w[(size_t)o * I + i] = to_bf16_bits(W1[i * H + o]);
+        uint16_t* w2t = w.data() + (size_t)H * I;
+        for (int i = 0; i < H; ++i)
+            for (int o = 0; o < H; ++o) w2t[(size_t)o * H + i] = to_bf16_bits(W2[i * H + o]);
+        uint16_t* w3t = w2t + (size_t)H * H;
+        for (int i = 0; i < H; ++i)
+            for (int o = 0; o < bm::kMlpOut; ++o) w3t[(size_t)o * H + i] = to_bf16_bits(W3[i * bm::kMlpOut + o]);
+        uint16_t* w2 = w3t + 16 * (size_t)H;
+        for (int i = 0; i < H * H; ++i) w2[i] = to_bf16_bits(W2[i]);
+        DeviceGuard dg(h->device);
+        bm_status r;
+        if ((r = check(h, hipDeviceSynchronize(), "sync")) ||
+            (r = check(h, hipMemcpy(h->sur_master, params, n * sizeof(float), hipMemcpyHostToDevice), "load")) ||
+            (r = check(h, hipMemcpy(h->sur_w, w.data(), w.size() * 2, hipMemcpyHostToDevice), "load")) ||
+            (r = check(h, hipMemset(h->adam_m, 0, n * sizeof(float)), "load")) ||
+            (r = check(h, hipMemset(h->adam_v, 0, n * sizeof(float)), "load")))
+            return r;
+        h->adam_t = 0;
+        h->sur_loaded = true;
+        return BM_OK;
+    } catch (...) {
+        return fail(h, BM_E_NOMEM, "host exception in surrogate_load");
+    }
+}
+
+bm_status bosmusic_surrogate_save(bosmusic_t h, float* params, int64_t n) {
+    if (!h) return BM_E_INVALID_ARG;
+    if (!params || n != bm::kMlpParams) return fail(h, BM_E_INVALID_ARG, "need %d parameters", bm::kMlpParams);
+    DeviceGuard dg(h->device);
+    bm_status r;
+    if ((r = check(h, hipDeviceSynchronize(), "sync"))) return r;
+    return check(h, hipMemcpy(params, h->sur_master, n * sizeof(float), hipMemcpyDeviceToHost), "save");
+}
+
+bm_status bosmusic_surrogate_config(bosmusic_t h, float tau, int32_t predictor) {
+    if (!h) return BM_E_INVALID_ARG;
+    if (!(tau > 0.f && tau <= 1.f) || (predictor != 0 && predictor != 1))
+        return fail(h, BM_E_INVALID_ARG, "tau in (0, 1], predictor 0 or 1");
+    h->sur_tau = tau;
+    h->sur_predictor = predictor;
+    return BM_OK;
+}
+
+bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t count, uint64_t seed, float* X,
+                                     float* T, float* omega, void* stream) {
+    if (!h) return BM_E_INVALID_ARG;
+    try {
+        h->err.clear();
+        if (!X || !T || count < 0 || first_line < 0 || first_line + count > ((int64_t)1 << 32))
+            return fail(h, BM_E_INVALID_ARG, "X/T/count/first_line");
+        if (count == 0) return BM_OK;
+        DeviceGuard dg(h->device);
+        hipStream_t st = (hipStream_t)stream;
+        bm_status r;
+        constexpr int kLen = 128, kLabelL = 8, kLabelN = 32, kPerJob = 65536;
+        constexpr int64_t kChunk = (int64_t)1 << 18;
+        constexpr int kMaxJobs = (int)(kChunk / kPerJob);
+        const int64_t chunk = std::min(count, kChunk);
+        size_t off = 0;
+        auto carve = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
+        const size_t o_lines = carve((size_t)chunk * kLen * sizeof(float));
+        const size_t o_gamma = carve((size_t)chunk * kLen * sizeof(float2));
+        const size_t o_labels = carve((size_t)chunk * sizeof(float));
+        const size_t o_list = carve((size_t)chunk * sizeof(int2));
+        const size_t o_count = carve(sizeof(int));
+        const size_t o_fj = carve(sizeof(bm::FftJob));
+        const size_t o_fp = carve(2 * sizeof(int));
+        const size_t o_rj = carve(kMaxJobs * sizeof(bm::RmJob));
+        const size_t o_rp = carve((kMaxJobs + 1) * sizeof(int));
+        if (off > h->ds_bytes) {
+            if ((r = check(h, hipStreamSynchronize(st), "sync"))) return r;
+            (void)hipFree(h->ds);
+            h->ds = nullptr;
+            h->ds_bytes = 0;
+            if (hipMalloc(&h->ds, off) != hipSuccess) return fail(h, BM_E_NOMEM, "dataset buffers (%zu bytes)", off);
+            h->ds_bytes = off;
+        }
+        bm::FftJob fj{};
+        if (!plan_fft(kLen, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "line length");
+        if ((r = get_twiddles(h, kLen, &fj.tw))) return r;
+        float* lines = (float*)(h->ds + o_lines);
+        float2* gamma = (float2*)(h->ds + o_gamma);
+        for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+            const int n = (int)std::min(chunk, count - c0);
+            float* labels = omega ? omega + c0 : (float*)(h->ds + o_labels);
+            fj.src = lines;
+            fj.src_ls = kLen;
+            fj.dst = gamma;
+            fj.elem = BM_F32;
+            fj.nlines = n;
+            const int fprefix[2] = {0, n};
+            std::vector<bm::RmJob> rj;
+            std::vector<int> rp(1, 0);
+            for (int j = 0; j * kPerJob < n; ++j) {
+                bm::RmJob J{};
+                J.gamma = gamma + (int64_t)j * kPerJob * kLen;
+                J.gamma_ls = kLen;
+                J.out = labels + (int64_t)j * kPerJob;
+                J.out_es = 0;
+                J.out_ls = 1;
+                J.len = kLen;
+                J.nlines = std::min(kPerJob, n - j * kPerJob);
+                J.N = kLabelN;
+                J.bpl = 1;
+                rj.push_back(J);
+                rp.push_back(rp.back() + J.nlines);
+            }
+            // the tables are read by this chunk's kernels: finish the previous chunk first
+            if ((r = check(h, hipStreamSynchronize(st), "sync")) ||
+                (r = check(h, hipMemcpy(h->ds + o_fj, &fj, sizeof(fj), hipMemcpyHostToDevice), "tables")) ||
+                (r = check(h, hipMemcpy(h->ds + o_fp, fprefix, sizeof(fprefix), hipMemcpyHostToDevice), "tables")) ||
+                (r = check(h, hipMemcpy(h->ds + o_rj, rj.data(), rj.size() * sizeof(bm::RmJob), hipMemcpyHostToDevice),
+                           "tables")) ||
+                (r = check(h, hipMemcpy(h->ds + o_rp, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice),
+                           "tables")))
+                return r;
+            bm::FftBatch fb;
+            fb.jobs = (const bm::FftJob*)(h->ds + o_fj);
+            fb.prefix = (const int*)(h->ds + o_fp);
+            fb.njobs = 1;
+            fb.total = n;
+            fb.max_n = kLen;
+            bm::RmBatch rb;
+            rb.jobs = (const bm::RmJob*)(h->ds + o_rj);
+            rb.prefix = (const int*)(h->ds + o_rp);
+            rb.njobs = (int)rj.size();
+            rb.total = n;
+            rb.jacobi = (h->options & BM_OPT_JACOBI) ? 1 : 0;
+            rb.stats = nullptr;
+            rb.tmpl = h->tmpl[kLabelL];
+            int2* list = (int2*)(h->ds + o_list);
+            int* dcount = (int*)(h->ds + o_count);
+            const int grid = std::max(1, std::min(8 * h->cu_count, (n + bm::kGatherBlock - 1) / bm::kGatherBlock));
+            if ((r = check(h, bm::launch_gen_lines(lines, first_line + c0, n, seed, st), "training lines")) ||
+                (r = check(h, bm::launch_analytic(fb, st), "analytic")) ||
+                (r = check(h, bm::launch_label_entries(list, n, st), "label windows")) ||
+                (r = check(h, bm::launch_fill_int(dcount, 1, n, st), "label count")) ||
+                (r = check(h, bm::launch_rootmusic_gather(kLabelL, rb, list, dcount, grid, st), "labels")) ||
+                (r = check(h, bm::launch_train_features(gamma, n, labels, X + c0 * bm::kMlpIn, T + c0 * bm::kMlpOut,
+                                                        st),
+                           "features")))
+                return r;
+        }
+        return check(h, hipStreamSynchronize(st), "dataset");
+    } catch (...) {
+        return fail(h, BM_E_NOMEM, "host exception in surrogate_dataset");
+    }
+}
+
+namespace {
+
+bm_status ensure_partials(bosmusic_s* h, int blocks, hipStream_t st) {
+    if (blocks <= h->part_blocks) return BM_OK;
+    bm_status r;
+    if ((r = check(h, hipStreamSynchronize(st), "sync"))) return r;
+    (void)hipFree(h->part);
+    h->part = nullptr;
+    h->part_blocks = 0;
+    if (hipMalloc(&h->part, (size_t)blocks * bm::mlp_partial_stride() * sizeof(float)) != hipSuccess)
+        return fail(h, BM_E_NOMEM, "gradient partials");
+    h->part_blocks = blocks;
+    return BM_OK;
+}
+
+const __bf16* w2_plain(const bosmusic_s* h) {
+    return h->sur_w + bm::kMlpHidden * bm::kMlpIn + bm::kMlpHidden * bm::kMlpHidden + 16 * bm::kMlpHidden;
+}
+
+// One Adam step from the partials of `blocks` blocks (or from grad when part is null).
+bm_status adam_step(bosmusic_s* h, const float* part, int blocks, float* grad, float* loss, float lr, hipStream_t st) {
+    ++h->adam_t;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)h->adam_t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)h->adam_t)));
+    return check(h, bm::launch_mlp_reduce_adam(part, blocks, h->sur_master, h->adam_m, h->adam_v, grad, loss, h->sur_w,
+                                               1, lr, c1, c2, st),
+                 "adam");
+}
+
+}  // namespace
+
+bm_status bosmusic_surrogate_grad(bosmusic_t h, const float* X, const float* T, int32_t M, float* grad, float* loss,
+                                  void* stream) {
+    if (!h) return BM_E_INVALID_ARG;
+    if (!X || !T || !grad || M <= 0 || M % 64) return fail(h, BM_E_INVALID_ARG, "X/T/grad, M a positive multiple of 64");
+    DeviceGuard dg(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int blocks = bm::mlp_train_blocks(M);
+    bm_status r;
+    if ((r = ensure_partials(h, blocks, st)) ||
+        (r = check(h, bm::launch_mlp_train(mlp_weights(h), w2_plain(h), X, T, M, h->part, blocks, st), "mlp train")))
+        return r;
+    return check(h, bm::launch_mlp_reduce_adam(h->part, blocks, nullptr, nullptr, nullptr, grad, loss, nullptr, 0, 0.f,
+                                               0.f, 0.f, st),
+                 "gradient sum");
+}
+
+bm_status bosmusic_surrogate_step(bosmusic_t h, const float* grad, float lr, void* stream) {
+    if (!h) return BM_E_INVALID_ARG;
+    if (!grad || !(lr > 0.f)) return fail(h, BM_E_INVALID_ARG, "grad/lr");
+    DeviceGuard dg(h->device);
+    return adam_step(h, nullptr, 0, const_cast<float*>(grad), nullptr, lr, (hipStream_t)stream);
+}
+
+bm_status bosmusic_surrogate_train(bosmusic_t h, const float* X, const float* T, int64_t M, int32_t batch,
+                                   int32_t steps, float lr, float* losses, void* stream) {
+    if (!h) return BM_E_INVALID_ARG;
+    try {
+        h->err.clear();
+        if (!X || !T || batch <= 0 || batch % 64 || M < batch || steps < 0 || !(lr > 0.f))
+            return fail(h, BM_E_INVALID_ARG, "X/T, batch a positive multiple of 64 and <= M, steps >= 0, lr > 0");
+        DeviceGuard dg(h->device);
+        hipStream_t st = (hipStream_t)stream;
+        const int blocks = bm::mlp_train_blocks(batch);
+        bm_status r;
+        if ((r = ensure_partials(h, blocks, st))) return r;
+        if (losses && steps > h->losses_cap) {
+            if ((r = check(h, hipStreamSynchronize(st), "sync"))) return r;
+            (void)hipFree(h->losses);
+            h->losses = nullptr;
+            h->losses_cap = 0;
+            if (hipMalloc(&h->losses, (size_t)steps * sizeof(float)) != hipSuccess)
+                return fail(h, BM_E_NOMEM, "loss buffer");
+            h->losses_cap = steps;
+        }
+        const int64_t nb = M / batch;   // whole batches per pass over the data
+        for (int s = 0; s < steps; ++s) {
+            const int64_t b0 = (int64_t)(s % nb) * batch;
+            if ((r = check(h, bm::launch_mlp_train(mlp_weights(h), w2_plain(h), X + b0 * bm::kMlpIn,
+                                                   T + b0 * bm::kMlpOut, batch, h->part, blocks, st),
+                           "mlp train")) ||
+                (r = adam_step(h, h->part, blocks, nullptr, losses ? h->losses + s : nullptr, lr, st)))
+                return r;
+        }
+        if (losses && steps > 0) {
+            if ((r = check(h, hipMemcpyAsync(losses, h->losses, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost, st),
+                           "losses")))
+                return r;
+            return check(h, hipStreamSynchronize(st), "train");
+        }
+        return BM_OK;
+    } catch (...) {
+        return fail(h, BM_E_NOMEM, "host exception in surrogate_train");
+    }
+}
+
+bm_status bosmusic_surrogate_forward(bosmusic_t h, const float* X, float* Y, int32_t M, void* stream) {
+    if (!h) return BM_E_INVALID_ARG;
+    if (!X || !Y || M < 0) return fail(h, BM_E_INVALID_ARG, "X/Y/M");
+    DeviceGuard dg(h->device);
+    return check(h, bm::launch_mlp_forward(mlp_weights(h), X, Y, M, (hipStream_t)stream), "mlp forward");
+}
+
+}  // extern "C"
+
+namespace {
+
 void release(bosmusic_s* h) {
     if (!h) return;
     for (auto& kv : h->graphs) destroy_graph(kv.second);
@@ -618,6 +993,15 @@ void release(bosmusic_s* h) {
     (void)hipFree(h->anchor);
     (void)hipFree(h->stats);
     (void)hipFree(h->djobs);
+    (void)hipFree(h->sur_master);
+    (void)hipFree(h->sur_w);
+    (void)hipFree(h->rejects);
+    (void)hipFree(h->reject_count);
+    (void)hipFree(h->adam_m);
+    (void)hipFree(h->adam_v);
+    (void)hipFree(h->part);
+    (void)hipFree(h->losses);
+    (void)hipFree(h->ds);
     if (h->pin) (void)hipHostFree(h->pin);
     for (auto& kv : h->twiddles) (void)hipFree(kv.second);
     for (auto* v : {&h->ev_free, &h->ev_pending})
@@ -690,12 +1074,12 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         h->ws_bytes = (size_t)ws_px * 20 + (size_t)3 * 256 * 1024;
         if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess ||
             hipMalloc(&h->anchor, (size_t)cfg->max_height * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->stats, 4 * bm::kStatSlots * sizeof(unsigned long long)) != hipSuccess) {
+            hipMalloc(&h->stats, bm::kStatFields * bm::kStatSlots * sizeof(unsigned long long)) != hipSuccess) {
             release(h);
             (void)hipGetLastError();
             return fail(nullptr, BM_E_NOMEM, "workspace for %lld pixels", (long long)ws_px);
         }
-        bool ok = hipMemset(h->stats, 0, 4 * bm::kStatSlots * sizeof(unsigned long long)) == hipSuccess &&
+        bool ok = hipMemset(h->stats, 0, bm::kStatFields * bm::kStatSlots * sizeof(unsigned long long)) == hipSuccess &&
                   bm::analytic_set_attributes() == hipSuccess && bm::integrate_set_attributes() == hipSuccess &&
                   hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) == hipSuccess;
@@ -705,6 +1089,19 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         if (!ok) {
             release(h);
             return fail(nullptr, BM_E_DEVICE, "device set-up failed");
+        }
+        const size_t nw = (size_t)bm::kMlpHidden * bm::kMlpIn + 2 * (size_t)bm::kMlpHidden * bm::kMlpHidden +
+                          16 * (size_t)bm::kMlpHidden;
+        if (hipMalloc(&h->sur_master, bm::kMlpParams * sizeof(float)) != hipSuccess ||
+            hipMalloc(&h->adam_m, bm::kMlpParams * sizeof(float)) != hipSuccess ||
+            hipMalloc(&h->adam_v, bm::kMlpParams * sizeof(float)) != hipSuccess ||
+            hipMemset(h->adam_m, 0, bm::kMlpParams * sizeof(float)) != hipSuccess ||
+            hipMemset(h->adam_v, 0, bm::kMlpParams * sizeof(float)) != hipSuccess ||
+            hipMalloc(&h->sur_w, nw * sizeof(__bf16)) != hipSuccess ||
+            hipMemset(h->sur_master, 0, bm::kMlpParams * sizeof(float)) != hipSuccess ||
+            hipMemset(h->sur_w, 0, nw * sizeof(__bf16)) != hipSuccess) {
+            release(h);
+            return fail(nullptr, BM_E_NOMEM, "surrogate parameters");
         }
         for (int L = 2; L <= bm::kMaxL; ++L) make_template(L, h->tmpl[L]);
         if (cfg->tune_cache) h->tune_path = cfg->tune_cache;
@@ -734,11 +1131,14 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
     try {
         h->err.clear();
         if (n_frames < 0 || (n_frames > 0 && !frames)) return fail(h, BM_E_INVALID_ARG, "frames/n_frames");
-        if (mode == BM_SURROGATE) return fail(h, BM_E_UNSUPPORTED, "surrogate mode is not built");
-        if (mode != BM_PLAIN) return fail(h, BM_E_INVALID_ARG, "mode %d", mode);
+        if (mode != BM_PLAIN && mode != BM_SURROGATE) return fail(h, BM_E_INVALID_ARG, "mode %d", mode);
+        if (mode == BM_SURROGATE && !h->sur_loaded && h->sur_predictor == 0)
+            return fail(h, BM_E_UNSUPPORTED, "surrogate mode needs loaded parameters");
         for (int i = 0; i < n_frames; ++i) {
             bm_status st = validate_frame(h, frames[i], i);
             if (st != BM_OK) return st;
+            if (mode == BM_SURROGATE && frames[i].N < 16)
+                return fail(h, BM_E_UNSUPPORTED, "frame %d: surrogate mode needs N >= 16", i);
         }
         if (n_frames == 0) return BM_OK;
         DeviceGuard dg(h->device);
@@ -759,10 +1159,10 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
         }
         groups.push_back({g0, n_frames});
         const bool graph = (h->options & BM_OPT_GRAPH) && !(h->options & BM_OPT_TIMING);
-        if (graph) return run_graph(h, frames, n_frames, groups, s);
+        if (graph) return run_graph(h, frames, n_frames, groups, mode, s);
         for (auto& g : groups) {
             GroupPlan gp;
-            bm_status st = plan_group(h, frames, g.first, g.second, gp);
+            bm_status st = plan_group(h, frames, g.first, g.second, mode, gp);
             if (st == BM_OK) st = run_group_eager(h, gp, s);
             if (st != BM_OK) return st;
         }
@@ -905,13 +1305,13 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
     try {
         DeviceGuard dg(h->device);
         hipStream_t s = (hipStream_t)stream;
-        unsigned long long slots[4 * bm::kStatSlots];
-        unsigned long long v[4] = {0, 0, 0, 0};
+        unsigned long long slots[bm::kStatFields * bm::kStatSlots];
+        unsigned long long v[bm::kStatFields] = {};
         bm_status st;
         if ((st = check(h, hipStreamSynchronize(s), "sync"))) return st;
         if ((st = check(h, hipMemcpy(slots, h->stats, sizeof(slots), hipMemcpyDeviceToHost), "stats copy")))
             return st;
-        for (int i = 0; i < 4 * bm::kStatSlots; ++i) v[i % 4] += slots[i];
+        for (int i = 0; i < bm::kStatFields * bm::kStatSlots; ++i) v[i % bm::kStatFields] += slots[i];
         if (reset && (st = check(h, hipMemset(h->stats, 0, sizeof(slots)), "stats reset"))) return st;
         for (auto& e : h->ev_pending) {
             float ms = 0.f;
@@ -925,6 +1325,8 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
         out->eig_iters = v[1];
         out->root_iters = v[2];
         out->polish_fail = v[3];
+        out->sur_accepted = v[4];
+        out->sur_rejected = v[5];
         out->rm_launches = h->rm_launches;
         out->rm_time_ns = h->rm_time_ns;
         if (reset) h->rm_launches = h->rm_time_ns = 0;

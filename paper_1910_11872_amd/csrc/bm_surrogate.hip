@@ -1,0 +1,740 @@
+// Learned surrogate of the per-window frequency estimate (an addition to the
+// paper's method), with the paper's root-MUSIC as the check and the fallback.
+//
+// surrogate_kernel: one block per work item of the plain kernel's grid.
+//   1. stage the analytic signal of BLOCK + N - 1 samples in LDS;
+//   2. features of every window: 16 central samples, de-rotated by the phase
+//      of the central sample, divided by the window's RMS magnitude, as
+//      bfloat16 [Re(16), Im(16)];
+//   3. MLP 32 -> GELU 64 -> GELU 64 -> 2 on the matrix cores: every GEMM is
+//      a set of v_mfma_f32_16x16x32_bf16 tiles with FP32 accumulation, in
+//      transposed form (W^T X^T) so that the bfloat16 weights are the A
+//      operand and each layer's output tile is the next layer's B operand
+//      after one LDS round trip; omega_hat = atan2 of the two outputs;
+//   4. lag sums and covariance as in the plain kernel, the real symmetric
+//      T = Q^H R_fb Q, its top eigenvector by power iteration seeded with the
+//      steering vector of omega_hat, the MUSIC null spectrum, and Newton
+//      iterations on the quadratic factor of the root-MUSIC polynomial (paper
+//      Eq. 12) started from the double root e^{j omega_hat} (FP32, then FP64);
+//   5. accept when the factor converged, its roots sit within 0.05 of the
+//      unit circle and the null spectrum at the refined frequency is below
+//      tau: omega = arg(z1 + z2) as in the plain path; otherwise the window
+//      goes to the reject list, which the plain gather kernel finishes.
+#include "bm_window.h"
+
+#include <algorithm>
+
+namespace bm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSurBlock = 256;
+constexpr int kPowerSteps = 6;
+constexpr int kRefine32 = 8;
+constexpr int kRefine64 = 2;
+constexpr float kPairBand = 0.05f;
+
+// C(16 x 16) += A(16 x 32) B(32 x 16) on one wave.  A(i, k) = a[i*lda + k],
+// B(k, j) = b[j*ldb + k]; both 16-byte aligned with k contiguous.  Lane l
+// supplies row l%16 of A and column l%16 of B for k = 8(l/16) .. 8(l/16)+7;
+// the result holds column l%16, rows 4(l/16) .. 4(l/16)+3.
+__device__ __forceinline__ floatx4 mfma_tile(const __bf16* a, int lda, const __bf16* b, int ldb, floatx4 c) {
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, kg = (l >> 4) * 8;
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + i * lda + kg);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + i * ldb + kg);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+
+struct alignas(16) MlpSmem {
+    __bf16 w1t[kMlpHidden * kMlpIn];
+    __bf16 w2t[kMlpHidden * kMlpHidden];
+    __bf16 w3t[16 * kMlpHidden];
+    float b1[kMlpHidden], b2[kMlpHidden], b3[4];
+};
+
+__device__ void load_weights(const MlpWeights& w, MlpSmem& s, int nthreads) {
+    for (int i = threadIdx.x; i < kMlpHidden * kMlpIn; i += nthreads) s.w1t[i] = w.w1t[i];
+    for (int i = threadIdx.x; i < kMlpHidden * kMlpHidden; i += nthreads) s.w2t[i] = w.w2t[i];
+    for (int i = threadIdx.x; i < 16 * kMlpHidden; i += nthreads) s.w3t[i] = w.w3t[i];
+    for (int i = threadIdx.x; i < kMlpHidden; i += nthreads) {
+        s.b1[i] = w.b1[i];
+        s.b2[i] = w.b2[i];
+    }
+    if (threadIdx.x < 2) s.b3[threadIdx.x] = w.b3[threadIdx.x];
+}
+
+// MLP on one tile of 16 rows of x ([row][32] bf16); h1, h2 are this wave's
+// [16][64] bf16 scratch tiles.  Lanes 0..15 return (y0, y1) of row l.
+__device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __bf16* h1, __bf16* h2) {
+    const int l = threadIdx.x & 63;
+    const int col = l & 15, rq = (l >> 4) * 4;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        floatx4 c = {0.f, 0.f, 0.f, 0.f};
+        c = mfma_tile(s.w1t + 16 * rb * kMlpIn, kMlpIn, x, kMlpIn, c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int hid = 16 * rb + rq + q;
+            h1[col * kMlpHidden + hid] = (__bf16)gelu(c[q] + s.b1[hid]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            c = mfma_tile(s.w2t + 16 * rb * kMlpHidden + 32 * kb, kMlpHidden, h1 + 32 * kb, kMlpHidden, c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int hid = 16 * rb + rq + q;
+            h2[col * kMlpHidden + hid] = (__bf16)gelu(c[q] + s.b2[hid]);
+        }
+    }
+    __syncthreads();
+    floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) c = mfma_tile(s.w3t + 32 * kb, kMlpHidden, h2 + 32 * kb, kMlpHidden, c);
+    return make_float2(c[0] + s.b3[0], c[1] + s.b3[1]);
+}
+
+// Real form of the unit steering vector of frequency w under the unitary
+// transform of build_T: v0 = Q^H a(w) e^{-j w (L-1)/2} / sqrt(L).
+template <int L>
+__device__ __forceinline__ void steering_real(float w, float (&v0)[L]) {
+    constexpr int m = L / 2;
+    constexpr int o = L - m;
+    const float sc = 1.41421356237309515f * rsqrtf((float)L);
+#pragma unroll
+    for (int a = 0; a < m; ++a) {
+        float sn, cs;
+        sincosf(w * ((float)a - 0.5f * (float)(L - 1)), &sn, &cs);
+        v0[a] = sc * cs;
+        v0[o + a] = sc * sn;
+    }
+    if (L & 1) v0[m] = rsqrtf((float)L);
+}
+
+// Refinement of a predicted frequency; true when the estimate is accepted.
+template <int L>
+__device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, float& omega) {
+    constexpr int n = 2 * L - 2;
+    Sym<L> T;
+    if (!normalised_T<L>(R, T)) return false;
+    float v[L];
+    steering_real<L>(what, v);
+    for (int it = 0; it < kPowerSteps; ++it) {
+        float y[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < L; ++j) acc = fmaf(T.at(i, j), v[j], acc);
+            y[i] = acc;
+        }
+        float n2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < L; ++i) n2 = fmaf(y[i], y[i], n2);
+        const float in = frsq(n2);
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = y[i] * in;
+    }
+    float ur[L], ui[L];
+    signal_vector<L>(v, ur, ui);
+    float ar[n + 1], ai[n + 1];
+    poly_coeffs<L>(ur, ui, ar, ai);
+    // the quadratic factor of the double root e^{j what}: z^2 - r z - s
+    float sw, cw;
+    sincosf(what, &sw, &cw);
+    float r32 = 2.f * cw, i32 = 2.f * sw, sr32 = -(cw * cw - sw * sw), si32 = -2.f * cw * sw, last32 = 0.f;
+    if (!bairstow<float, n>(ar, ai, r32, i32, sr32, si32, kRefine32, last32)) return false;
+    double rr = r32, ri = i32, s_r = sr32, s_i = si32, last = 0.0;
+    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefine64, last)) return false;
+    if (!(last <= 1e-6 * (fabs(rr) + fabs(ri)))) return false;
+    // roots of the factor: (r +- sqrt(r^2 + 4 s)) / 2
+    const float pr = (float)rr, pi = (float)ri;
+    const float dr = pr * pr - pi * pi + 4.f * (float)s_r, di = 2.f * pr * pi + 4.f * (float)s_i;
+    const float md = fsqrt(dr * dr + di * di);
+    const float qr = fsqrt(fmaxf(0.f, 0.5f * (md + dr)));
+    const float qi = copysignf(fsqrt(fmaxf(0.f, 0.5f * (md - dr))), di);
+    const float z1r = 0.5f * (pr + qr), z1i = 0.5f * (pi + qi);
+    const float z2r = 0.5f * (pr - qr), z2i = 0.5f * (pi - qi);
+    const float d1 = fabsf(fsqrt(z1r * z1r + z1i * z1i) - 1.f);
+    const float d2 = fabsf(fsqrt(z2r * z2r + z2i * z2i) - 1.f);
+    if (!(fminf(d1, d2) < kPairBand)) return false;
+    const float w = atan2f(pi, pr);
+    float v0[L];
+    steering_real<L>(w, v0);
+    float dot = 0.f;
+#pragma unroll
+    for (int i = 0; i < L; ++i) dot = fmaf(v[i], v0[i], dot);
+    if (!(1.f - dot * dot < tau)) return false;
+    omega = w;
+    return finitef(w);
+}
+
+template <int L>
+__global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
+    constexpr int BLOCK = kSurBlock;
+    constexpr int WPB = BLOCK - (L - 1);
+    __shared__ MlpSmem sm;
+    __shared__ float2 sg[BLOCK + kMaxN];
+    __shared__ float what[BLOCK];
+    // x [BLOCK][32] + per-wave h1, h2 [16][64]; later reused for the lag sums
+    constexpr int kXBytes = BLOCK * kMlpIn * 2, kHBytes = 4 * 2 * 16 * kMlpHidden * 2;
+    constexpr int kSBytes = L * BLOCK * 8;
+    constexpr int kUBytes = (kXBytes + kHBytes) > kSBytes ? (kXBytes + kHBytes) : kSBytes;
+    __shared__ alignas(16) unsigned char ubuf[kUBytes];
+    __bf16* xs = reinterpret_cast<__bf16*>(ubuf);
+    float2 (*sS)[BLOCK] = reinterpret_cast<float2 (*)[BLOCK]>(ubuf);
+    const int t = threadIdx.x, wv = t >> 6;
+    __bf16* h1 = reinterpret_cast<__bf16*>(ubuf + kXBytes) + wv * 2 * 16 * kMlpHidden;
+    __bf16* h2 = h1 + 16 * kMlpHidden;
+
+    load_weights(S.w, sm, BLOCK);
+    const RmBatch& B = S.rm;
+    const int j = find_job(B.prefix, B.njobs, blockIdx.x);
+    const RmJob J = B.jobs[j];
+    const int local = blockIdx.x - B.prefix[j];
+    const int line = local / J.bpl;
+    const int p0 = (local - line * J.bpl) * WPB;
+    const int N = J.N, half = N >> 1, K = N - L + 1, len = J.len;
+    const float2* g = J.gamma + (int64_t)line * J.gamma_ls;
+    const int base = p0 - half;
+    for (int i = t; i < BLOCK + N - 1; i += BLOCK) {
+        const int q = base + i;
+        sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int p = p0 + t;
+    const bool inside_line = (t < WPB) && (p < len);
+    const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
+
+    // ---- features and the MLP ------------------------------------------
+    if (S.predictor == 0) {
+        {
+            const float2* w = sg + t;
+            float e = 0.f;
+            for (int k = 0; k < N; ++k) e = fmaf(w[k].x, w[k].x, fmaf(w[k].y, w[k].y, e));
+            const float2 gc = w[half];
+            const float mc = fsqrt(gc.x * gc.x + gc.y * gc.y);
+            const bool ok = valid && mc > 0.f && e > 0.f;
+            const float sc = ok ? frcp(mc) * rsqrtf(e / (float)N) : 0.f;
+            const float rc = gc.x * sc, rs = -gc.y * sc;           // conj(gc)/|gc|/rms
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float2 v = w[half - 8 + k];
+                xs[t * kMlpIn + k] = (__bf16)(v.x * rc - v.y * rs);
+                xs[t * kMlpIn + 16 + k] = (__bf16)(v.x * rs + v.y * rc);
+            }
+        }
+        __syncthreads();
+        for (int tile = wv; tile < BLOCK / 16; tile += BLOCK / 64) {
+            const float2 y = mlp_tile(sm, xs + tile * 16 * kMlpIn, h1, h2);
+            if ((t & 63) < 16) what[tile * 16 + (t & 15)] = atan2f(y.y, y.x);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // ---- lag sums (the MLP scratch is dead now) ---------------------------
+    {
+        float sr[L], si[L];
+#pragma unroll
+        for (int d = 0; d < L; ++d) { sr[d] = 0.f; si[d] = 0.f; }
+        float2 win[L];
+#pragma unroll
+        for (int d = 0; d < L - 1; ++d) win[d + 1] = sg[t + d];
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int d = 0; d < L - 1; ++d) win[d] = win[d + 1];
+            win[L - 1] = sg[t + k + L - 1];
+#pragma unroll
+            for (int d = 0; d < L; ++d) {
+                sr[d] = fmaf(win[0].x, win[d].x, fmaf(win[0].y, win[d].y, sr[d]));
+                si[d] = fmaf(win[0].y, win[d].x, fmaf(-win[0].x, win[d].y, si[d]));
+            }
+        }
+        __syncthreads();   // every lane has read the features before they are overwritten
+#pragma unroll
+        for (int d = 0; d < L; ++d) sS[d][t] = make_float2(sr[d], si[d]);
+    }
+    __syncthreads();
+
+    float omega = __builtin_nanf("");
+    unsigned flag = 0;
+    bool reject = false;
+    int acc = 0;
+    if (valid) {
+        Cov<L> R;
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int jj = i; jj < L; ++jj) {
+                const float2 v = sS[jj - i][t + i];
+                R.re[i][jj] = v.x;
+                R.im[i][jj] = (i == jj) ? 0.f : v.y;
+            }
+        float wh;
+        if (S.predictor == 0) {
+            wh = what[t];
+        } else {
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int i = 0; i + 1 < L; ++i) { sr += R.re[i][i + 1]; si -= R.im[i][i + 1]; }
+            wh = atan2f(si, sr);
+        }
+        if (refine<L>(R, wh, S.tau, omega)) acc = 1;
+        else reject = true;
+    } else {
+        flag |= BM_FLAG_UNDEFINED;
+    }
+    // compact the rejected windows: one atomic per wave
+    const unsigned long long mask = __ballot(reject);
+    int slot = 0;
+    if (mask) {
+        const int lane = t & 63;
+        const int leader = __ffsll((long long)mask) - 1;
+        int basei = 0;
+        if (lane == leader) basei = atomicAdd(S.reject_count, __popcll(mask));
+        basei = __shfl(basei, leader);
+        slot = basei + __popcll(mask & ((1ull << lane) - 1ull));
+    }
+    if (reject) S.rejects[slot] = make_int2(j, (int)(((unsigned)line << 16) | (unsigned)p));
+    else if (inside_line) store_omega(J, line, p, omega, flag);
+    if (B.stats) {
+        unsigned long long a0 = acc, a1 = reject ? 1 : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            a0 += __shfl_xor(a0, off);
+            a1 += __shfl_xor(a1, off);
+        }
+        if ((t & 63) == 0) {
+            unsigned long long* sl = B.stats + kStatFields * ((blockIdx.x * 4 + wv) % kStatSlots);
+            if (a0) atomicAdd(sl + 4, a0);
+            if (a1) atomicAdd(sl + 5, a1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void mlp_forward_kernel(MlpWeights w, const float* X, float* Y, int M) {
+    __shared__ MlpSmem sm;
+    __shared__ alignas(16) __bf16 xs[64 * kMlpIn];
+    __shared__ alignas(16) __bf16 hs[4][2][16 * kMlpHidden];
+    load_weights(w, sm, 256);
+    const int t = threadIdx.x, wv = t >> 6;
+    const int r0 = blockIdx.x * 64;
+    for (int i = t; i < 64 * kMlpIn; i += 256) {
+        const int r = r0 + i / kMlpIn;
+        xs[i] = (__bf16)(r < M ? X[(int64_t)r0 * kMlpIn + i] : 0.f);
+    }
+    __syncthreads();
+    const float2 y = mlp_tile(sm, xs + wv * 16 * kMlpIn, hs[wv][0], hs[wv][1]);
+    const int r = r0 + wv * 16 + (t & 15);
+    if ((t & 63) < 16 && r < M) {
+        Y[2 * (int64_t)r] = y.x;
+        Y[2 * (int64_t)r + 1] = y.y;
+    }
+}
+
+
+// ===========================================================================
+// Training: data generation, forward/backward on the matrix cores, Adam
+// ===========================================================================
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): words 0 and
+// 2 are multiplied by the round constants, the high halves are crossed with
+// words 1 and 3 and the key, and the key is bumped by the Weyl constants
+// between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ float u01(uint32_t u) { return ((float)u + 0.5f) * 2.3283064365386963e-10f; }
+
+// Training line id (first + blockIdx.x): 0.5 + 0.4 cos(w n + theta) + noise,
+// parameters from counter (id, 0, 0, 0), noise of samples 4b..4b+3 from
+// counter (id, b+1, 0, 0) by two Box-Muller pairs.  One block of 32 lanes per line.
+__global__ __launch_bounds__(32) void gen_lines_kernel(float* lines, long long first, unsigned long long seed) {
+    const uint32_t id = (uint32_t)(first + blockIdx.x);
+    const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint4 pr = philox4x32_10(make_uint4(id, 0u, 0u, 0u), key);
+    const float kTwoPi = 6.28318530717958648f;
+    const float w = kTwoPi / 16.f + u01(pr.x) * (kTwoPi / 4.f - kTwoPi / 16.f);
+    const float th = kTwoPi * u01(pr.y);
+    const float snr = 30.f * u01(pr.z);
+    const float sig = sqrtf(0.08f * exp10f(-0.1f * snr));
+    const int b = threadIdx.x;
+    const uint4 q = philox4x32_10(make_uint4(id, (uint32_t)b + 1u, 0u, 0u), key);
+    const float r0 = sqrtf(-2.f * logf(u01(q.x))), r1 = sqrtf(-2.f * logf(u01(q.z)));
+    float s0, c0, s1, c1;
+    sincosf(kTwoPi * u01(q.y), &s0, &c0);
+    sincosf(kTwoPi * u01(q.w), &s1, &c1);
+    const float z[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
+    float* out = lines + (int64_t)blockIdx.x * 128;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int n = 4 * b + i;
+        out[n] = 0.5f + 0.4f * cosf(w * (float)n + th) + sig * z[i];
+    }
+}
+
+// Entries {job, line << 16 | 64} of the label windows (centre of each line),
+// 65536 lines per job.
+__global__ void label_entries_kernel(int2* list, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) list[i] = make_int2(i >> 16, (int)(((unsigned)(i & 0xFFFF) << 16) | 64u));
+}
+
+// Features of the 32-sample window centred on sample 64 of each line, and the
+// target (cos w, sin w) of its label.
+__global__ void train_features_kernel(const float2* gamma, int count, const float* labels, float* X, float* T) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float2* w = gamma + (int64_t)i * 128 + 48;
+    float e = 0.f;
+    for (int k = 0; k < 32; ++k) e = fmaf(w[k].x, w[k].x, fmaf(w[k].y, w[k].y, e));
+    const float2 gc = w[16];
+    const float mc = sqrtf(gc.x * gc.x + gc.y * gc.y);
+    const float sc = (mc > 0.f && e > 0.f) ? 1.f / (mc * sqrtf(e / 32.f)) : 0.f;
+    const float rc = gc.x * sc, rs = -gc.y * sc;
+    float* x = X + (int64_t)i * kMlpIn;
+    for (int k = 0; k < 16; ++k) {
+        const float2 v = w[8 + k];
+        x[k] = v.x * rc - v.y * rs;
+        x[16 + k] = v.x * rs + v.y * rc;
+    }
+    float sw, cw;
+    sincosf(labels[i], &sw, &cw);
+    T[2 * (int64_t)i] = cw;
+    T[2 * (int64_t)i + 1] = sw;
+}
+
+constexpr int kTrainChunk = 64;     // samples per block iteration (4 waves x 16)
+// per-block partial layout: dW1^T [64][32], db1 [64], dW2^T [64][64], db2 [64], dW3^T [2][64], db3 [2], loss
+constexpr int kPartDW1 = 0, kPartDB1 = 2048, kPartDW2 = 2112, kPartDB2 = 6208, kPartDW3 = 6272, kPartDB3 = 6400,
+              kPartLoss = 6402, kPartStride = 6404;
+
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+}
+
+struct alignas(16) TrainSmem {
+    __bf16 w1t[64 * 32], w2t[64 * 64], w3t[16 * 64], w2[64 * 64];
+    float b1[64], b2[64], b3[4];
+    __bf16 x[64 * 32], xT[32 * 64];
+    __bf16 h1[64 * 64], h1T[64 * 64], h2[64 * 64], h2T[64 * 64];
+    __bf16 dz2[64 * 64], dz2T[64 * 64], dz1T[64 * 64];
+    __bf16 dyT[16 * 64];
+    float dy[64 * 2];
+    float red[4][2 * 64 + 2 + 1];
+};
+
+// Forward and backward of M samples (M a multiple of 64), gradients of the
+// mean squared error summed per block into `part` (kPartStride floats per block).
+__global__ __launch_bounds__(256) void mlp_train_kernel(MlpWeights w, const __bf16* w2, const float* X, const float* T,
+                                                         int M, float* part) {
+    __shared__ TrainSmem sm;
+    const int t = threadIdx.x, wv = t >> 6, l = t & 63, col = l & 15, rq = (l >> 4) * 4;
+    for (int i = t; i < 64 * 32; i += 256) { sm.w1t[i] = w.w1t[i]; }
+    for (int i = t; i < 64 * 64; i += 256) { sm.w2t[i] = w.w2t[i]; sm.w2[i] = w2[i]; }
+    for (int i = t; i < 16 * 64; i += 256) { sm.w3t[i] = w.w3t[i]; sm.dyT[i] = (__bf16)0.f; }
+    if (t < 64) { sm.b1[t] = w.b1[t]; sm.b2[t] = w.b2[t]; }
+    if (t < 2) sm.b3[t] = w.b3[t];
+    const float inv = 2.f / (float)M;
+    floatx4 acc[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) acc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float db1[16], db2[16], db3[2] = {0.f, 0.f}, lsum = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { db1[k] = 0.f; db2[k] = 0.f; }
+    __syncthreads();
+    const int r0 = wv * 16;     // this wave's rows in the chunk
+    for (int c0 = blockIdx.x * kTrainChunk; c0 < M; c0 += gridDim.x * kTrainChunk) {
+        for (int i = t; i < 64 * 32; i += 256) {
+            const __bf16 v = (__bf16)X[(int64_t)c0 * 32 + i];
+            sm.x[i] = v;
+            sm.xT[(i % 32) * 64 + i / 32] = v;
+        }
+        __syncthreads();
+        // ---- forward ----------------------------------------------------
+        float z1[4][4], z2[4][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            floatx4 c = {0.f, 0.f, 0.f, 0.f};
+            c = mfma_tile(sm.w1t + 16 * rb * 32, 32, sm.x + r0 * 32, 32, c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int hid = 16 * rb + rq + q, win = r0 + col;
+                z1[rb][q] = c[q] + sm.b1[hid];
+                const __bf16 hv = (__bf16)gelu(z1[rb][q]);
+                sm.h1[win * 64 + hid] = hv;
+                sm.h1T[hid * 64 + win] = hv;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                c = mfma_tile(sm.w2t + 16 * rb * 64 + 32 * kb, 64, sm.h1 + r0 * 64 + 32 * kb, 64, c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int hid = 16 * rb + rq + q, win = r0 + col;
+                z2[rb][q] = c[q] + sm.b2[hid];
+                const __bf16 hv = (__bf16)gelu(z2[rb][q]);
+                sm.h2[win * 64 + hid] = hv;
+                sm.h2T[hid * 64 + win] = hv;
+            }
+        }
+        __syncthreads();
+        {
+            floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                c = mfma_tile(sm.w3t + 32 * kb, 64, sm.h2 + r0 * 64 + 32 * kb, 64, c);
+            if (l < 16) {
+                const int win = r0 + l;
+                const int64_t gi = (int64_t)(c0 + win) * 2;
+                const float e0 = c[0] + sm.b3[0] - T[gi], e1 = c[1] + sm.b3[1] - T[gi + 1];
+                lsum += e0 * e0 + e1 * e1;
+                sm.dy[win * 2] = inv * e0;
+                sm.dy[win * 2 + 1] = inv * e1;
+                sm.dyT[0 * 64 + win] = (__bf16)(inv * e0);
+                sm.dyT[1 * 64 + win] = (__bf16)(inv * e1);
+                db3[0] += inv * e0;
+                db3[1] += inv * e1;
+            }
+        }
+        __syncthreads();
+        // ---- backward: dZ2 = (dY W3^T) * gelu'(Z2) on the vector units ---------
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int hid = 16 * rb + rq + q, win = r0 + col;
+                const float dh = sm.dy[win * 2] * (float)sm.w3t[hid] + sm.dy[win * 2 + 1] * (float)sm.w3t[64 + hid];
+                const float dz = dh * gelu_grad(z2[rb][q]);
+                db2[rb * 4 + q] += dz;
+                const __bf16 dv = (__bf16)dz;
+                sm.dz2[win * 64 + hid] = dv;
+                sm.dz2T[hid * 64 + win] = dv;
+            }
+        __syncthreads();
+        // dH1^T = W2 dZ2^T (A = W2 [in][out], k = out contiguous), dZ1 = dH1 * gelu'(Z1)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                c = mfma_tile(sm.w2 + 16 * rb * 64 + 32 * kb, 64, sm.dz2 + r0 * 64 + 32 * kb, 64, c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int hid = 16 * rb + rq + q, win = r0 + col;
+                const float dz = c[q] * gelu_grad(z1[rb][q]);
+                db1[rb * 4 + q] += dz;
+                sm.dz1T[hid * 64 + win] = (__bf16)dz;
+            }
+        }
+        __syncthreads();
+        // ---- weight gradients over the 64 samples: 28 tiles, 7 per wave -----
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int tile = wv + 4 * k;
+            const __bf16 *a, *b;
+            if (tile < 8) {            // dW1^T [64 out][32 in]
+                a = sm.dz1T + 16 * (tile >> 1) * 64;
+                b = sm.xT + 16 * (tile & 1) * 64;
+            } else if (tile < 24) {    // dW2^T [64 out][64 in]
+                a = sm.dz2T + 16 * ((tile - 8) >> 2) * 64;
+                b = sm.h1T + 16 * ((tile - 8) & 3) * 64;
+            } else {                   // dW3^T [16 (2) out][64 in]
+                a = sm.dyT;
+                b = sm.h2T + 16 * (tile - 24) * 64;
+            }
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) acc[k] = mfma_tile(a + 32 * kb, 64, b + 32 * kb, 64, acc[k]);
+        }
+        __syncthreads();
+    }
+    // ---- per-block partial sums ---------------------------------------------
+    float* P = part + (int64_t)blockIdx.x * kPartStride;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const int tile = wv + 4 * k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rq + q;     // within the 16-row tile
+            if (tile < 8) P[kPartDW1 + (16 * (tile >> 1) + row) * 32 + 16 * (tile & 1) + col] = acc[k][q];
+            else if (tile < 24)
+                P[kPartDW2 + (16 * ((tile - 8) >> 2) + row) * 64 + 16 * ((tile - 8) & 3) + col] = acc[k][q];
+            else if (row < 2)
+                P[kPartDW3 + row * 64 + 16 * (tile - 24) + col] = acc[k][q];
+        }
+    }
+    // bias sums: reduce over the 16 lanes sharing rq (different samples), then over waves
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            db1[k] += __shfl_xor(db1[k], off);
+            db2[k] += __shfl_xor(db2[k], off);
+        }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+        db3[0] += __shfl_xor(db3[0], off);
+        db3[1] += __shfl_xor(db3[1], off);
+        lsum += __shfl_xor(lsum, off);
+    }
+    if (col == 0) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sm.red[wv][16 * rb + rq + q] = db1[rb * 4 + q];
+                sm.red[wv][64 + 16 * rb + rq + q] = db2[rb * 4 + q];
+            }
+    }
+    if (l == 0) {
+        sm.red[wv][128] = db3[0];
+        sm.red[wv][129] = db3[1];
+        sm.red[wv][130] = lsum;
+    }
+    __syncthreads();
+    if (t < 131) {
+        const float v = ((sm.red[0][t] + sm.red[1][t]) + sm.red[2][t]) + sm.red[3][t];
+        if (t < 64) P[kPartDB1 + t] = v;
+        else if (t < 128) P[kPartDB2 + t - 64] = v;
+        else if (t < 130) P[kPartDB3 + t - 128] = v;
+        else P[kPartLoss] = v / (float)M;
+    }
+}
+
+// Gradient sums over the blocks in a fixed order, then (adam != 0) one Adam
+// step on the FP32 master parameters and fresh bfloat16 copies.
+__global__ void mlp_reduce_adam_kernel(const float* part, int nblocks, float* master, float* m, float* v, float* grad,
+                                       float* loss, __bf16* wts, int adam, float lr, float c1, float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0 && loss && part) {
+        float s = 0.f;
+        for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kPartStride + kPartLoss];
+        *loss = s;
+    }
+    if (p >= kMlpParams) return;
+    // master layout: W1 [32][64], b1, W2 [64][64], b2, W3 [64][2], b3
+    int src, kind, i = 0, o = 0;
+    if (p < 2048) { i = p / 64; o = p % 64; src = kPartDW1 + o * 32 + i; kind = 1; }
+    else if (p < 2112) { src = kPartDB1 + p - 2048; kind = 0; }
+    else if (p < 6208) { const int q = p - 2112; i = q / 64; o = q % 64; src = kPartDW2 + o * 64 + i; kind = 2; }
+    else if (p < 6272) { src = kPartDB2 + p - 6208; kind = 0; }
+    else if (p < 6400) { const int q = p - 6272; i = q / 2; o = q % 2; src = kPartDW3 + o * 64 + i; kind = 3; }
+    else { src = kPartDB3 + p - 6400; kind = 0; }
+    float g = 0.f;
+    if (part) {
+        for (int b = 0; b < nblocks; ++b) g += part[(int64_t)b * kPartStride + src];
+        if (grad) grad[p] = g;
+    } else {
+        g = grad[p];
+    }
+    if (!adam) return;
+    const float mm = 0.9f * m[p] + 0.1f * g;
+    const float vv = 0.999f * v[p] + 0.001f * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float val = master[p] - lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
+    master[p] = val;
+    const __bf16 bv = (__bf16)val;
+    if (kind == 1) wts[o * 32 + i] = bv;                                  // W1^T
+    else if (kind == 2) {
+        wts[2048 + o * 64 + i] = bv;                                      // W2^T
+        wts[2048 + 4096 + 1024 + i * 64 + o] = bv;                        // W2
+    } else if (kind == 3) wts[2048 + 4096 + o * 64 + i] = bv;             // W3^T
+}
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_surrogate(int L, const SurBatch& b, hipStream_t s) {
+    if (b.rm.total <= 0) return hipSuccess;
+    const dim3 grid(b.rm.total), block(kSurBlock);
+    switch (L) {
+        case 2: hipLaunchKernelGGL(surrogate_kernel<2>, grid, block, 0, s, b); break;
+        case 3: hipLaunchKernelGGL(surrogate_kernel<3>, grid, block, 0, s, b); break;
+        case 4: hipLaunchKernelGGL(surrogate_kernel<4>, grid, block, 0, s, b); break;
+        case 5: hipLaunchKernelGGL(surrogate_kernel<5>, grid, block, 0, s, b); break;
+        case 6: hipLaunchKernelGGL(surrogate_kernel<6>, grid, block, 0, s, b); break;
+        case 7: hipLaunchKernelGGL(surrogate_kernel<7>, grid, block, 0, s, b); break;
+        case 8: hipLaunchKernelGGL(surrogate_kernel<8>, grid, block, 0, s, b); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpWeights& w, const float* X, float* Y, int M, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((M + 63) / 64), dim3(256), 0, s, w, X, Y, M);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_gen_lines(float* lines, long long first, int count, unsigned long long seed, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gen_lines_kernel, dim3(count), dim3(32), 0, s, lines, first, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_entries(int2* list, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(label_entries_kernel, dim3((count + 255) / 256), dim3(256), 0, s, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_features(const float2* gamma, int count, const float* labels, float* X, float* T,
+                                 hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(train_features_kernel, dim3((count + 255) / 256), dim3(256), 0, s, gamma, count, labels, X, T);
+    return hipGetLastError();
+}
+
+int mlp_train_blocks(int M) { return std::max(1, std::min(256, M / kTrainChunk)); }
+int mlp_partial_stride() { return kPartStride; }
+
+hipError_t launch_mlp_train(const MlpWeights& w, const __bf16* w2, const float* X, const float* T, int M, float* part,
+                            int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_train_kernel, dim3(nblocks), dim3(256), 0, s, w, w2, X, T, M, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_reduce_adam(const float* part, int nblocks, float* master, float* m, float* v, float* grad,
+                                  float* loss, __bf16* wts, int adam, float lr, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, part, nblocks, master,
+                       m, v, grad, loss, wts, adam, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace bm

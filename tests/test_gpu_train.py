@@ -1,0 +1,201 @@
+"""Surrogate training on the GPU: the generated training set, the gradients
+and the Adam step against the oracle, and what a trained network gains."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from oracle import surrogate as S
+from parity_util import OMEGA_TOL, wrap
+
+pytestmark = pytest.mark.gpu
+
+LABEL_L, LABEL_N, CENTRE = 8, 32, 64
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def oracle_dataset(ids, seed):
+    """Features, targets and labels of training lines, from the oracle alone."""
+    lines, _ = wl.philox_training_lines(ids, seed)
+    gamma = oracle.analytic_signal(lines)
+    win = gamma[:, CENTRE - LABEL_N // 2:CENTRE - LABEL_N // 2 + LABEL_N]
+    omega = oracle.demod_windows(win, LABEL_L)
+    return S.features(win), S.targets(omega), omega
+
+
+def gpu_dataset(bm, torch, h, first, count, seed):
+    X = torch.empty((count, 32), device="cuda")
+    T = torch.empty((count, 2), device="cuda")
+    w = torch.empty(count, device="cuda")
+    bm.bosmusic_surrogate_dataset(h, first, X, T, w, seed=seed)
+    return X, T, w
+
+
+def test_dataset_matches_oracle(bm, torch):
+    d = bm.Demodulator(0, max_width=64, max_height=64)
+    first, count, seed = 70000, 3000, 11
+    X, T, w = gpu_dataset(bm, torch, d.h, first, count, seed)
+    torch.cuda.synchronize()
+    Xr, Tr, wr = oracle_dataset(np.arange(first, first + count), seed)
+    got = w.cpu().numpy().astype(np.float64)
+    dw = np.abs(wrap(got - wr))
+    assert np.quantile(dw, 0.999) <= OMEGA_TOL, np.quantile(dw, 0.999)
+    assert np.max(np.abs(X.cpu().numpy() - Xr)) < 2e-4
+    assert np.max(np.abs(T.cpu().numpy() - Tr)) < 2e-4
+    # the frequencies lie in the drawn range up to the estimation error
+    assert np.quantile(got, 0.01) > 2 * math.pi / 16 - 0.1 and np.quantile(got, 0.99) < 2 * math.pi / 4 + 0.1
+    d.close()
+
+
+def test_dataset_chunks_and_label_jobs(bm, torch):
+    """More than one generation chunk and more than one label job: equal to
+    the same lines generated piecewise, and to the oracle on a sample."""
+    d = bm.Demodulator(0, max_width=64, max_height=64)
+    n = (1 << 18) + 1000
+    X, T, w = gpu_dataset(bm, torch, d.h, 5, n, 3)
+    X2, T2, w2 = gpu_dataset(bm, torch, d.h, 5 + 200000, 100000, 3)
+    torch.cuda.synchronize()
+    k = n - 200000
+    assert torch.equal(X[200000:], X2[:k]) and torch.equal(T[200000:], T2[:k]) and torch.equal(w[200000:], w2[:k])
+    pick = np.random.default_rng(0).choice(n, 400, replace=False)
+    Xr, Tr, wr = oracle_dataset(5 + pick, 3)
+    dw = np.abs(wrap(w.cpu().numpy()[pick].astype(np.float64) - wr))
+    assert np.quantile(dw, 0.99) <= OMEGA_TOL
+    d.close()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_gradient_matches_oracle(bm, torch):
+    d = bm.Demodulator(0, max_width=64, max_height=64)
+    p = S.init_params(8)
+    bm.bosmusic_surrogate_load(d.h, p)
+    M = 64 * 300                                          # 256 blocks, ragged walk over 300 chunks
+    Xr, Tr, _ = oracle_dataset(np.arange(M), 2)
+    X = torch.from_numpy(Xr.astype(np.float32)).cuda()
+    T = torch.from_numpy(Tr.astype(np.float32)).cuda()
+    g = torch.empty(bm.MLP_PARAMS, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    bm.bosmusic_surrogate_grad(d.h, X, T, g, loss)
+    g2 = torch.empty_like(g)
+    bm.bosmusic_surrogate_grad(d.h, X, T, g2)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g2)                             # fixed summation order
+    cache = S.forward(p, Xr.astype(np.float32), quantize=True)
+    ref = S.backward(cache, Tr)
+    assert abs(loss.item() - S.loss(cache["Y"], Tr)) <= 1e-3 * S.loss(cache["Y"], Tr)
+    got = g.cpu().numpy().astype(np.float64)
+    off = 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        n = int(np.prod(S.SHAPES[k]))
+        a, b = got[off:off + n], ref[k].reshape(-1)
+        off += n
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        assert _rel(a, b) <= 1e-2 and cos >= 0.999, (k, _rel(a, b), cos)
+    d.close()
+
+
+def test_adam_steps_match_oracle(bm, torch):
+    d = bm.Demodulator(0, max_width=64, max_height=64)
+    p0 = S.init_params(4)
+    bm.bosmusic_surrogate_load(d.h, p0)
+    rng = np.random.default_rng(9)
+    flat0 = bm._flat_params(p0).astype(np.float64)
+    P = {"p": flat0}
+    m = {"p": np.zeros_like(flat0)}
+    v = {"p": np.zeros_like(flat0)}
+    for t, lr in ((1, 1e-2), (2, 1e-2), (3, 3e-3)):
+        g = rng.standard_normal(flat0.size).astype(np.float32) * rng.uniform(1e-3, 1, flat0.size).astype(np.float32)
+        bm.bosmusic_surrogate_step(d.h, torch.from_numpy(g).cuda(), lr)
+        P, m, v = S.adam(P, {"p": g.astype(np.float64)}, m, v, t=t, lr=lr)
+    got = bm.bosmusic_surrogate_save(d.h).astype(np.float64)
+    assert np.max(np.abs(got - P["p"])) < 1e-6 * (1 + np.max(np.abs(P["p"])))
+    # the bfloat16 copies follow the master weights: forward equals the oracle at the new parameters
+    X = np.random.default_rng(1).standard_normal((256, 32)).astype(np.float32)
+    Y = torch.empty((256, 2), device="cuda")
+    bm.bosmusic_surrogate_forward(d.h, torch.from_numpy(X).cuda(), Y)
+    torch.cuda.synchronize()
+    newp = {}
+    off = 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        n = int(np.prod(S.SHAPES[k]))
+        newp[k] = got[off:off + n].astype(np.float32).reshape(S.SHAPES[k])
+        off += n
+    ref = S.forward(newp, X, quantize=True, fp32_acc=True)["Y"]
+    err = np.abs(Y.cpu().numpy() - ref)
+    assert np.quantile(err, 0.99) < 2e-3 * np.max(np.abs(ref))
+    # and so does the plain W2 copy used by the backward pass
+    Xr, Tr, _ = oracle_dataset(np.arange(1024), 6)
+    gd = torch.empty(bm.MLP_PARAMS, device="cuda")
+    bm.bosmusic_surrogate_grad(d.h, torch.from_numpy(Xr.astype(np.float32)).cuda(),
+                               torch.from_numpy(Tr.astype(np.float32)).cuda(), gd)
+    torch.cuda.synchronize()
+    refg = S.backward(S.forward(newp, Xr.astype(np.float32)), Tr)
+    a = gd.cpu().numpy()[2048 + 64:2048 + 64 + 4096].astype(np.float64)
+    assert _rel(a, refg["W2"].reshape(-1)) <= 1e-2
+    d.close()
+
+
+def test_training_gain(bm, torch):
+    """A network trained on the GPU predicts the labels far better than the
+    untrained one, and lets the surrogate path accept most windows of fringe
+    frames while the maps stay within RMS 2e-3 rad/px of the oracle."""
+    d = bm.Demodulator(0, max_width=512, max_height=512, stats=True)
+    p0 = S.init_params(1)
+    bm.bosmusic_surrogate_load(d.h, p0)
+    n = 1 << 18
+    X, T, _ = gpu_dataset(bm, torch, d.h, 0, n, 21)
+    Xh, Th, wh = gpu_dataset(bm, torch, d.h, 1 << 30, 8192, 21)
+    Y = torch.empty((8192, 2), device="cuda")
+
+    def held_out_rms():
+        bm.bosmusic_surrogate_forward(d.h, Xh, Y)
+        torch.cuda.synchronize()
+        y = Y.cpu().numpy().astype(np.float64)
+        e = wrap(np.arctan2(y[:, 1], y[:, 0]) - wh.cpu().numpy())
+        return math.sqrt(np.mean(e * e))
+
+    rms0 = held_out_rms()
+    losses = bm.bosmusic_surrogate_train(d.h, X, T, batch=4096, steps=1500, lr=2e-3)
+    assert np.all(np.isfinite(losses))
+    assert losses[-50:].mean() < 0.1 * losses[:10].mean(), (losses[:10].mean(), losses[-50:].mean())
+    rms1 = held_out_rms()
+    assert rms1 < 0.2 * rms0 and rms1 < 0.1, (rms0, rms1)
+
+    frame = wl.cfg4_frame(0, size=256)
+    img = torch.from_numpy(frame.data.astype(np.float32)).cuda()
+    ref = oracle.demodulate(frame.data.astype(np.float64), 8, 32, "x")[0]
+
+    def run(params):
+        if params is not None:
+            bm.bosmusic_surrogate_load(d.h, params)
+        d.stats(reset=True)
+        wx, _ = d.demodulate(img, 8, 32, "x", mode=bm.BM_SURROGATE)
+        torch.cuda.synchronize()
+        st = d.stats()
+        got = wx.cpu().numpy().astype(np.float64)
+        m = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got), m)
+        e = wrap(got[m] - ref[m])
+        return st["sur_accepted"] / max(1, st["sur_accepted"] + st["sur_rejected"]), math.sqrt(np.mean(e * e))
+
+    trained = bm.bosmusic_surrogate_save(d.h)
+    acc1, r1 = run(None)
+    acc0, r0 = run(p0)
+    assert r1 <= 2e-3 and r0 <= 2e-3
+    assert acc1 > 0.9 and acc1 > acc0 + 0.3, (acc0, acc1)
+    np.testing.assert_array_equal(bm.bosmusic_surrogate_save(d.h), bm._flat_params(p0))
+    d.close()
+    print(f"held-out RMS {rms0:.3f} -> {rms1:.4f} rad; accepted {acc0:.3f} -> {acc1:.3f}; "
+          f"trained params {trained[:2]}")
