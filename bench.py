@@ -55,6 +55,72 @@ def flops_per_window(L: int, N: int, newton: float, iters: float) -> dict:
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
 
+def surrogate_flops_per_window(L: int, N: int) -> dict:
+    """Algorithmic flops of one window of the surrogate kernel, counted up to
+    the first point where a window can be rejected (so a lower bound for the
+    accepted ones): features, the MLP (matrix-core flops kept apart), lag
+    sums, the real transform, the power iteration, the polynomial and the
+    FP32 and FP64 quadratic-factor Newton steps.  Transcendentals (erf,
+    sincos, atan2) count as one flop."""
+    K = N - L + 1
+    n = 2 * L - 2
+    feat = 4 * N + 16 * 6 + 10
+    mlp_mfma = 2 * (32 * 64 + 64 * 64 + 64 * 2)
+    mlp_valu = 2 * 64 * 4 + 64 * 2 + 2
+    lag = K * L * 8
+    build_t = 3 * L * L + L + L * (L + 1) // 2
+    power = 6 * (2 * L * L + 3 * L + 1)
+    coef = 2 * L + 8 * L * (L + 1) // 2
+    bairstow = (n + 1) * 32 + 60
+    fp32 = feat + mlp_valu + lag + build_t + power + coef + 8 * bairstow + 40
+    fp64 = 2 * bairstow
+    return {"fp32": fp32, "fp64": fp64, "mfma": mlp_mfma, "valu": fp32 + fp64}
+
+
+TRAIN_MFMA_FLOPS = 2 * (32 * 64 + 64 * 64 + 64 * 2) * 2 + 2 * 64 * 64   # forward, weight gradients, dH1
+
+
+def train_surrogate(bm, torch, args):
+    """Training set on the GPU, then minibatch Adam; returns (params, report)."""
+    tr = bm.Demodulator(0, max_width=64, max_height=64)
+    bm.bosmusic_surrogate_load(tr.h, bm.init_params(0))
+    M = args.train_windows
+    X = torch.empty((M, 32), device="cuda")
+    T = torch.empty((M, 2), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bm.bosmusic_surrogate_dataset(tr.h, 0, X, T, None, seed=2024)
+    t_ds = time.perf_counter() - t0
+    Mh = 65536
+    Xh = torch.empty((Mh, 32), device="cuda")
+    Th = torch.empty((Mh, 2), device="cuda")
+    wh = torch.empty(Mh, device="cuda")
+    bm.bosmusic_surrogate_dataset(tr.h, 1 << 31, Xh, Th, wh, seed=2024)
+    print(f"# training set: {M} windows in {t_ds:.2f}s", file=sys.stderr, flush=True)
+    s1 = (2 * args.train_steps) // 3
+    t0 = time.perf_counter()
+    l1 = bm.bosmusic_surrogate_train(tr.h, X, T, args.train_batch, s1, 2e-3)
+    l2 = bm.bosmusic_surrogate_train(tr.h, X, T, args.train_batch, args.train_steps - s1, 2e-4)
+    t_tr = time.perf_counter() - t0
+    Y = torch.empty((Mh, 2), device="cuda")
+    bm.bosmusic_surrogate_forward(tr.h, Xh, Y)
+    torch.cuda.synchronize()
+    y = Y.cpu().numpy().astype(np.float64)
+    e = (np.arctan2(y[:, 1], y[:, 0]) - wh.cpu().numpy() + np.pi) % (2 * np.pi) - np.pi
+    params = bm.bosmusic_surrogate_save(tr.h)
+    tr.close()
+    losses = np.concatenate([l1, l2])
+    ws = args.train_steps * args.train_batch
+    rep = {"windows": M, "steps": args.train_steps, "batch": args.train_batch, "lr": "2e-3 then 2e-4 (last third)",
+           "dataset_s": round(t_ds, 3), "train_s": round(t_tr, 3), "window_steps_per_s": ws / t_tr,
+           "mfma_tflops": ws * TRAIN_MFMA_FLOPS / t_tr / 1e12, "loss_first": float(losses[0]),
+           "loss_last": float(losses[-20:].mean()), "held_out_rms_rad": float(np.sqrt(np.mean(e * e))),
+           "held_out_windows": Mh}
+    print(f"# trained {args.train_steps} steps x {args.train_batch} in {t_tr:.2f}s, loss {losses[0]:.4f} -> "
+          f"{losses[-20:].mean():.5f}, held-out rms {rep['held_out_rms_rad']:.4f} rad", file=sys.stderr, flush=True)
+    return params, rep
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample, on the host cores
 # ---------------------------------------------------------------------------
@@ -132,7 +198,8 @@ def main():
     ap.add_argument("--train-batch", type=int, default=16384, help="cfg5: minibatch")
     ap.add_argument("--frames", type=int, default=0, help="number of frames (0: the workload's own)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-lines", type=int, default=512, help="oracle sample: lines per direction per frame")
+    ap.add_argument("--cpu-lines", type=int, default=0,
+                    help="oracle sample: lines per direction per frame (0: about 4M windows in all)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -154,6 +221,9 @@ def main():
     if not args.no_cpu:
         workers = max(1, min(16, os.cpu_count() or 1))
         sf = sorted({0, nf // 3, (2 * nf) // 3, nf - 1})
+        if args.cpu_lines <= 0:
+            mean_len = np.mean([fr[t].width + fr[t].height for t in sf]) / 2
+            args.cpu_lines = max(8, int(4e6 / (2 * len(sf) * mean_len)))
         res, windows, osec = cpu_baseline(frames, fr, sf, args.cpu_lines, workers)
         sample = res
         px_s = windows / osec / 2.0            # two directions per pixel
@@ -183,6 +253,11 @@ def main():
             tdem.autotune(L, N, width=1024, lines=512)
         tdem.close()
     stream = torch.cuda.current_stream()
+    surrogate = args.workload == "cfg5"
+    mode = bm.BM_SURROGATE if surrogate else bm.BM_PLAIN
+    params = train_rep = None
+    if surrogate:
+        params, train_rep = train_surrogate(bm, torch, args)
 
     if args.copy_mib > 0:
         nel = args.copy_mib * (1 << 20) // 4
@@ -194,22 +269,25 @@ def main():
         del src, dst
 
     def make(**kw):
-        return bm.Demodulator(0, max_width=maxw, max_height=maxh, max_batch_pixels=total_px, **kw)
+        dm = bm.Demodulator(0, max_width=maxw, max_height=maxh, max_batch_pixels=total_px, **kw)
+        if surrogate:
+            bm.bosmusic_surrogate_load(dm.h, params)
+        return dm
 
-    def step(dm):
-        bm.bosmusic_demodulate(dm.h, specs, bm.BM_PLAIN, stream)
+    def step(dm, m=None):
+        bm.bosmusic_demodulate(dm.h, specs, mode if m is None else m, stream)
         for i in range(nf):
             bm.bosmusic_integrate(dm.h, wx[i], wy[i], fr[i].N, fr[i].N, 0.0, 0.0, phi[i], stream)
 
-    def timed(dm):
+    def timed(dm, m=None):
         for _ in range(args.warmup):
-            step(dm)
+            step(dm, m)
         torch.cuda.synchronize()
         dm.stats(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(dm)
+            step(dm, m)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         return (t1 - t0) * 1e3 / args.steps, dm.stats(reset=True)
@@ -230,14 +308,23 @@ def main():
     print(f"# {args.steps} steps, {ms:.2f} ms/step, {mpx:.1f} Mpixel/s (event-timed pass {ms_ev:.2f} ms/step)",
           file=sys.stderr, flush=True)
 
-    # iteration counts per L (counting variant of the kernel, outside the timed region)
+    plain_same = None
+    if surrogate:
+        pdem = make(timing=True)
+        ms_plain, _ = timed(pdem, bm.BM_PLAIN)
+        pdem.close()
+        plain_same = {"value": total_px / (ms_plain / 1e3) / 1e6, "unit": "Mpixel/s", "ms_per_step": ms_plain}
+        print(f"# plain on the same frames: {ms_plain:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # iteration counts per L (counting variant of the kernels, outside the timed region)
     flops_step = 0.0
+    mfma_step = 0.0
     per_L = {}
     for L in sorted({f.L for f in fr}):
         idx = [i for i in range(nf) if fr[i].L == L]
-        sdem = bm.Demodulator(0, max_width=maxw, max_height=maxh, stats=True)
+        sdem = make(stats=True)
         sub = [specs[i] for i in idx[:3]]
-        bm.bosmusic_demodulate(sdem.h, sub, bm.BM_PLAIN, stream)
+        bm.bosmusic_demodulate(sdem.h, sub, mode, stream)
         ss = sdem.stats(reset=True)
         sdem.close()
         newton = ss["eig_iters"] / max(1, ss["windows"])
@@ -247,16 +334,29 @@ def main():
             W, H, N = fr[i].width, fr[i].height, fr[i].N
             wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
         fl = flops_per_window(L, fr[idx[0]].N, newton, iters)
-        flops_step += fl["total"] * wins
-        per_L[L] = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2), "root_iters": round(iters, 2),
-                    "windows_per_step": wins}
-    rm_s = st["rm_time_ns"] / 1e9 / args.steps          # root-MUSIC time per step
+        entry = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2), "root_iters": round(iters, 2),
+                 "windows_per_step": wins}
+        if surrogate:
+            acc, rej = ss["sur_accepted"], ss["sur_rejected"]
+            frac_rej = rej / max(1, acc + rej)
+            sf = surrogate_flops_per_window(L, fr[idx[0]].N)
+            flops_step += wins * (sf["valu"] + frac_rej * fl["total"])
+            mfma_step += wins * sf["mfma"]
+            entry.update({"surrogate_valu_flop_per_window": sf["valu"], "surrogate_mfma_flop_per_window": sf["mfma"],
+                          "accepted_fraction": round(1 - frac_rej, 5)})
+        else:
+            flops_step += fl["total"] * wins
+        per_L[L] = entry
+    rm_s = st["rm_time_ns"] / 1e9 / args.steps          # root-MUSIC (or surrogate + fallback) time per step
     achieved = flops_step / rm_s
+    kname = ("surrogate_kernel + rootmusic_gather_kernel fallback" if surrogate else "rootmusic_kernel")
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-            "kernel": f"rootmusic_kernel, {st['rm_launches'] // args.steps} launch(es)/step, mean launch "
+            "kernel": f"{kname}, {st['rm_launches'] // args.steps} timed region(s)/step, mean "
                       f"{st['rm_time_ns'] / max(1, st['rm_launches']) / 1e6:.3f} ms (HIP events on its stream), "
                       f"per L: {json.dumps(per_L)}"}
+    if surrogate:
+        roof["mfma_tflops_in_mlp"] = mfma_step / rm_s / 1e12
 
     err = None
     if sample is not None:
@@ -268,6 +368,7 @@ def main():
             ds.append(np.abs((got[m] - om[m] + np.pi) % (2 * np.pi) - np.pi))
         d = np.concatenate(ds)
         err = {"vs_oracle_p999": float(np.quantile(d, 0.999)), "vs_oracle_max": float(d.max()),
+               "tolerance": "RMS <= 2e-3" if surrogate else "p99.9 <= 1e-4",
                "vs_oracle_rms": float(np.sqrt(np.mean(d * d))), "windows": int(d.size), "unit": "rad/px"}
 
     out = {
@@ -284,11 +385,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "frames": nf, "pixels": total_px,
-                   "dirs": "xy", "mode": "plain", "graph": use_graph},
+                   "dirs": "xy", "mode": "surrogate" if surrogate else "plain", "graph": use_graph},
         "roofline": roof,
         "cpu_baseline": cpu,
         "error": err,
     }
+    if surrogate:
+        out["plain_same_gpu"] = plain_same
+        out["training"] = train_rep
     print(json.dumps(out))
     dem.close()
 

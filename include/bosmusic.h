@@ -173,11 +173,16 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
  * An MLP 32 -> 64 -> 64 -> 2 (exact-erf GELU) maps the normalised window (16
  * central samples de-rotated by the central sample's phase, divided by the
  * window's RMS magnitude, [Re(16), Im(16)]) to (cos w, sin w).  Its estimate
- * seeds a power iteration for the signal subspace and Newton iterations on
- * the quadratic factor of the root-MUSIC polynomial (paper Eq. 12); the
- * window is accepted when the factor converged with a root within 0.05 of
- * the unit circle and the MUSIC null spectrum 1 - |u1^H a(w)|^2 / L at the
- * refined w is below tau; every other window is finished by the plain path.
+ * w_hat seeds a power iteration for the signal eigenvector u1; the window is
+ * rejected when the MUSIC null spectrum 1 - |u1^H a(w_hat)|^2 / L at the
+ * prediction exceeds tau.  Newton iterations (FP64) on the quadratic factor
+ * of the root-MUSIC polynomial (paper Eq. 12) started from the double root
+ * e^{j w_hat} then find a root pair, and the window is accepted only when
+ * the pair is conjugate-reciprocal and a Schur-Cohn count on the deflated
+ * polynomial shows that no other root lies as near the unit circle: the
+ * accepted pair is then the pair the plain path selects (Sec. 3, Eq. 15),
+ * and w = arg(z1 + z2) as there.  Every other window is finished by the
+ * plain path, so the output equals the plain output up to rounding.
  * Parameters are FP32, in this order, row-major: W1[32][64], b1[64],
  * W2[64][64], b2[64], W3[64][2], b3[2] (6402 floats); the kernels use
  * bfloat16 copies (round to nearest even) and FP32 accumulation. */
@@ -190,7 +195,7 @@ bm_status bosmusic_surrogate_load(bosmusic_t h, const float* params, int64_t n);
 /* Copy the current FP32 parameters to host memory. Synchronous. */
 bm_status bosmusic_surrogate_save(bosmusic_t h, float* params, int64_t n);
 
-/* Acceptance bound tau on the null spectrum (default 1e-3) and predictor:
+/* Bound tau on the null spectrum at the prediction (default 0.25) and predictor:
  * 0 = the MLP, 1 = the lag-1 phase of the covariance (a non-learned
  * predictor, for comparison). */
 bm_status bosmusic_surrogate_config(bosmusic_t h, float tau, int32_t predictor);

@@ -203,6 +203,17 @@ def bosmusic_autotune(h, L: int, N: int, width: int = 1024, lines: int = 512, st
     return us.value
 
 
+def init_params(seed: int = 0):
+    """Seeded starting weights for training: W ~ N(0, 1/fan_in), b ~ N(0, 0.01), flat FP32."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, shape in ((32, (32, 64)), (0, (64,)), (64, (64, 64)), (0, (64,)), (64, (64, 2)), (0, (2,))):
+        z = rng.standard_normal(shape)
+        parts.append((z / np.sqrt(fan_in) if fan_in else 0.1 * z).astype(np.float32).reshape(-1))
+    return np.concatenate(parts)
+
+
 def _flat_params(params):
     import numpy as np
     if isinstance(params, dict):
@@ -227,7 +238,7 @@ def bosmusic_surrogate_save(h):
     return a
 
 
-def bosmusic_surrogate_config(h, tau: float = 1e-3, predictor: int = 0) -> None:
+def bosmusic_surrogate_config(h, tau: float = 0.25, predictor: int = 0) -> None:
     _check(lib().bosmusic_surrogate_config(h, tau, predictor), h)
 
 

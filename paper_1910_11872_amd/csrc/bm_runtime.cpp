@@ -70,7 +70,7 @@ struct bosmusic_s {
     float* sur_master = nullptr;   // FP32 parameters (BOSMUSIC_MLP_PARAMS)
     __bf16* sur_w = nullptr;       // bfloat16 W1^T [64][32] | W2^T [64][64] | W3^T [16][64] | W2 [64][64]
     bool sur_loaded = false;
-    float sur_tau = 1e-3f;
+    float sur_tau = 0.25f;
     int sur_predictor = 0;
     int2* rejects = nullptr;
     size_t rejects_cap = 0;

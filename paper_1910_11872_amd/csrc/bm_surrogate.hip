@@ -13,13 +13,15 @@
 //      after one LDS round trip; omega_hat = atan2 of the two outputs;
 //   4. lag sums and covariance as in the plain kernel, the real symmetric
 //      T = Q^H R_fb Q, its top eigenvector by power iteration seeded with the
-//      steering vector of omega_hat, the MUSIC null spectrum, and Newton
-//      iterations on the quadratic factor of the root-MUSIC polynomial (paper
-//      Eq. 12) started from the double root e^{j omega_hat} (FP32, then FP64);
-//   5. accept when the factor converged, its roots sit within 0.05 of the
-//      unit circle and the null spectrum at the refined frequency is below
-//      tau: omega = arg(z1 + z2) as in the plain path; otherwise the window
-//      goes to the reject list, which the plain gather kernel finishes.
+//      steering vector of omega_hat, and the MUSIC null spectrum at
+//      omega_hat (reject above tau);
+//   5. Newton iterations in FP64 on the quadratic factor of the root-MUSIC
+//      polynomial (paper Eq. 12) started from the double root e^{j omega_hat};
+//      accept when the factor converged to a conjugate-reciprocal pair and a
+//      Schur-Cohn count on the deflated polynomial shows no other root as
+//      near the unit circle, so that the pair is the one the plain path
+//      selects: omega = arg(z1 + z2) as in the plain path; otherwise the
+//      window goes to the reject list, which the plain gather kernel finishes.
 #include "bm_window.h"
 
 #include <algorithm>
@@ -32,9 +34,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
 constexpr int kPowerSteps = 6;
-constexpr int kRefine32 = 8;
-constexpr int kRefine64 = 2;
-constexpr float kPairBand = 0.05f;
+constexpr int kRefineIters = 6;       // FP64 Newton steps on the quadratic factor
+constexpr double kMateTol = 1e-6;     // |z1 conj(z2) - 1| of an accepted pair
+constexpr double kCertMargin = 1e-6;  // relative radius margin of the nearest-pair certificate
 
 // C(16 x 16) += A(16 x 32) B(32 x 16) on one wave.  A(i, k) = a[i*lda + k],
 // B(k, j) = b[j*ldb + k]; both 16-byte aligned with k contiguous.  Lane l
@@ -120,14 +122,65 @@ __device__ __forceinline__ void steering_real(float w, float (&v0)[L]) {
     if (L & 1) v0[m] = rsqrtf((float)L);
 }
 
+// Number of zeros of f(z) = sum_i (fr[i] + j fi[i]) z^i (formal degree m)
+// strictly inside the unit disk, by the Schur-Cohn recursion
+//     T f = conj(a_0) f - a_m f*,   f*(z) = z^m conj(f(1/conj(z))),
+// whose constant term gamma = |a_0|^2 - |a_m|^2 decides the count: when
+// gamma > 0, T f has as many zeros inside as f; when gamma < 0, as many as
+// f*, i.e. m minus those of f (Henrici, Applied and Computational Complex
+// Analysis I, Sec. 6.8).  Returns -1 when some |gamma| is too small to
+// decide, which is the case of a zero on or very near the unit circle.
+template <int m>
+__device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], double (&fi)[m + 1]) {
+    unsigned neg = 0;
+    bool ok = true;
+#pragma unroll
+    for (int d = m; d >= 1; --d) {
+        const double a0r = fr[0], a0i = fi[0], adr = fr[d], adi = fi[d];
+        const double p0 = a0r * a0r + a0i * a0i, pd = adr * adr + adi * adi;
+        const double g = p0 - pd;
+        ok = ok && (fabs(g) > 1e-9 * (p0 + pd));
+        neg |= (g < 0.0 ? 1u : 0u) << d;
+        const double sc = 1.0 / (p0 + pd);
+        // new_i = conj(a0) a_i - a_d conj(a_{d-i}), in place over the pairs (i, d-i)
+#pragma unroll
+        for (int i = 1; 2 * i <= d; ++i) {
+            const int k = d - i;
+            const double xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
+            const double nir = (a0r * xr + a0i * xi) - (adr * yr + adi * yi);
+            const double nii = (a0r * xi - a0i * xr) - (adi * yr - adr * yi);
+            const double nkr = (a0r * yr + a0i * yi) - (adr * xr + adi * xi);
+            const double nki = (a0r * yi - a0i * yr) - (adi * xr - adr * xi);
+            fr[i] = nir * sc; fi[i] = nii * sc;
+            fr[k] = nkr * sc; fi[k] = nki * sc;
+        }
+        fr[0] = g * sc;
+        fi[0] = 0.0;
+    }
+    int count = 0;
+#pragma unroll
+    for (int d = 1; d <= m; ++d)
+        if ((neg >> d) & 1u) count = d - count;
+    return ok ? count : -1;
+}
+
 // Refinement of a predicted frequency; true when the estimate is accepted.
+// The estimate is judged by the MUSIC null spectrum at the prediction, then
+// the quadratic factor z^2 - r z - s of the root-MUSIC polynomial (paper
+// Eq. 12) holding the predicted double root is found by Newton's method in
+// FP64, and the window is accepted only when that factor is the pair of
+// roots nearest the unit circle, which is the pair the plain path selects
+// (Sec. 3): its roots are a conjugate-reciprocal pair (z, 1/conj z), and
+// the quotient polynomial has all its inner roots strictly inside |z| < |z_in|.
 template <int L>
 __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, float& omega) {
     constexpr int n = 2 * L - 2;
     Sym<L> T;
     if (!normalised_T<L>(R, T)) return false;
-    float v[L];
-    steering_real<L>(what, v);
+    float v0[L], v[L];
+    steering_real<L>(what, v0);
+#pragma unroll
+    for (int i = 0; i < L; ++i) v[i] = v0[i];
     for (int it = 0; it < kPowerSteps; ++it) {
         float y[L];
 #pragma unroll
@@ -144,36 +197,56 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
 #pragma unroll
         for (int i = 0; i < L; ++i) v[i] = y[i] * in;
     }
+    // MUSIC null spectrum 1 - |u1^H a(w)|^2 / L at the prediction
+    float dot = 0.f;
+#pragma unroll
+    for (int i = 0; i < L; ++i) dot = fmaf(v[i], v0[i], dot);
+    if (!(1.f - dot * dot <= tau)) return false;
     float ur[L], ui[L];
     signal_vector<L>(v, ur, ui);
     float ar[n + 1], ai[n + 1];
     poly_coeffs<L>(ur, ui, ar, ai);
-    // the quadratic factor of the double root e^{j what}: z^2 - r z - s
+    // the factor of the double root e^{j what}: r = 2 e^{j what}, s = -e^{2 j what}
     float sw, cw;
     sincosf(what, &sw, &cw);
-    float r32 = 2.f * cw, i32 = 2.f * sw, sr32 = -(cw * cw - sw * sw), si32 = -2.f * cw * sw, last32 = 0.f;
-    if (!bairstow<float, n>(ar, ai, r32, i32, sr32, si32, kRefine32, last32)) return false;
-    double rr = r32, ri = i32, s_r = sr32, s_i = si32, last = 0.0;
-    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefine64, last)) return false;
-    if (!(last <= 1e-6 * (fabs(rr) + fabs(ri)))) return false;
+    double rr = 2.0 * cw, ri = 2.0 * sw, s_r = -((double)cw * cw - (double)sw * sw), s_i = -2.0 * (double)cw * sw;
+    double last = 0.0;
+    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last)) return false;
+    if (!(last <= 1e-9 * (fabs(rr) + fabs(ri)))) return false;
     // roots of the factor: (r +- sqrt(r^2 + 4 s)) / 2
-    const float pr = (float)rr, pi = (float)ri;
-    const float dr = pr * pr - pi * pi + 4.f * (float)s_r, di = 2.f * pr * pi + 4.f * (float)s_i;
-    const float md = fsqrt(dr * dr + di * di);
-    const float qr = fsqrt(fmaxf(0.f, 0.5f * (md + dr)));
-    const float qi = copysignf(fsqrt(fmaxf(0.f, 0.5f * (md - dr))), di);
-    const float z1r = 0.5f * (pr + qr), z1i = 0.5f * (pi + qi);
-    const float z2r = 0.5f * (pr - qr), z2i = 0.5f * (pi - qi);
-    const float d1 = fabsf(fsqrt(z1r * z1r + z1i * z1i) - 1.f);
-    const float d2 = fabsf(fsqrt(z2r * z2r + z2i * z2i) - 1.f);
-    if (!(fminf(d1, d2) < kPairBand)) return false;
-    const float w = atan2f(pi, pr);
-    float v0[L];
-    steering_real<L>(w, v0);
-    float dot = 0.f;
+    const double dr = rr * rr - ri * ri + 4.0 * s_r, di = 2.0 * rr * ri + 4.0 * s_i;
+    const double md = sqrt(dr * dr + di * di);
+    const double qr = sqrt(fmax(0.0, 0.5 * (md + dr)));
+    const double qi = copysign(sqrt(fmax(0.0, 0.5 * (md - dr))), di);
+    const double z1r = 0.5 * (rr + qr), z1i = 0.5 * (ri + qi);
+    const double z2r = 0.5 * (rr - qr), z2i = 0.5 * (ri - qi);
+    // a conjugate-reciprocal pair: z1 conj(z2) = 1
+    const double pr = z1r * z2r + z1i * z2i, pi = z1i * z2r - z1r * z2i;
+    if (!(fabs(pr - 1.0) + fabs(pi) < kMateTol)) return false;
+    const double rin = sqrt(fmin(z1r * z1r + z1i * z1i, z2r * z2r + z2i * z2i));
+    // quotient Q(z) = P(z) / (z^2 - r z - s) (degree n - 2), scaled to Q(rho z)
+    double fr[n - 1], fi[n - 1];
+    {
+        double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
 #pragma unroll
-    for (int i = 0; i < L; ++i) dot = fmaf(v[i], v0[i], dot);
-    if (!(1.f - dot * dot < tau)) return false;
+        for (int k = n; k >= 2; --k) {
+            const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
+            const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
+            fr[k - 2] = bkr;
+            fi[k - 2] = bki;
+            b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
+        }
+    }
+    const double rho = fmin(rin, 1.0) * (1.0 - kCertMargin);
+    double rp = 1.0;
+#pragma unroll
+    for (int k = 1; k <= n - 2; ++k) {
+        rp *= rho;
+        fr[k] *= rp;
+        fi[k] *= rp;
+    }
+    if (zeros_inside_unit_disk<n - 2>(fr, fi) != L - 2) return false;
+    const float w = atan2f((float)ri, (float)rr);
     omega = w;
     return finitef(w);
 }
