@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--train-windows", type=int, default=10_000_000, help="cfg5: training set size")
     ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: Adam steps")
     ap.add_argument("--train-batch", type=int, default=16384, help="cfg5: minibatch")
+    ap.add_argument("--predictor", default="mlp", choices=["mlp", "lag1"],
+                    help="cfg5: the trained MLP, or the non-learned lag-1 phase predictor")
     ap.add_argument("--frames", type=int, default=0, help="number of frames (0: the workload's own)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-lines", type=int, default=0,
@@ -272,6 +274,7 @@ def main():
         dm = bm.Demodulator(0, max_width=maxw, max_height=maxh, max_batch_pixels=total_px, **kw)
         if surrogate:
             bm.bosmusic_surrogate_load(dm.h, params)
+            bm.bosmusic_surrogate_config(dm.h, 0.25, 1 if args.predictor == "lag1" else 0)
         return dm
 
     def step(dm, m=None):
@@ -385,7 +388,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "frames": nf, "pixels": total_px,
-                   "dirs": "xy", "mode": "surrogate" if surrogate else "plain", "graph": use_graph},
+                   "dirs": "xy", "mode": "surrogate" if surrogate else "plain", "graph": use_graph,
+                   **({"predictor": args.predictor} if surrogate else {})},
         "roofline": roof,
         "cpu_baseline": cpu,
         "error": err,

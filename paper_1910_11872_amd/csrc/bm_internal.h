@@ -45,6 +45,8 @@ struct RmJob {
     int64_t out_es;        // output stride along the line (elements)
     int64_t out_ls;        // output stride between lines (elements)
     uint8_t* flags;        // optional per-pixel flags
+    int64_t flag_es;       // flag strides along the line and between lines (elements)
+    int64_t flag_ls;
     int len;
     int nlines;
     int N;                 // window length

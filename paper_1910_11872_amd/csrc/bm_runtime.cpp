@@ -271,10 +271,13 @@ struct GroupPlan {
     std::vector<int> fft_prefix;
     int max_n = 0;
     std::vector<RmSet> rm;          // one (or two, with flags) per distinct L
-    size_t tr_off = 0, trp_off = 0, fft_off = 0, fftp_off = 0;
+    std::vector<bm::TrJob> back;    // omega_y from its line-major scratch to the caller's row-major map
+    std::vector<int> back_prefix;
+    size_t tr_off = 0, trp_off = 0, fft_off = 0, fftp_off = 0, back_off = 0, backp_off = 0;
     std::vector<char> blob;
     bm::TrBatch trb{};
     bm::FftBatch fftb{};
+    bm::TrBatch backb{};
 };
 
 template <typename T>
@@ -327,6 +330,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             j.out_es = 1;
             j.out_ls = W;
             j.flags = f.flags;
+            j.flag_es = 1;
+            j.flag_ls = W;
             j.len = W;
             j.nlines = H;
             j.N = f.N;
@@ -362,13 +367,29 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 gp.max_n = std::max(gp.max_n, H);
             }
             gp.tr.push_back(tj);
+            // omega_y is written line-major (coalesced) into a scratch map, then
+            // transposed into the caller's map; for real input the scratch is the
+            // transposed frame, dead once the analytic step has read it
+            float* oy = (e == bm::Elem::C32) ? (float*)(h->ws + cur) : (float*)tj.dst;
+            if (e == bm::Elem::C32) cur += align_up(px * sizeof(float), 256);
+            bm::TrJob bj{};
+            bj.src = oy;
+            bj.src_ls = H;
+            bj.dst = f.omega_y;
+            bj.rows = W;
+            bj.cols = H;
+            bj.tiles_x = (H + 31) / 32;
+            bj.elem = BM_F32;
+            gp.back.push_back(bj);
             bm::RmJob j{};
             j.gamma = gy;
             j.gamma_ls = H;
-            j.out = f.omega_y;
-            j.out_es = W;
-            j.out_ls = 1;
+            j.out = oy;
+            j.out_es = 1;
+            j.out_ls = H;
             j.flags = f.flags;
+            j.flag_es = W;
+            j.flag_ls = 1;
             j.len = H;
             j.nlines = W;
             j.N = f.N;
@@ -383,6 +404,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     for (auto& t : gp.tr) gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
     gp.fft_prefix.assign(1, 0);
     for (auto& f : gp.fft) gp.fft_prefix.push_back(gp.fft_prefix.back() + f.nlines);
+    gp.back_prefix.assign(1, 0);
+    for (auto& t : gp.back) gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
     for (auto& kv : sets) {
         RmSet s = kv.second;
         int nmax = 0;
@@ -403,6 +426,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     gp.trp_off = append(gp.blob, gp.tr_prefix);
     gp.fft_off = append(gp.blob, gp.fft);
     gp.fftp_off = append(gp.blob, gp.fft_prefix);
+    gp.back_off = append(gp.blob, gp.back);
+    gp.backp_off = append(gp.blob, gp.back_prefix);
     for (auto& s : gp.rm) {
         s.jobs_off = append(gp.blob, s.jobs);
         s.prefix_off = append(gp.blob, s.prefix);
@@ -421,6 +446,10 @@ void bind_group(bosmusic_s* h, GroupPlan& gp, const char* dev) {
     gp.fftb.njobs = (int)gp.fft.size();
     gp.fftb.total = gp.fft_prefix.back();
     gp.fftb.max_n = gp.max_n;
+    gp.backb.jobs = (const bm::TrJob*)(dev + gp.back_off);
+    gp.backb.prefix = (const int*)(dev + gp.backp_off);
+    gp.backb.njobs = (int)gp.back.size();
+    gp.backb.total = gp.back_prefix.back();
     for (auto& s : gp.rm) {
         s.batch.jobs = (const bm::RmJob*)(dev + s.jobs_off);
         s.batch.prefix = (const int*)(dev + s.prefix_off);
@@ -524,6 +553,11 @@ bm_status launch_front(bosmusic_s* h, const GroupPlan& gp, hipStream_t st) {
     return check(h, bm::launch_analytic(gp.fftb, st), "analytic");
 }
 
+// omega_y maps from their line-major scratch into the caller's maps.
+bm_status launch_back(bosmusic_s* h, const GroupPlan& gp, hipStream_t st) {
+    return check(h, bm::launch_transpose(gp.backb, st), "omega_y transpose");
+}
+
 bm_status ensure_upload_buffers(bosmusic_s* h, size_t bytes, hipStream_t st) {
     if (bytes <= h->pin_bytes && bytes <= h->djobs_bytes) return BM_OK;
     bm_status r;
@@ -562,7 +596,7 @@ bm_status run_group_eager(bosmusic_s* h, GroupPlan& gp, hipStream_t st) {
     const bool timing = (h->options & BM_OPT_TIMING) != 0;
     for (auto& s : gp.rm)
         if ((r = launch_rm(h, s, st, timing, gp.mode))) return r;
-    return BM_OK;
+    return launch_back(h, gp, st);
 }
 
 // Signature of a call: every frame field, mode-relevant options and tuning.
@@ -614,6 +648,7 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
         if ((lr = launch_front(h, gp, c0))) break;
         if (gp.rm.size() == 1) {
             if ((lr = launch_rm(h, gp.rm[0], c0, false, mode))) break;
+            if ((lr = launch_back(h, gp, c0))) break;
             continue;
         }
         // fork: each distinct L on its own capture stream; a y pass stays on
@@ -638,6 +673,7 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
             if ((lr = check(h, hipStreamWaitEvent(c0, h->join_ev[kv.second], 0), "join wait"))) break;
         }
         if (lr) break;
+        if ((lr = launch_back(h, gp, c0))) break;
     }
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(c0, &graph);

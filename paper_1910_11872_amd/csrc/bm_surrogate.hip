@@ -34,7 +34,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
 constexpr int kPowerSteps = 6;
-constexpr int kRefineIters = 6;       // FP64 Newton steps on the quadratic factor
+constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps on the quadratic factor
 constexpr double kMateTol = 1e-6;     // |z1 conj(z2) - 1| of an accepted pair
 constexpr double kCertMargin = 1e-6;  // relative radius margin of the nearest-pair certificate
 
@@ -211,7 +211,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
     sincosf(what, &sw, &cw);
     double rr = 2.0 * cw, ri = 2.0 * sw, s_r = -((double)cw * cw - (double)sw * sw), s_i = -2.0 * (double)cw * sw;
     double last = 0.0;
-    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last)) return false;
+    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last, 1e-13)) return false;
     if (!(last <= 1e-9 * (fabs(rr) + fabs(ri)))) return false;
     // roots of the factor: (r +- sqrt(r^2 + 4 s)) / 2
     const double dr = rr * rr - ri * ri + 4.0 * s_r, di = 2.0 * rr * ri + 4.0 * s_i;

@@ -285,12 +285,12 @@ __device__ __forceinline__ int find_job(const int* prefix, int njobs, int w) {
 
 // Store omega (and the flag nibble) of pixel p of `line` of job J.
 __device__ __forceinline__ void store_omega(const RmJob& J, int line, int p, float omega, unsigned flag) {
-    const int64_t oidx = (int64_t)p * J.out_es + (int64_t)line * J.out_ls;
-    J.out[oidx] = omega;
+    J.out[(int64_t)p * J.out_es + (int64_t)line * J.out_ls] = omega;
     if (J.flags) {
+        const int64_t fidx = (int64_t)p * J.flag_es + (int64_t)line * J.flag_ls;
         const uint8_t f = (uint8_t)(flag << J.flag_shift);
-        if (J.flag_or) J.flags[oidx] |= f;
-        else J.flags[oidx] = f;
+        if (J.flag_or) J.flags[fidx] |= f;
+        else J.flags[fidx] = f;
     }
 }
 
@@ -344,11 +344,12 @@ __device__ __forceinline__ void poly_coeffs(const float (&ur)[L], const float (&
 }
 
 // Newton iterations on the quadratic factor z^2 - r z - s of the polynomial
-// (complex Bairstow), in precision T.  Returns false when a step is not
-// finite; `lastc` receives |dr| of the last step.
+// (complex Bairstow), in precision T: at most `iters` steps, fewer once a
+// step is below tol |r|.  Returns false when a step is not finite; `lastc`
+// receives |dr| of the last step.
 template <typename Tp, int n>
 __device__ __forceinline__ bool bairstow(const float (&ar)[n + 1], const float (&ai)[n + 1], Tp& rr, Tp& ri, Tp& s_r,
-                                         Tp& s_i, int iters, Tp& lastc) {
+                                         Tp& s_i, int iters, Tp& lastc, Tp tol = 0) {
     for (int it = 0; it < iters; ++it) {
         Tp b1r = 0, b1i = 0, b2r = 0, b2i = 0;     // b_{k+1}, b_{k+2}
         Tp c1r = 0, c1i = 0, c2r = 0, c2i = 0;     // c_{k+1}, c_{k+2}
@@ -387,6 +388,7 @@ __device__ __forceinline__ bool bairstow(const float (&ar)[n + 1], const float (
             return false;
         rr += drr; ri += dri; s_r += dsr; s_i += dsi;
         lastc = (drr < 0 ? -drr : drr) + (dri < 0 ? -dri : dri);
+        if (lastc <= tol * ((rr < 0 ? -rr : rr) + (ri < 0 ? -ri : ri))) break;
     }
     return true;
 }
