@@ -32,12 +32,32 @@ PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed), F
 PEAK_HBM = 8.0e12
 
 
-def flops_per_window(L: int, N: int, newton: float, iters: float) -> dict:
+def bairstow_flops(n: int) -> int:
+    """One complex Newton step on a quadratic factor of a degree-n polynomial:
+    two synthetic divisions (16 flops per coefficient each) and the 2x2 solve."""
+    return 32 * (n + 1) + 60
+
+
+def certificate_flops(L: int) -> int:
+    """Roots of the factor, mate test, deflation, scaling and the Schur-Cohn
+    recursion on the degree 2L-4 quotient (FP64)."""
+    n = 2 * L - 2
+    m = n - 2
+    schur = sum(20 * (d // 2) + 10 for d in range(1, m + 1))
+    return 60 + 16 * (n - 1) + 3 * m + schur
+
+
+def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,
+                     cert_frac: float = 0.0) -> dict:
     """Algorithmic flop count of one window of the root-MUSIC kernel.
 
-    FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` and
-    `iters` are the measured mean Newton steps (largest eigenvalue) and
-    simultaneous root iterations per window.
+    FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` is the
+    measured mean number of Newton steps for the largest eigenvalue per
+    window, `pair_iters` the mean FP64 Newton steps on the quadratic factor
+    before the certified-pair test, `cert_frac` the fraction of windows
+    finished by the certificate, and `iters` the mean simultaneous root
+    iterations of the windows whose roots were all found.  Certificate work
+    of a window that fails it is not counted.
     """
     K = N - L + 1
     n = 2 * L - 2
@@ -47,33 +67,34 @@ def flops_per_window(L: int, N: int, newton: float, iters: float) -> dict:
     newton_f = newton * 8 * L
     inverse = 6 * L + 2 * 8 * L + sum(4 * l for l in range(2, L))
     coef = 2 * L + 8 * L * (L + 1) // 2
+    common32 = lag + build_t + house + newton_f + inverse + coef + 20
+    full = 1.0 - cert_frac
     start = 4 * n + 40
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
-    fp32 = lag + build_t + house + newton_f + inverse + coef + start + aberth + select + 20
-    fp64 = 3 * ((n + 1) * 32 + 60)
+    fp32 = common32 + full * (start + aberth + select)
+    fp64 = pair_iters * bairstow_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
 
 def surrogate_flops_per_window(L: int, N: int) -> dict:
     """Algorithmic flops of one window of the surrogate kernel, counted up to
     the first point where a window can be rejected (so a lower bound for the
-    accepted ones): features, the MLP (matrix-core flops kept apart), lag
-    sums, the real transform, the power iteration, the polynomial and the
-    FP32 and FP64 quadratic-factor Newton steps.  Transcendentals (erf,
-    sincos, atan2) count as one flop."""
+    accepted ones): features, the MLP (matrix-core flops kept apart, GELU as
+    its A&S erf: 16 flops), lag sums, the real transform, the power
+    iteration, the polynomial, three FP64 Newton steps on the quadratic
+    factor and the certificate.  Transcendentals count as one flop."""
     K = N - L + 1
     n = 2 * L - 2
     feat = 4 * N + 16 * 6 + 10
     mlp_mfma = 2 * (32 * 64 + 64 * 64 + 64 * 2)
-    mlp_valu = 2 * 64 * 4 + 64 * 2 + 2
+    mlp_valu = 2 * 64 * (16 + 1) + 2
     lag = K * L * 8
     build_t = 3 * L * L + L + L * (L + 1) // 2
-    power = 6 * (2 * L * L + 3 * L + 1)
+    power = 6 * (2 * L * L + 3 * L + 1) + 2 * L
     coef = 2 * L + 8 * L * (L + 1) // 2
-    bairstow = (n + 1) * 32 + 60
-    fp32 = feat + mlp_valu + lag + build_t + power + coef + 8 * bairstow + 40
-    fp64 = 2 * bairstow
+    fp32 = feat + mlp_valu + lag + build_t + power + coef + 20
+    fp64 = 3 * bairstow_flops(n) + certificate_flops(L)
     return {"fp32": fp32, "fp64": fp64, "mfma": mlp_mfma, "valu": fp32 + fp64}
 
 
@@ -202,6 +223,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-lines", type=int, default=0,
                     help="oracle sample: lines per direction per frame (0: about 4M windows in all)")
+    ap.add_argument("--full-roots", action="store_true",
+                    help="find every root of every window (no certified-pair shortcut)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -271,7 +294,8 @@ def main():
         del src, dst
 
     def make(**kw):
-        dm = bm.Demodulator(0, max_width=maxw, max_height=maxh, max_batch_pixels=total_px, **kw)
+        dm = bm.Demodulator(0, max_width=maxw, max_height=maxh, max_batch_pixels=total_px,
+                            full_roots=args.full_roots, **kw)
         if surrogate:
             bm.bosmusic_surrogate_load(dm.h, params)
             bm.bosmusic_surrogate_config(dm.h, 0.25, 1 if args.predictor == "lag1" else 0)
@@ -330,15 +354,25 @@ def main():
         bm.bosmusic_demodulate(sdem.h, sub, mode, stream)
         ss = sdem.stats(reset=True)
         sdem.close()
-        newton = ss["eig_iters"] / max(1, ss["windows"])
-        iters = ss["root_iters"] / max(1, ss["windows"])
+        nwin = max(1, ss["windows"])
+        newton = ss["eig_iters"] / nwin
+        if surrogate:
+            # the fallback windows (the surrogate kernel's own work is modelled below)
+            iters = ss["root_iters"] / nwin
+            pair_its, cert = ss["pair_iters"] / nwin, 0.0
+        else:
+            iters = ss["root_iters"] / max(1, ss["sur_rejected"])
+            pair_its = ss["pair_iters"] / nwin
+            cert = ss["sur_accepted"] / nwin
         wins = 0
         for i in idx:
             W, H, N = fr[i].width, fr[i].height, fr[i].N
             wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
-        fl = flops_per_window(L, fr[idx[0]].N, newton, iters)
+        fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert)
         entry = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2), "root_iters": round(iters, 2),
                  "windows_per_step": wins}
+        if not surrogate:
+            entry.update({"pair_iters": round(pair_its, 2), "certified_fraction": round(cert, 5)})
         if surrogate:
             acc, rej = ss["sur_accepted"], ss["sur_rejected"]
             frac_rej = rej / max(1, acc + rej)
@@ -389,6 +423,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "frames": nf, "pixels": total_px,
                    "dirs": "xy", "mode": "surrogate" if surrogate else "plain", "graph": use_graph,
+                   "roots": "all" if args.full_roots else "certified pair, all roots where uncertified",
                    **({"predictor": args.predictor} if surrogate else {})},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -82,6 +82,8 @@ enum {
     BM_OPT_JACOBI = 4u, /* signal subspace by cyclic Jacobi instead of the tridiagonal solver */
     BM_OPT_GRAPH = 8u,  /* capture each distinct batch once into a hipGraph and replay it;
                            ignored when BM_OPT_TIMING is set */
+    BM_OPT_FULL_ROOTS = 16u, /* always find every root of the polynomial, never the
+                                certified-pair shortcut (same results up to rounding) */
 };
 
 /* per-pixel flag bits (optional output); bits 0-3 for x, 4-7 for y */
@@ -118,10 +120,14 @@ typedef struct {
 typedef struct {
     uint64_t windows;       /* windows demodulated since the last reset */
     uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI) */
-    uint64_t root_iters;    /* sum over windows of simultaneous root iterations */
+    uint64_t root_iters;    /* sum over windows of simultaneous root iterations (all-roots windows) */
     uint64_t polish_fail;   /* windows whose FP64 pair polish did not converge */
-    uint64_t sur_accepted;  /* BM_SURROGATE: windows whose surrogate estimate was accepted */
-    uint64_t sur_rejected;  /* BM_SURROGATE: windows sent to the plain fallback */
+    uint64_t sur_accepted;  /* BM_SURROGATE: windows whose surrogate estimate was accepted;
+                               BM_PLAIN: windows finished by the certified pair */
+    uint64_t sur_rejected;  /* BM_SURROGATE: windows sent to the plain fallback;
+                               BM_PLAIN: windows whose roots were all found */
+    uint64_t pair_iters;    /* sum over windows of FP64 Newton steps on the quadratic factor
+                               before the certified-pair test (BM_PLAIN) */
     uint64_t rm_launches;   /* root-MUSIC kernel launches timed (BM_OPT_TIMING) */
     uint64_t rm_time_ns;    /* their summed duration between HIP events, ns */
 } bosmusic_stats;

@@ -25,6 +25,7 @@ BM_OPT_STATS = 1
 BM_OPT_TIMING = 2
 BM_OPT_JACOBI = 4
 BM_OPT_GRAPH = 8
+BM_OPT_FULL_ROOTS = 16
 BM_FLAG_UNDEFINED, BM_FLAG_NO_POLISH = 1, 2
 
 ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "bosmusic_integrate",
@@ -49,7 +50,7 @@ class bosmusic_frame(ctypes.Structure):
 class bosmusic_stats(ctypes.Structure):
     _fields_ = [("windows", c_uint64), ("eig_iters", c_uint64), ("root_iters", c_uint64),
                 ("polish_fail", c_uint64), ("sur_accepted", c_uint64), ("sur_rejected", c_uint64),
-                ("rm_launches", c_uint64), ("rm_time_ns", c_uint64)]
+                ("pair_iters", c_uint64), ("rm_launches", c_uint64), ("rm_time_ns", c_uint64)]
 
 
 class BosmusicError(RuntimeError):
@@ -289,11 +290,12 @@ def bosmusic_get_stats(h, reset: bool = False, stream=None) -> dict:
 class Demodulator:
     def __init__(self, device: int = 0, max_width: int = 4096, max_height: int = 4096, stats: bool = False,
                  timing: bool = False, jacobi: bool = False, graph: bool = False, max_batch_pixels: int = 0,
-                 tune_cache: str | None = None):
+                 tune_cache: str | None = None, full_roots: bool = False):
         self.device = device
         self.h = bosmusic_create(device, max_width, max_height,
                                  (BM_OPT_STATS if stats else 0) | (BM_OPT_TIMING if timing else 0) |
-                                 (BM_OPT_JACOBI if jacobi else 0) | (BM_OPT_GRAPH if graph else 0),
+                                 (BM_OPT_JACOBI if jacobi else 0) | (BM_OPT_GRAPH if graph else 0) |
+                                 (BM_OPT_FULL_ROOTS if full_roots else 0),
                                  max_batch_pixels, tune_cache)
 
     def close(self):

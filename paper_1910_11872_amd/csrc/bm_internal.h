@@ -62,6 +62,7 @@ struct RmBatch {
     int njobs;
     int total;             // prefix[njobs]
     int jacobi;            // 1: cyclic Jacobi eigen-split instead of the tridiagonal solver
+    int full_roots;        // 1: always find every root (no certified-pair shortcut)
     unsigned long long* stats;  // kStatSlots x kStatFields counters, or nullptr
     RootTemplate tmpl;
 };

@@ -40,7 +40,7 @@ namespace {
 // One block of windows: BLOCK-(L-1) consecutive pixels p0.. of one line of job J.
 template <int L, int BLOCK, bool JACOBI>
 __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg, float2 (*sS)[BLOCK],
-                                                const RootTemplate& tmpl, LaneStats& ls) {
+                                                const RootTemplate& tmpl, bool full_roots, LaneStats& ls) {
     constexpr int WPB = BLOCK - (L - 1);
     const int t = threadIdx.x;
     const int N = J.N;
@@ -96,7 +96,7 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
                 R.re[i][j] = v.x;
                 R.im[i][j] = (i == j) ? 0.f : v.y;
             }
-        window_omega<L, JACOBI>(R, tmpl, omega, flag, ls);
+        window_omega<L, JACOBI>(R, tmpl, full_roots, omega, flag, ls);
     } else {
         flag |= BM_FLAG_UNDEFINED;
     }
@@ -105,19 +105,20 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
 
 template <int BLOCK>
 __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long long* stats) {
-    unsigned long long a[6] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
+    unsigned long long a[7] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
                                (unsigned long long)ls.iters, (unsigned long long)ls.pfail,
-                               (unsigned long long)ls.accepted, (unsigned long long)ls.rejected};
+                               (unsigned long long)ls.accepted, (unsigned long long)ls.rejected,
+                               (unsigned long long)ls.pair_its};
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) a[c] += __shfl_xor(a[c], off);
+        for (int c = 0; c < 7; ++c) a[c] += __shfl_xor(a[c], off);
     if ((threadIdx.x & 63) == 0) {
         // spread the counters over kStatSlots slots to avoid one hot address
         unsigned long long* sl =
             stats + kStatFields * ((blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) % kStatSlots);
 #pragma unroll
-        for (int c = 0; c < 6; ++c)
+        for (int c = 0; c < 7; ++c)
             if (a[c]) atomicAdd(sl + c, a[c]);
     }
 }
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
         const int local = w - B.prefix[j];
         const int line = local / J.bpl;
         const int bx = local - line * J.bpl;
-        rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, ls);
+        rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, B.full_roots != 0, ls);
         __syncthreads();
     }
     if (STATS) flush_stats<BLOCK>(ls, B.stats);
@@ -180,9 +181,12 @@ __global__ __launch_bounds__(kGatherBlock) void rootmusic_gather_kernel(RmBatch 
         }
         float omega = __builtin_nanf("");
         unsigned flag = 0;
-        window_omega<L, JACOBI>(R, B.tmpl, omega, flag, ls);
+        window_omega<L, JACOBI>(R, B.tmpl, B.full_roots != 0, omega, flag, ls);
         store_omega(J, line, p, omega, flag);
     }
+    // the surrogate kernel owns the accepted/rejected counters of its windows
+    ls.accepted = 0;
+    ls.rejected = 0;
     if (STATS) flush_stats<kGatherBlock>(ls, B.stats);
 }
 

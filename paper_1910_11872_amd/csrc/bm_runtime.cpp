@@ -456,6 +456,7 @@ void bind_group(bosmusic_s* h, GroupPlan& gp, const char* dev) {
         s.batch.njobs = (int)s.jobs.size();
         s.batch.total = s.prefix.back();
         s.batch.jacobi = (h->options & BM_OPT_JACOBI) ? 1 : 0;
+        s.batch.full_roots = (h->options & BM_OPT_FULL_ROOTS) ? 1 : 0;
         s.batch.stats = (h->options & BM_OPT_STATS) ? h->stats : nullptr;
         s.batch.tmpl = h->tmpl[s.L];
     }
@@ -893,6 +894,7 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             rb.njobs = (int)rj.size();
             rb.total = n;
             rb.jacobi = (h->options & BM_OPT_JACOBI) ? 1 : 0;
+            rb.full_roots = (h->options & BM_OPT_FULL_ROOTS) ? 1 : 0;
             rb.stats = nullptr;
             rb.tmpl = h->tmpl[kLabelL];
             int2* list = (int2*)(h->ds + o_list);
@@ -1080,7 +1082,7 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         if (!cfg) return fail(nullptr, BM_E_INVALID_ARG, "cfg is NULL");
         if (cfg->max_width < 1 || cfg->max_height < 1 || cfg->max_width > 65536 || cfg->max_height > 65536)
             return fail(nullptr, BM_E_INVALID_ARG, "max size %dx%d", cfg->max_width, cfg->max_height);
-        if (cfg->options & ~(uint32_t)(BM_OPT_STATS | BM_OPT_TIMING | BM_OPT_JACOBI | BM_OPT_GRAPH))
+        if (cfg->options & ~(uint32_t)(BM_OPT_STATS | BM_OPT_TIMING | BM_OPT_JACOBI | BM_OPT_GRAPH | BM_OPT_FULL_ROOTS))
             return fail(nullptr, BM_E_INVALID_ARG, "options %u", cfg->options);
         if (cfg->max_batch_pixels < 0) return fail(nullptr, BM_E_INVALID_ARG, "max_batch_pixels < 0");
         int ndev = 0;
@@ -1363,6 +1365,7 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
         out->polish_fail = v[3];
         out->sur_accepted = v[4];
         out->sur_rejected = v[5];
+        out->pair_iters = v[6];
         out->rm_launches = h->rm_launches;
         out->rm_time_ns = h->rm_time_ns;
         if (reset) h->rm_launches = h->rm_time_ns = 0;

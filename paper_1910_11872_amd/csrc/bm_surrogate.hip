@@ -30,13 +30,12 @@ namespace bm {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
 constexpr int kPowerSteps = 6;
 constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps on the quadratic factor
-constexpr double kMateTol = 1e-6;     // |z1 conj(z2) - 1| of an accepted pair
-constexpr double kCertMargin = 1e-6;  // relative radius margin of the nearest-pair certificate
 
 // C(16 x 16) += A(16 x 32) B(32 x 16) on one wave.  A(i, k) = a[i*lda + k],
 // B(k, j) = b[j*ldb + k]; both 16-byte aligned with k contiguous.  Lane l
@@ -50,7 +49,27 @@ __device__ __forceinline__ floatx4 mfma_tile(const __bf16* a, int lda, const __b
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz and Stegun, Handbook of Mathematical Functions, 7.1.26:
+// erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x), x >= 0,
+// absolute error below 1.5e-7 (plus the hardware reciprocal and exp2
+// roundings), extended as an odd function.  A GELU evaluated with it is
+// exact to well under one bfloat16 unit, the precision of the activations.
+__device__ __forceinline__ float erf_as(float x) {
+    const float a = fabsf(x);
+    const float t = frcp(fmaf(0.3275911f, a, 1.f));
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    p *= t;
+    const float e = __builtin_amdgcn_exp2f(-1.44269504088896341f * a * a);
+    return copysignf(fmaf(-p, e, 1.f), x);
+}
+
+__device__ __forceinline__ float gelu(float x) {
+    const float h = 0.5f * x;
+    return fmaf(h, erf_as(x * 0.70710678118654752f), h);
+}
 
 struct alignas(16) MlpSmem {
     __bf16 w1t[kMlpHidden * kMlpIn];
@@ -79,11 +98,12 @@ __device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __
     for (int rb = 0; rb < 4; ++rb) {
         floatx4 c = {0.f, 0.f, 0.f, 0.f};
         c = mfma_tile(s.w1t + 16 * rb * kMlpIn, kMlpIn, x, kMlpIn, c);
+        // this lane's four outputs are adjacent hidden units: one 8-byte store
+        const int hid = 16 * rb + rq;
+        bf16x4 hv;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int hid = 16 * rb + rq + q;
-            h1[col * kMlpHidden + hid] = (__bf16)gelu(c[q] + s.b1[hid]);
-        }
+        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b1[hid + q]);
+        *reinterpret_cast<bf16x4*>(h1 + col * kMlpHidden + hid) = hv;
     }
     __syncthreads();
 #pragma unroll
@@ -92,11 +112,11 @@ __device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
             c = mfma_tile(s.w2t + 16 * rb * kMlpHidden + 32 * kb, kMlpHidden, h1 + 32 * kb, kMlpHidden, c);
+        const int hid = 16 * rb + rq;
+        bf16x4 hv;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int hid = 16 * rb + rq + q;
-            h2[col * kMlpHidden + hid] = (__bf16)gelu(c[q] + s.b2[hid]);
-        }
+        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b2[hid + q]);
+        *reinterpret_cast<bf16x4*>(h2 + col * kMlpHidden + hid) = hv;
     }
     __syncthreads();
     floatx4 c = {0.f, 0.f, 0.f, 0.f};
@@ -120,48 +140,6 @@ __device__ __forceinline__ void steering_real(float w, float (&v0)[L]) {
         v0[o + a] = sc * sn;
     }
     if (L & 1) v0[m] = rsqrtf((float)L);
-}
-
-// Number of zeros of f(z) = sum_i (fr[i] + j fi[i]) z^i (formal degree m)
-// strictly inside the unit disk, by the Schur-Cohn recursion
-//     T f = conj(a_0) f - a_m f*,   f*(z) = z^m conj(f(1/conj(z))),
-// whose constant term gamma = |a_0|^2 - |a_m|^2 decides the count: when
-// gamma > 0, T f has as many zeros inside as f; when gamma < 0, as many as
-// f*, i.e. m minus those of f (Henrici, Applied and Computational Complex
-// Analysis I, Sec. 6.8).  Returns -1 when some |gamma| is too small to
-// decide, which is the case of a zero on or very near the unit circle.
-template <int m>
-__device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], double (&fi)[m + 1]) {
-    unsigned neg = 0;
-    bool ok = true;
-#pragma unroll
-    for (int d = m; d >= 1; --d) {
-        const double a0r = fr[0], a0i = fi[0], adr = fr[d], adi = fi[d];
-        const double p0 = a0r * a0r + a0i * a0i, pd = adr * adr + adi * adi;
-        const double g = p0 - pd;
-        ok = ok && (fabs(g) > 1e-9 * (p0 + pd));
-        neg |= (g < 0.0 ? 1u : 0u) << d;
-        const double sc = 1.0 / (p0 + pd);
-        // new_i = conj(a0) a_i - a_d conj(a_{d-i}), in place over the pairs (i, d-i)
-#pragma unroll
-        for (int i = 1; 2 * i <= d; ++i) {
-            const int k = d - i;
-            const double xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
-            const double nir = (a0r * xr + a0i * xi) - (adr * yr + adi * yi);
-            const double nii = (a0r * xi - a0i * xr) - (adi * yr - adr * yi);
-            const double nkr = (a0r * yr + a0i * yi) - (adr * xr + adi * xi);
-            const double nki = (a0r * yi - a0i * yr) - (adi * xr - adr * xi);
-            fr[i] = nir * sc; fi[i] = nii * sc;
-            fr[k] = nkr * sc; fi[k] = nki * sc;
-        }
-        fr[0] = g * sc;
-        fi[0] = 0.0;
-    }
-    int count = 0;
-#pragma unroll
-    for (int d = 1; d <= m; ++d)
-        if ((neg >> d) & 1u) count = d - count;
-    return ok ? count : -1;
 }
 
 // Refinement of a predicted frequency; true when the estimate is accepted.
@@ -213,39 +191,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
     double last = 0.0;
     if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last, 1e-13)) return false;
     if (!(last <= 1e-9 * (fabs(rr) + fabs(ri)))) return false;
-    // roots of the factor: (r +- sqrt(r^2 + 4 s)) / 2
-    const double dr = rr * rr - ri * ri + 4.0 * s_r, di = 2.0 * rr * ri + 4.0 * s_i;
-    const double md = sqrt(dr * dr + di * di);
-    const double qr = sqrt(fmax(0.0, 0.5 * (md + dr)));
-    const double qi = copysign(sqrt(fmax(0.0, 0.5 * (md - dr))), di);
-    const double z1r = 0.5 * (rr + qr), z1i = 0.5 * (ri + qi);
-    const double z2r = 0.5 * (rr - qr), z2i = 0.5 * (ri - qi);
-    // a conjugate-reciprocal pair: z1 conj(z2) = 1
-    const double pr = z1r * z2r + z1i * z2i, pi = z1i * z2r - z1r * z2i;
-    if (!(fabs(pr - 1.0) + fabs(pi) < kMateTol)) return false;
-    const double rin = sqrt(fmin(z1r * z1r + z1i * z1i, z2r * z2r + z2i * z2i));
-    // quotient Q(z) = P(z) / (z^2 - r z - s) (degree n - 2), scaled to Q(rho z)
-    double fr[n - 1], fi[n - 1];
-    {
-        double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
-#pragma unroll
-        for (int k = n; k >= 2; --k) {
-            const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
-            const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
-            fr[k - 2] = bkr;
-            fi[k - 2] = bki;
-            b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
-        }
-    }
-    const double rho = fmin(rin, 1.0) * (1.0 - kCertMargin);
-    double rp = 1.0;
-#pragma unroll
-    for (int k = 1; k <= n - 2; ++k) {
-        rp *= rho;
-        fr[k] *= rp;
-        fi[k] *= rp;
-    }
-    if (zeros_inside_unit_disk<n - 2>(fr, fi) != L - 2) return false;
+    if (!certified_pair<L>(ar, ai, rr, ri, s_r, s_i)) return false;
     const float w = atan2f((float)ri, (float)rr);
     omega = w;
     return finitef(w);
@@ -503,7 +449,8 @@ constexpr int kPartDW1 = 0, kPartDB1 = 2048, kPartDW2 = 2112, kPartDB2 = 6208, k
               kPartLoss = 6402, kPartStride = 6404;
 
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+    return fmaf(0.5f, erf_as(x * 0.70710678118654752f), 0.5f) +
+           x * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x);
 }
 
 struct alignas(16) TrainSmem {

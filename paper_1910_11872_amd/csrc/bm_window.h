@@ -36,6 +36,7 @@ constexpr float kJacobiTol2 = BM_JACOBI_TOL2;
 constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
 constexpr float kRootTol2 = BM_ROOT_TOL2;
 constexpr int kPolishIters = BM_POLISH_ITERS;
+constexpr int kCertIters = 8;     // at most this many FP64 Newton steps before the pair certificate
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
 constexpr int kInverseIters = BM_INVERSE_ITERS;
 
@@ -296,7 +297,7 @@ __device__ __forceinline__ void store_omega(const RmJob& J, int line, int p, flo
 
 // Counters a lane accumulates over the windows it owns.
 struct LaneStats {
-    int counted = 0, eig_its = 0, iters = 0, pfail = 0, accepted = 0, rejected = 0;
+    int counted = 0, eig_its = 0, iters = 0, pfail = 0, accepted = 0, rejected = 0, pair_its = 0;
 };
 
 // u1 = Q v for the unitary transform used by build_T.
@@ -346,11 +347,12 @@ __device__ __forceinline__ void poly_coeffs(const float (&ur)[L], const float (&
 // Newton iterations on the quadratic factor z^2 - r z - s of the polynomial
 // (complex Bairstow), in precision T: at most `iters` steps, fewer once a
 // step is below tol |r|.  Returns false when a step is not finite; `lastc`
-// receives |dr| of the last step.
+// receives |dr| of the last step; *its (optional) counts the steps.
 template <typename Tp, int n>
 __device__ __forceinline__ bool bairstow(const float (&ar)[n + 1], const float (&ai)[n + 1], Tp& rr, Tp& ri, Tp& s_r,
-                                         Tp& s_i, int iters, Tp& lastc, Tp tol = 0) {
+                                         Tp& s_i, int iters, Tp& lastc, Tp tol = 0, int* its = nullptr) {
     for (int it = 0; it < iters; ++it) {
+        if (its) ++*its;
         Tp b1r = 0, b1i = 0, b2r = 0, b2i = 0;     // b_{k+1}, b_{k+2}
         Tp c1r = 0, c1i = 0, c2r = 0, c2i = 0;     // c_{k+1}, c_{k+2}
         Tp B0r = 0, B0i = 0, B1r = 0, B1i = 0;
@@ -393,6 +395,99 @@ __device__ __forceinline__ bool bairstow(const float (&ar)[n + 1], const float (
     return true;
 }
 
+// Number of zeros of f(z) = sum_i (fr[i] + j fi[i]) z^i (formal degree m)
+// strictly inside the unit disk, by the Schur-Cohn recursion
+//     T f = conj(a_0) f - a_m f*,   f*(z) = z^m conj(f(1/conj(z))),
+// whose constant term gamma = |a_0|^2 - |a_m|^2 decides the count: when
+// gamma > 0, T f has as many zeros inside as f; when gamma < 0, as many as
+// f*, i.e. m minus those of f (Henrici, Applied and Computational Complex
+// Analysis I, Sec. 6.8).  Returns -1 when some |gamma| is too small to
+// decide, which is the case of a zero on or very near the unit circle.
+template <int m>
+__device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], double (&fi)[m + 1]) {
+    unsigned neg = 0;
+    bool ok = true;
+#pragma unroll
+    for (int d = m; d >= 1; --d) {
+        const double a0r = fr[0], a0i = fi[0], adr = fr[d], adi = fi[d];
+        const double p0 = a0r * a0r + a0i * a0i, pd = adr * adr + adi * adi;
+        const double g = p0 - pd;
+        ok = ok && (fabs(g) > 1e-9 * (p0 + pd));
+        neg |= (g < 0.0 ? 1u : 0u) << d;
+        const double sc = __builtin_amdgcn_rcp(p0 + pd);   // any positive scale: only signs are read
+        // new_i = conj(a0) a_i - a_d conj(a_{d-i}), in place over the pairs (i, d-i)
+#pragma unroll
+        for (int i = 1; 2 * i <= d; ++i) {
+            const int k = d - i;
+            const double xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
+            const double nir = (a0r * xr + a0i * xi) - (adr * yr + adi * yi);
+            const double nii = (a0r * xi - a0i * xr) - (adi * yr - adr * yi);
+            const double nkr = (a0r * yr + a0i * yi) - (adr * xr + adi * xi);
+            const double nki = (a0r * yi - a0i * yr) - (adi * xr - adr * xi);
+            fr[i] = nir * sc; fi[i] = nii * sc;
+            fr[k] = nkr * sc; fi[k] = nki * sc;
+        }
+        fr[0] = g * sc;
+        fi[0] = 0.0;
+    }
+    int count = 0;
+#pragma unroll
+    for (int d = 1; d <= m; ++d)
+        if ((neg >> d) & 1u) count = d - count;
+    return ok ? count : -1;
+}
+
+
+constexpr double kMateTol = 1e-6;     // |z1 conj(z2) - 1| of a certified pair
+constexpr double kCertMargin = 1e-6;  // relative radius margin of the nearest-pair certificate
+
+// True when the converged quadratic factor z^2 - r z - s of the root-MUSIC
+// polynomial (coefficients ar, ai; paper Eq. 12) holds the root pair nearest
+// the unit circle, i.e. the pair the selection rule of Sec. 3 picks from all
+// roots.  Every root of this polynomial has its mate 1/conj(z) (c_{-k} =
+// conj(c_k)), so the nearest pair is the one with the largest inner radius:
+// the factor's roots must be such a pair, z1 conj(z2) = 1, and the quotient
+// Q = P / (z^2 - r z - s) must have all its L - 2 inner roots strictly inside
+// |z| < |z_in| (1 - margin), counted by Schur-Cohn on Q(rho z).
+template <int L>
+__device__ __forceinline__ bool certified_pair(const float (&ar)[2 * L - 1], const float (&ai)[2 * L - 1], double rr,
+                                               double ri, double s_r, double s_i) {
+    constexpr int n = 2 * L - 2;
+    // roots of the factor: (r +- sqrt(r^2 + 4 s)) / 2
+    const double dr = rr * rr - ri * ri + 4.0 * s_r, di = 2.0 * rr * ri + 4.0 * s_i;
+    const double md = sqrt(dr * dr + di * di);
+    const double qr = sqrt(fmax(0.0, 0.5 * (md + dr)));
+    const double qi = copysign(sqrt(fmax(0.0, 0.5 * (md - dr))), di);
+    const double z1r = 0.5 * (rr + qr), z1i = 0.5 * (ri + qi);
+    const double z2r = 0.5 * (rr - qr), z2i = 0.5 * (ri - qi);
+    const double pr = z1r * z2r + z1i * z2i, pi = z1i * z2r - z1r * z2i;
+    if (!(fabs(pr - 1.0) + fabs(pi) < kMateTol)) return false;
+    if (L == 2) return true;                       // no other roots
+    const double rin = sqrt(fmin(z1r * z1r + z1i * z1i, z2r * z2r + z2i * z2i));
+    // quotient by synthetic division, then Q(rho z)
+    double fr[n - 1], fi[n - 1];
+    {
+        double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
+#pragma unroll
+        for (int k = n; k >= 2; --k) {
+            const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
+            const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
+            fr[k - 2] = bkr;
+            fi[k - 2] = bki;
+            b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
+        }
+    }
+    const double rho = fmin(rin, 1.0) * (1.0 - kCertMargin);
+    double rp = 1.0;
+#pragma unroll
+    for (int k = 1; k <= n - 2; ++k) {
+        rp *= rho;
+        fr[k] *= rp;
+        fi[k] *= rp;
+    }
+    return zeros_inside_unit_disk<n - 2>(fr, fi) == L - 2;
+}
+
 // Trace-normalised T = Q^H R_fb Q from the covariance; false when R is zero
 // or not finite (no signal subspace).
 template <int L>
@@ -415,8 +510,8 @@ __device__ __forceinline__ bool normalised_T(const Cov<L>& R, Sym<L>& T) {
 // FP64 pair polish.  omega stays NaN and BM_FLAG_UNDEFINED is set when the
 // covariance is zero or not finite.
 template <int L, bool JACOBI>
-__device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, float& omega,
-                                             unsigned& flag, LaneStats& ls) {
+__device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots,
+                                             float& omega, unsigned& flag, LaneStats& ls) {
     constexpr int n = 2 * L - 2;
     Sym<L> T;
     if (!normalised_T<L>(R, T)) {
@@ -434,11 +529,30 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     float ar[n + 1], ai[n + 1];
     poly_coeffs<L>(ur, ui, ar, ai);
 
-    // ---- Aberth-Ehrlich in FP32 -------------------------------------------
     // frequency guess: u1[i+1]/u1[i] ~ e^{j w}, so c_1 ~ -((L-1)/L) e^{-j w}
     const float w0 = atan2f(ai[L], -ar[L]);
     float sw0, cw0;
     sincosf(w0, &sw0, &cw0);
+
+    // ---- certified pair ---------------------------------------------------
+    // FP64 Newton on the quadratic factor holding the double root e^{j w0};
+    // when the factor is certified as the pair nearest the unit circle it is
+    // the pair the selection rule picks from all roots, and its sum gives
+    // omega exactly as below.  Otherwise every root is found.
+    bool cert = false;
+    if (!full_roots) {
+        double rr = 2.0 * cw0, ri = 2.0 * sw0;
+        double s_r = -((double)cw0 * cw0 - (double)sw0 * sw0), s_i = -2.0 * (double)cw0 * sw0;
+        double lastc = 0.0;
+        cert = bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kCertIters, lastc, 1e-13, &ls.pair_its) &&
+               lastc <= 1e-9 * (fabs(rr) + fabs(ri)) && certified_pair<L>(ar, ai, rr, ri, s_r, s_i);
+        if (cert) omega = atan2f((float)ri, (float)rr);
+    }
+    ls.accepted += cert ? 1 : 0;
+    ls.rejected += (!full_roots && !cert) ? 1 : 0;
+    if (cert) return;
+
+    // ---- Aberth-Ehrlich in FP32 -------------------------------------------
     float zr[n], zi[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {

@@ -47,6 +47,38 @@ def test_version_and_status_strings():
     assert pkg.bosmusic_status_string(12345) == "unknown status"
 
 
+def test_struct_layout_matches_compiled_header(tmp_path):
+    """The ctypes structures have the sizes and offsets a C compiler gives the header."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pkg, _ = _lib()
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"bosmusic.h\"\n"
+        "#define F(T, m) printf(\"%s.%s %zu\\n\", #T, #m, offsetof(T, m));\n"
+        "int main(void) {\n"
+        "  printf(\"bosmusic_frame %zu\\n\", sizeof(bosmusic_frame));\n"
+        "  printf(\"bosmusic_config %zu\\n\", sizeof(bosmusic_config));\n"
+        "  printf(\"bosmusic_stats %zu\\n\", sizeof(bosmusic_stats));\n"
+        + "".join(f"  F({t}, {m})\n" for t, cls in (("bosmusic_frame", pkg.bosmusic_frame),
+                                                    ("bosmusic_config", pkg.bosmusic_config),
+                                                    ("bosmusic_stats", pkg.bosmusic_stats))
+                  for m, _ in cls._fields_)
+        + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for t, cls in (("bosmusic_frame", pkg.bosmusic_frame), ("bosmusic_config", pkg.bosmusic_config),
+                   ("bosmusic_stats", pkg.bosmusic_stats)):
+        assert int(got[t]) == ctypes.sizeof(cls), t
+        for m, _ in cls._fields_:
+            assert int(got[f"{t}.{m}"]) == getattr(cls, m).offset, (t, m)
+
+
 def test_struct_layout_matches_header():
     pkg, _ = _lib()
     # bosmusic_frame: pointer, 3 x int32, int64, 2 x int32, uint32, 3 pointers
@@ -55,7 +87,7 @@ def test_struct_layout_matches_header():
     assert pkg.bosmusic_frame.omega_x.offset == 48
     assert ctypes.sizeof(pkg.bosmusic_config) == 32
     assert pkg.bosmusic_config.tune_cache.offset == 24
-    assert ctypes.sizeof(pkg.bosmusic_stats) == 64
+    assert ctypes.sizeof(pkg.bosmusic_stats) == 72
 
 
 def test_null_arguments_are_rejected_without_device_work():

@@ -241,7 +241,9 @@ def test_stats_count_windows(dem, torch):
     nx = 20 * (300 - 20 + 1)
     ny = 300 * (20 - 20 + 1)
     assert s["windows"] == nx + ny
-    assert s["eig_iters"] >= s["windows"] and s["root_iters"] >= s["windows"]
+    assert s["eig_iters"] >= s["windows"]
+    assert s["sur_accepted"] + s["sur_rejected"] == s["windows"]        # certified pair or all roots
+    assert s["pair_iters"] >= s["windows"] and s["root_iters"] >= s["sur_rejected"]
     print(s)
 
 
@@ -302,3 +304,29 @@ def test_jacobi_option_agrees_with_default_solver(bm, torch):
     assert np.isfinite(ox).any()
     dj.close()
     dt.close()
+
+
+@pytest.mark.parametrize("L,N,snr", [(2, 8, 10.0), (4, 12, 0.0), (6, 32, 10.0), (8, 32, 3.0), (8, 64, 20.0)])
+def test_certified_pair_agrees_with_all_roots(bm, torch, L, N, snr):
+    """The certified-pair shortcut returns the pair that finding every root selects;
+    both agree with the oracle, and most windows take the shortcut."""
+    img_np = wl.random_frame(520, 36, seed=10 * L + N, snr_db=snr)
+    img = to_dev(torch, img_np)
+    dc = bm.Demodulator(0, max_width=1024, max_height=1024, stats=True)
+    df = bm.Demodulator(0, max_width=1024, max_height=1024, stats=True, full_roots=True)
+    a = dc.demodulate(img, L, N, "xy")
+    b = df.demodulate(img, L, N, "xy")
+    torch.cuda.synchronize()
+    sc, sf = dc.stats(), df.stats()
+    assert sf["sur_accepted"] == 0 and sf["sur_rejected"] == 0
+    assert sc["sur_accepted"] + sc["sur_rejected"] == sc["windows"]
+    ref = oracle.demodulate(img_np, L, N, "xy")
+    for u, v, o, name in zip(a, b, ref, "xy"):
+        u, v = u.cpu().numpy(), v.cpu().numpy()
+        compare_omega(u, v, f"certified vs all roots L{L} {name}")
+        compare_omega(u, o, f"certified vs oracle L{L} {name}")
+    frac = sc["sur_accepted"] / max(1, sc["windows"])
+    print(f"L{L} N{N} {snr} dB: certified {frac:.4f} of {sc['windows']} windows")
+    assert frac > (0.5 if snr < 5 else 0.9)
+    dc.close()
+    df.close()

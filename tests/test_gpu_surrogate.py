@@ -55,7 +55,7 @@ def test_surrogate_maps_match_oracle(bm, torch, predictor):
     d = bm.Demodulator(0, max_width=1024, max_height=1024, stats=True)
     if predictor == 0:
         bm.bosmusic_surrogate_load(d.h, S.init_params(3))
-    bm.bosmusic_surrogate_config(d.h, 1e-3, predictor)
+    bm.bosmusic_surrogate_config(d.h, 0.25, predictor)
     for (W, H, L, N, snr) in [(600, 48, 8, 32, 10.0), (512, 40, 6, 24, 5.0), (300, 64, 4, 16, 15.0)]:
         img = wl.random_frame(W, H, seed=L + W, snr_db=snr)
         wx, wy = d.demodulate(torch.from_numpy(img).cuda(), L, N, "xy", mode=bm.BM_SURROGATE)
@@ -77,7 +77,7 @@ def test_surrogate_graph_replays_match_eager(bm, torch):
     eager = bm.Demodulator(0, max_width=1024, max_height=1024)
     graph = bm.Demodulator(0, max_width=1024, max_height=1024, graph=True)
     for h in (eager.h, graph.h):
-        bm.bosmusic_surrogate_config(h, 1e-3, 1)
+        bm.bosmusic_surrogate_config(h, 0.25, 1)
     img = torch.from_numpy(wl.random_frame(600, 64, seed=2, snr_db=8.0)).cuda()
     wx = torch.empty((64, 600), device="cuda")
     wy = torch.empty((64, 600), device="cuda")
