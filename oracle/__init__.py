@@ -26,4 +26,6 @@ from .rootmusic import (  # noqa: F401
     valid_range,
     to_complex_field,
     analytic_mask,
+    block_covariances,
+    demodulate_block,
 )

@@ -51,6 +51,16 @@ Readings of points the paper leaves open (each also listed in the design notes):
       subtracted from each sample.  NaN outside the valid region.
   R7  A window whose covariance is identically zero (or non-finite) has no
       signal subspace; its omega is NaN.
+  R8  Block mode (the paper's own window, Sec. 3): the block of pixel (y, x)
+      is the M x M patch Gamma[y-h .. y-h+M-1, x-h .. x-h+M-1], h = floor(M/2)
+      (centred for odd M = 2L+1 in the paper's notation), valid iff it fits.
+      Gamma is the row-wise analytic signal of R1 (the paper forms one complex
+      fringe field for the block; the row-wise one-sided mask is the 2-D
+      half-plane mask k_x > 0).  R_y = B B^H / M (the block's columns are the
+      snapshots, Eq. 4) gives z_y and omega_y = arg(z_y); R_x = B^H B / M (the
+      autocorrelation E{Gamma^H Gamma}) gives z_x and omega_x = -arg(z_x)
+      (Eq. 15).  FB averaging (R4) and the pair form of R5 are applied as in
+      the line mode.
 """
 from __future__ import annotations
 
@@ -268,6 +278,56 @@ def demodulate(frame: np.ndarray, L: int, N: int, dirs: str = "xy", fb: bool = T
     if "y" in dirs:
         g = to_complex_field(frame, 0)
         wy = demod_lines(g.T, L, N, fb=fb).T
+    return wx, wy
+
+
+# ---------------------------------------------------------------------------
+# Block mode: the paper's M x M moving window (Sec. 3, Eq. 4-15; reading R8)
+# ---------------------------------------------------------------------------
+def block_covariances(gamma: np.ndarray, M: int):
+    """R_y = B B^H / M and R_x = B^H B / M for every block that fits.
+
+    gamma: (H, W) complex.  Returns (R_y, R_x), each (H-M+1, W-M+1, M, M);
+    entry [a, b] belongs to the block whose top-left sample is gamma[a, b],
+    i.e. to pixel (a + M//2, b + M//2).
+    """
+    B = sliding_window_view(gamma, (M, M))            # B[a, b, i, j] = gamma[a+i, b+j]
+    Ry = np.einsum("...ij,...kj->...ik", B, B.conj()) / M
+    Rx = np.einsum("...ri,...rk->...ik", B.conj(), B) / M
+    return Ry, Rx
+
+
+def _omega_from_cov(R: np.ndarray, fb: bool) -> np.ndarray:
+    """Steps a4..a8 for covariances (n, M, M): pair-form angle, NaN if degenerate."""
+    if fb:
+        R = fb_average(R)
+    tr = np.real(np.trace(R, axis1=-2, axis2=-1))
+    ok = np.isfinite(tr) & (tr > 0)
+    out = np.full(R.shape[0], np.nan)
+    if np.any(ok):
+        C, _ = noise_projector(R[ok])
+        out[ok] = select_root_pair(poly_roots(poly_coeffs(C)))["omega"]
+    return out
+
+
+def demodulate_block(frame: np.ndarray, M: int, dirs: str = "xy", fb: bool = True, chunk: int = 16384):
+    """Block-mode demodulation: (omega_x or None, omega_y or None), NaN where the block does not fit."""
+    g = to_complex_field(frame, 1)
+    H, W = g.shape
+    wx = np.full((H, W), np.nan) if "x" in dirs else None
+    wy = np.full((H, W), np.nan) if "y" in dirs else None
+    if M > H or M > W:
+        return wx, wy
+    h = M // 2
+    nr, nc = H - M + 1, W - M + 1
+    for r0 in range(0, nr, max(1, chunk // nc)):
+        r1 = min(nr, r0 + max(1, chunk // nc))
+        Ry, Rx = block_covariances(g[r0:r1 + M - 1], M)
+        if wy is not None:
+            wy[r0 + h:r1 + h, h:h + nc] = _omega_from_cov(Ry.reshape(-1, M, M), fb).reshape(r1 - r0, nc)
+        if wx is not None:
+            # z_x = e^{-j omega_x}: omega_x = -arg(z_x)  (Eq. 15)
+            wx[r0 + h:r1 + h, h:h + nc] = -_omega_from_cov(Rx.reshape(-1, M, M), fb).reshape(r1 - r0, nc)
     return wx, wy
 
 
