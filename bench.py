@@ -48,7 +48,7 @@ def certificate_flops(L: int) -> int:
 
 
 def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,
-                     cert_frac: float = 0.0) -> dict:
+                     cert_frac: float = 0.0, block: bool = False) -> dict:
     """Algorithmic flop count of one window of the root-MUSIC kernel.
 
     FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` is the
@@ -57,11 +57,16 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     before the certified-pair test, `cert_frac` the fraction of windows
     finished by the certificate, and `iters` the mean simultaneous root
     iterations of the windows whose roots were all found.  Certificate work
-    of a window that fails it is not counted.
+    of a window that fails it is not counted.  `block`: the L x L block
+    window, whose covariance is summed directly from its L snapshots.
     """
     K = N - L + 1
     n = 2 * L - 2
-    lag = K * L * 8                                   # lag sums, complex MAC = 4 FMA
+    if block:
+        # block window: L snapshots, upper triangle of L x L complex products each
+        lag = L * (L * (L + 1) // 2 * 8 - 4 * L)
+    else:
+        lag = K * L * 8                               # lag sums, complex MAC = 4 FMA
     build_t = 3 * L * L + L + L * (L + 1) // 2        # T from R, trace normalisation
     house = sum(2 * l * l + 2 * l * (l + 1) + 9 * l for l in range(2, L))
     newton_f = newton * 8 * L
@@ -223,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-lines", type=int, default=0,
                     help="oracle sample: lines per direction per frame (0: about 4M windows in all)")
+    ap.add_argument("--block", type=int, default=0,
+                    help="use the paper's M x M block window with this M (L = N = M) instead of line windows")
     ap.add_argument("--full-roots", action="store_true",
                     help="find every root of every window (no certified-pair shortcut)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -233,6 +240,8 @@ def main():
               "see the sharding notes in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
 
+    if args.block:
+        args.no_cpu = True          # the oracle sample below is of line windows
     t_gen = time.perf_counter()
     fr, desc = workload(args.workload, args.frames)
     frames = [f.data for f in fr]
@@ -269,7 +278,13 @@ def main():
     wx = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in frames]
     wy = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in frames]
     phi = [torch.empty(f.shape, dtype=torch.float64, device=dev) for f in frames]
-    specs = [bm.FrameSpec(d_frames[i], fr[i].L, fr[i].N, bm.BM_DIR_X | bm.BM_DIR_Y, wx[i], wy[i]) for i in range(nf)]
+    if args.block:
+        for f in fr:
+            f.L = f.N = args.block
+        desc += f"; the paper's {args.block}x{args.block} block window instead of line windows"
+    bdir = bm.BM_BLOCK if args.block else 0
+    specs = [bm.FrameSpec(d_frames[i], fr[i].L, fr[i].N, bm.BM_DIR_X | bm.BM_DIR_Y | bdir, wx[i], wy[i])
+             for i in range(nf)]
     use_graph = args.workload == "cfg3"
     tuned = {}
     if use_graph:
@@ -367,8 +382,11 @@ def main():
         wins = 0
         for i in idx:
             W, H, N = fr[i].width, fr[i].height, fr[i].N
-            wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
-        fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert)
+            if args.block:
+                wins += 2 * max(0, W - N + 1) * max(0, H - N + 1)
+            else:
+                wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
+        fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert, block=bool(args.block))
         entry = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2), "root_iters": round(iters, 2),
                  "windows_per_step": wins}
         if not surrogate:

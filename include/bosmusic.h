@@ -69,8 +69,17 @@ enum {
     BM_C32 = 4, /* interleaved complex float: Gamma of Eq. 1 given directly */
 };
 
-/* directions */
-enum { BM_DIR_X = 1u, BM_DIR_Y = 2u };
+/* directions, and the window shape */
+enum {
+    BM_DIR_X = 1u,
+    BM_DIR_Y = 2u,
+    /* The paper's own window (Sec. 3): the L x L block of the row-wise analytic
+     * signal around the pixel (rows and columns y-floor(L/2) .., x-floor(L/2) ..,
+     * valid iff it fits), whose L columns are the snapshots for omega_y and whose
+     * L rows are the snapshots for omega_x (Eq. 4, 12-15; omega_x = -arg(z_x) of
+     * the paper's E{Gamma^H Gamma} form).  Requires N == L; only BM_PLAIN. */
+    BM_BLOCK = 4u,
+};
 
 /* demodulation modes */
 enum { BM_PLAIN = 0, BM_SURROGATE = 1 };
@@ -111,7 +120,7 @@ typedef struct {
     int64_t row_stride; /* elements between row starts, >= width */
     int32_t L;          /* covariance size, 2 <= L <= 8 */
     int32_t N;          /* window length, L <= N <= 64 */
-    uint32_t dirs;      /* BM_DIR_X | BM_DIR_Y, nonzero */
+    uint32_t dirs;      /* BM_DIR_X and/or BM_DIR_Y, optionally | BM_BLOCK */
     float* omega_x;     /* width*height, row stride = width; required iff BM_DIR_X */
     float* omega_y;     /* width*height, row stride = width; required iff BM_DIR_Y */
     uint8_t* flags;     /* optional width*height flag bytes (BM_FLAG_*), or NULL */

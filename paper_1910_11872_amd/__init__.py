@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libbosmusic.so")
 
 BM_OK, BM_E_INVALID_ARG, BM_E_UNSUPPORTED, BM_E_NOMEM, BM_E_DEVICE = 0, -1, -2, -3, -4
 BM_F16, BM_F32, BM_F64, BM_C32 = 1, 2, 3, 4
-BM_DIR_X, BM_DIR_Y = 1, 2
+BM_DIR_X, BM_DIR_Y, BM_BLOCK = 1, 2, 4
 BM_PLAIN, BM_SURROGATE = 0, 1
 BM_OPT_STATS = 1
 BM_OPT_TIMING = 2
@@ -310,11 +310,13 @@ class Demodulator:
             pass
 
     def demodulate(self, frame, L: int, N: int, dirs: str = "xy", flags: bool = False, stream=None,
-                   mode: int = BM_PLAIN):
-        """Returns (omega_x or None, omega_y or None[, flags]) for one device frame."""
+                   mode: int = BM_PLAIN, block: bool = False):
+        """Returns (omega_x or None, omega_y or None[, flags]) for one device frame.
+
+        block=True: the paper's L x L block window (N must equal L)."""
         import torch
         H, W = frame.shape
-        d = (BM_DIR_X if "x" in dirs else 0) | (BM_DIR_Y if "y" in dirs else 0)
+        d = (BM_DIR_X if "x" in dirs else 0) | (BM_DIR_Y if "y" in dirs else 0) | (BM_BLOCK if block else 0)
         wx = torch.empty((H, W), dtype=torch.float32, device=frame.device) if "x" in dirs else None
         wy = torch.empty((H, W), dtype=torch.float32, device=frame.device) if "y" in dirs else None
         fl = torch.empty((H, W), dtype=torch.uint8, device=frame.device) if flags else None

@@ -39,7 +39,7 @@ namespace {
 
 // One block of windows: BLOCK-(L-1) consecutive pixels p0.. of one line of job J.
 template <int L, int BLOCK, bool JACOBI>
-__device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg, float2 (*sS)[BLOCK],
+__device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg, float2 (*sS)[BLOCK + L],
                                                 const RootTemplate& tmpl, bool full_roots, LaneStats& ls) {
     constexpr int WPB = BLOCK - (L - 1);
     const int t = threadIdx.x;
@@ -103,6 +103,80 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
     if (inside_line) store_omega(J, line, p, omega, flag);
 }
 
+
+// One block of pixels p0 .. p0+BLOCK-L of line `line` in block mode (the
+// paper's L x L moving window, Sec. 3): the rows line-h .. line-h+L-1 of the
+// window columns p0-h .. are staged in LDS, and each lane sums its L x L
+// block's snapshots -- the block's rows (RM_BLOCK_X: omega_x) or its columns
+// (RM_BLOCK_Y: omega_y) -- into R = sum_k s_k s_k^H (Eq. 4).  With snapshots
+// read in increasing x (or y), omega = +arg of the selected root in both
+// directions, the paper's -arg(z_x) for its E{Gamma^H Gamma} form.
+template <int L, int BLOCK, bool JACOBI>
+__device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int p0, float2 (*sR)[BLOCK + L],
+                                                  const RootTemplate& tmpl, bool full_roots, LaneStats& ls) {
+    constexpr int WPB = BLOCK - (L - 1);
+    constexpr int h = L / 2;
+    const int t = threadIdx.x;
+    const int len = J.len, nl = J.nlines;
+    const int c0 = p0 - h, r0 = line - h;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int r = r0 + i;
+        const bool rin = r >= 0 && r < nl;
+        const float2* g = J.gamma + (int64_t)(rin ? r : 0) * J.gamma_ls;
+        for (int c = t; c < BLOCK + L - 1; c += BLOCK) {
+            const int q = c0 + c;
+            sR[i][c] = (rin && q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();
+    const int p = p0 + t;
+    const bool inside_line = (t < WPB) && (p < len);
+    const bool valid = inside_line && (c0 + t >= 0) && (c0 + t + L <= len) && (r0 >= 0) && (r0 + L <= nl);
+    float omega = __builtin_nanf("");
+    unsigned flag = 0;
+    if (valid) {
+        Cov<L> R;
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int j = i; j < L; ++j) { R.re[i][j] = 0.f; R.im[i][j] = 0.f; }
+        if (J.kind == RM_BLOCK_Y) {
+            // snapshots: the block's columns, s_k[i] = G[r0+i][c0+t+k]
+            for (int k = 0; k < L; ++k) {
+                float2 v[L];
+#pragma unroll
+                for (int i = 0; i < L; ++i) v[i] = sR[i][t + k];
+#pragma unroll
+                for (int i = 0; i < L; ++i)
+#pragma unroll
+                    for (int j = i; j < L; ++j) {
+                        R.re[i][j] = fmaf(v[i].x, v[j].x, fmaf(v[i].y, v[j].y, R.re[i][j]));
+                        if (i != j) R.im[i][j] = fmaf(v[i].y, v[j].x, fmaf(-v[i].x, v[j].y, R.im[i][j]));
+                    }
+            }
+        } else {
+            // snapshots: the block's rows, s_k[i] = G[r0+k][c0+t+i]
+            for (int k = 0; k < L; ++k) {
+                float2 v[L];
+#pragma unroll
+                for (int i = 0; i < L; ++i) v[i] = sR[k][t + i];
+#pragma unroll
+                for (int i = 0; i < L; ++i)
+#pragma unroll
+                    for (int j = i; j < L; ++j) {
+                        R.re[i][j] = fmaf(v[i].x, v[j].x, fmaf(v[i].y, v[j].y, R.re[i][j]));
+                        if (i != j) R.im[i][j] = fmaf(v[i].y, v[j].x, fmaf(-v[i].x, v[j].y, R.im[i][j]));
+                    }
+            }
+        }
+        window_omega<L, JACOBI>(R, tmpl, full_roots, omega, flag, ls);
+    } else {
+        flag |= BM_FLAG_UNDEFINED;
+    }
+    if (inside_line) store_omega(J, line, p, omega, flag);
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long long* stats) {
     unsigned long long a[7] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
@@ -127,11 +201,11 @@ __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long l
 // block (w - prefix[j]) of job j, i.e. line (w - prefix[j]) / bpl and window
 // block (w - prefix[j]) % bpl.  A grid of one block per item runs each item
 // once; a smaller (persistent) grid walks the list.
-template <int L, int BLOCK, bool STATS, bool JACOBI>
+template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN>
 __global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
     constexpr int WPB = BLOCK - (L - 1);
     __shared__ float2 sg[BLOCK + kMaxN];
-    __shared__ float2 sS[L][BLOCK];
+    __shared__ float2 sS[L][BLOCK + L];   // lag sums (line windows) or staged rows (block windows)
     LaneStats ls;
     for (int w = blockIdx.x; w < B.total; w += gridDim.x) {
         const int j = find_job(B.prefix, B.njobs, w);
@@ -139,7 +213,12 @@ __global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
         const int local = w - B.prefix[j];
         const int line = local / J.bpl;
         const int bx = local - line * J.bpl;
-        rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, B.full_roots != 0, ls);
+        // line and block windows are separate instantiations, so that neither
+        // pays the other's registers
+        if (BLOCKWIN)
+            rootmusic_block2d<L, BLOCK, JACOBI>(J, line, bx * WPB, sS, B.tmpl, B.full_roots != 0, ls);
+        else
+            rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, B.full_roots != 0, ls);
         __syncthreads();
     }
     if (STATS) flush_stats<BLOCK>(ls, B.stats);
@@ -193,14 +272,25 @@ __global__ __launch_bounds__(kGatherBlock) void rootmusic_gather_kernel(RmBatch 
 template <int L, int BLOCK, bool JACOBI>
 hipError_t launch_LBJ(const RmBatch& b, int grid, hipStream_t s) {
     if (b.stats)
-        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, true, JACOBI>), dim3(grid), dim3(BLOCK), 0, s, b);
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, true, JACOBI, false>), dim3(grid), dim3(BLOCK), 0, s, b);
     else
-        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI>), dim3(grid), dim3(BLOCK), 0, s, b);
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI, false>), dim3(grid), dim3(BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+// Block windows: 256 lanes per block.
+template <int L, bool JACOBI>
+hipError_t launch_block_LJ(const RmBatch& b, int grid, hipStream_t s) {
+    if (b.stats)
+        hipLaunchKernelGGL((rootmusic_kernel<L, 256, true, JACOBI, true>), dim3(grid), dim3(256), 0, s, b);
+    else
+        hipLaunchKernelGGL((rootmusic_kernel<L, 256, false, JACOBI, true>), dim3(grid), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_L(const RmBatch& b, int block, int grid, hipStream_t s) {
+    if (b.block_windows) return b.jacobi ? launch_block_LJ<L, true>(b, grid, s) : launch_block_LJ<L, false>(b, grid, s);
     if (block == 128)
         return b.jacobi ? launch_LBJ<L, 128, true>(b, grid, s) : launch_LBJ<L, 128, false>(b, grid, s);
     return b.jacobi ? launch_LBJ<L, 256, true>(b, grid, s) : launch_LBJ<L, 256, false>(b, grid, s);

@@ -225,14 +225,18 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
     if (f.row_stride < f.width) return fail(h, BM_E_INVALID_ARG, "frame %d: row_stride < width", idx);
     if (f.L < 2 || f.L > bm::kMaxL) return fail(h, BM_E_INVALID_ARG, "frame %d: L=%d outside 2..8", idx, f.L);
     if (f.N < f.L || f.N > bm::kMaxN) return fail(h, BM_E_INVALID_ARG, "frame %d: N=%d outside L..64", idx, f.N);
-    if (f.dirs == 0 || (f.dirs & ~3u)) return fail(h, BM_E_INVALID_ARG, "frame %d: dirs=%u", idx, f.dirs);
+    if ((f.dirs & 3u) == 0 || (f.dirs & ~(3u | BM_BLOCK)))
+        return fail(h, BM_E_INVALID_ARG, "frame %d: dirs=%u", idx, f.dirs);
+    if ((f.dirs & BM_BLOCK) && f.N != f.L)
+        return fail(h, BM_E_INVALID_ARG, "frame %d: block windows need N == L (got L=%d, N=%d)", idx, f.L, f.N);
     if ((f.dirs & BM_DIR_X) && !f.omega_x) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_x is NULL", idx);
     if ((f.dirs & BM_DIR_Y) && !f.omega_y) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_y is NULL", idx);
     if (f.dtype != BM_C32) {
-        if ((f.dirs & BM_DIR_X) && !factors_235(f.width))
+        // block windows use the row-wise analytic signal for both directions
+        if (((f.dirs & BM_DIR_X) || (f.dirs & BM_BLOCK)) && !factors_235(f.width))
             return fail(h, BM_E_UNSUPPORTED, "frame %d: width %d is not 2^a 3^b 5^c <= %d", idx, f.width,
                         bm::kMaxFFT);
-        if ((f.dirs & BM_DIR_Y) && !factors_235(f.height))
+        if ((f.dirs & BM_DIR_Y) && !(f.dirs & BM_BLOCK) && !factors_235(f.height))
             return fail(h, BM_E_UNSUPPORTED, "frame %d: height %d is not 2^a 3^b 5^c <= %d", idx, f.height,
                         bm::kMaxFFT);
     }
@@ -241,11 +245,12 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
 
 size_t frame_ws_bytes(const bosmusic_frame& f) {
     const size_t px = (size_t)f.width * (size_t)f.height;
+    if (f.dirs & BM_BLOCK) return f.dtype != BM_C32 ? align_up(px * sizeof(float2), 256) : 0;
     size_t b = 0;
     if ((f.dirs & BM_DIR_X) && f.dtype != BM_C32) b += align_up(px * sizeof(float2), 256);
     if (f.dirs & BM_DIR_Y) {
         b += align_up(px * sizeof(float2), 256);
-        if (f.dtype != BM_C32) b += align_up(px * sizeof(float), 256);
+        b += align_up(px * sizeof(float), 256);   // transposed real frame, then the omega_y scratch
     }
     return b;
 }
@@ -256,6 +261,7 @@ size_t frame_ws_bytes(const bosmusic_frame& f) {
 struct RmSet {
     int L = 0;
     bool y_pass = false;            // second launch for y jobs (flags are OR-ed after x)
+    bool block_win = false;         // block-window jobs (their own kernel instantiation)
     std::vector<bm::RmJob> jobs;
     std::vector<int> prefix;
     size_t jobs_off = 0, prefix_off = 0;
@@ -290,13 +296,15 @@ size_t append(std::vector<char>& blob, const std::vector<T>& v) {
 
 bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1, int mode, GroupPlan& gp) {
     size_t cur = 0;
-    std::map<std::pair<int, int>, RmSet> sets;   // (L, pass) -> set
+    std::map<std::pair<int, int>, RmSet> sets;   // (L, pass + 2 * block) -> set
     bool any_flags = false;
     for (int i = i0; i < i1; ++i) any_flags |= frames[i].flags != nullptr;
     auto add_rm = [&](int L, bool ypass, const bm::RmJob& jb) {
-        RmSet& s = sets[{L, ypass ? 1 : 0}];
+        const bool blk = jb.kind != bm::RM_LINE;
+        RmSet& s = sets[{L, (ypass ? 1 : 0) + (blk ? 2 : 0)}];
         s.L = L;
         s.y_pass = ypass;
+        s.block_win = blk;
         s.jobs.push_back(jb);
     };
     for (int i = i0; i < i1; ++i) {
@@ -305,6 +313,47 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         const int W = f.width, H = f.height;
         const size_t px = (size_t)W * (size_t)H;
         bm_status st;
+        if (f.dirs & BM_BLOCK) {
+            // the paper's block window: one row-wise analytic signal serves both directions
+            const float2* gam = (const float2*)f.data;
+            int64_t gls = f.row_stride;
+            if (e != bm::Elem::C32) {
+                float2* gx = (float2*)(h->ws + cur);
+                cur += align_up(px * sizeof(float2), 256);
+                bm::FftJob fj{};
+                if (!plan_fft(W, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "width %d", W);
+                if ((st = get_twiddles(h, W, &fj.tw)) != BM_OK) return st;
+                fj.src = f.data;
+                fj.src_ls = f.row_stride;
+                fj.dst = gx;
+                fj.elem = f.dtype;
+                fj.nlines = H;
+                gp.fft.push_back(fj);
+                gp.max_n = std::max(gp.max_n, W);
+                gam = gx;
+                gls = W;
+            }
+            for (int d = 0; d < 2; ++d) {
+                if (!(f.dirs & (d == 0 ? BM_DIR_X : BM_DIR_Y))) continue;
+                bm::RmJob j{};
+                j.gamma = gam;
+                j.gamma_ls = gls;
+                j.out = d == 0 ? f.omega_x : f.omega_y;
+                j.out_es = 1;
+                j.out_ls = W;
+                j.flags = f.flags;
+                j.flag_es = 1;
+                j.flag_ls = W;
+                j.len = W;
+                j.nlines = H;
+                j.N = f.N;
+                j.flag_shift = d == 0 ? 0 : 4;
+                j.flag_or = (d == 1 && (f.dirs & BM_DIR_X)) ? 1 : 0;
+                j.kind = d == 0 ? bm::RM_BLOCK_X : bm::RM_BLOCK_Y;
+                add_rm(f.L, d == 1 && any_flags && (f.dirs & BM_DIR_X), j);
+            }
+            continue;
+        }
         if (f.dirs & BM_DIR_X) {
             bm::RmJob j{};
             if (e == bm::Elem::C32) {
@@ -411,7 +460,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         int nmax = 0;
         for (auto& j : s.jobs) nmax = std::max(nmax, j.N);
         s.tune = h->tune[s.L][nmax];
-        if (mode == BM_SURROGATE) s.tune = Tune{};   // the surrogate kernel runs 256 lanes, one block per item
+        // the surrogate and block-window kernels run 256 lanes, one block per item
+        if (mode == BM_SURROGATE || s.block_win) s.tune = Tune{};
         const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block);
         s.prefix.assign(1, 0);
         for (auto& j : s.jobs) {
@@ -457,6 +507,7 @@ void bind_group(bosmusic_s* h, GroupPlan& gp, const char* dev) {
         s.batch.total = s.prefix.back();
         s.batch.jacobi = (h->options & BM_OPT_JACOBI) ? 1 : 0;
         s.batch.full_roots = (h->options & BM_OPT_FULL_ROOTS) ? 1 : 0;
+        s.batch.block_windows = s.block_win ? 1 : 0;
         s.batch.stats = (h->options & BM_OPT_STATS) ? h->stats : nullptr;
         s.batch.tmpl = h->tmpl[s.L];
     }
@@ -888,7 +939,7 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             fb.njobs = 1;
             fb.total = n;
             fb.max_n = kLen;
-            bm::RmBatch rb;
+            bm::RmBatch rb{};
             rb.jobs = (const bm::RmJob*)(h->ds + o_rj);
             rb.prefix = (const int*)(h->ds + o_rp);
             rb.njobs = (int)rj.size();
@@ -1177,6 +1228,8 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
             if (st != BM_OK) return st;
             if (mode == BM_SURROGATE && frames[i].N < 16)
                 return fail(h, BM_E_UNSUPPORTED, "frame %d: surrogate mode needs N >= 16", i);
+            if (mode == BM_SURROGATE && (frames[i].dirs & BM_BLOCK))
+                return fail(h, BM_E_UNSUPPORTED, "frame %d: surrogate mode needs line windows", i);
         }
         if (n_frames == 0) return BM_OK;
         DeviceGuard dg(h->device);

@@ -310,7 +310,7 @@ def test_jacobi_option_agrees_with_default_solver(bm, torch):
 def test_certified_pair_agrees_with_all_roots(bm, torch, L, N, snr):
     """The certified-pair shortcut returns the pair that finding every root selects;
     both agree with the oracle, and most windows take the shortcut."""
-    img_np = wl.random_frame(520, 36, seed=10 * L + N, snr_db=snr)
+    img_np = wl.random_frame(540, 36, seed=10 * L + N, snr_db=snr)
     img = to_dev(torch, img_np)
     dc = bm.Demodulator(0, max_width=1024, max_height=1024, stats=True)
     df = bm.Demodulator(0, max_width=1024, max_height=1024, stats=True, full_roots=True)
