@@ -28,4 +28,5 @@ from .rootmusic import (  # noqa: F401
     analytic_mask,
     block_covariances,
     demodulate_block,
+    block_phase,
 )

@@ -61,6 +61,9 @@ Readings of points the paper leaves open (each also listed in the design notes):
       autocorrelation E{Gamma^H Gamma}) gives z_x and omega_x = -arg(z_x)
       (Eq. 15).  FB averaging (R4) and the pair form of R5 are applied as in
       the line mode.
+  R9  Block phase: Eq. 15's alpha = angle(mean(Gamma_w e^{-j(omega_x x +
+      omega_y y)})) with (x, y) measured from the pixel, i.e. the wrapped
+      phase of the block's linear model at the pixel.
 """
 from __future__ import annotations
 
@@ -329,6 +332,33 @@ def demodulate_block(frame: np.ndarray, M: int, dirs: str = "xy", fb: bool = Tru
             # z_x = e^{-j omega_x}: omega_x = -arg(z_x)  (Eq. 15)
             wx[r0 + h:r1 + h, h:h + nc] = -_omega_from_cov(Rx.reshape(-1, M, M), fb).reshape(r1 - r0, nc)
     return wx, wy
+
+
+def block_phase(frame: np.ndarray, M: int, omega_x: np.ndarray, omega_y: np.ndarray) -> np.ndarray:
+    """Wrapped phase of the linear model of every block (Eq. 15, reading R9).
+
+    The paper's alpha = angle(mean(Gamma_w e^{-j(omega_x x + omega_y y)})) with
+    the block coordinates taken relative to the pixel, which makes alpha the
+    model phase alpha_abs + omega_x x + omega_y y at the pixel itself, in
+    (-pi, pi].  NaN where either frequency is NaN.
+    """
+    g = to_complex_field(frame, 1)
+    H, W = g.shape
+    out = np.full((H, W), np.nan)
+    if M > H or M > W:
+        return out
+    h = M // 2
+    B = sliding_window_view(g, (M, M))                # B[a, b, i, j] = g[a+i, b+j], pixel (a+h, b+h)
+    wx = np.asarray(omega_x, dtype=np.float64)[h:h + H - M + 1, h:h + W - M + 1]
+    wy = np.asarray(omega_y, dtype=np.float64)[h:h + H - M + 1, h:h + W - M + 1]
+    d = np.arange(M) - h
+    ex = np.exp(-1j * wx[..., None] * d)               # over the block's columns
+    ey = np.exp(-1j * wy[..., None] * d)               # over its rows
+    s = np.einsum("abij,abi,abj->ab", B, ey, ex) / (M * M)
+    alpha = np.angle(s)
+    alpha[~(np.isfinite(wx) & np.isfinite(wy))] = np.nan
+    out[h:h + H - M + 1, h:h + W - M + 1] = alpha
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -115,3 +115,48 @@ def test_block_with_identical_snapshots_equals_line_mode(M):
     assert np.max(np.abs(ox[h, v] - line[v])) < 1e-9
     no_fb = oracle.demod_lines(f[None, :], M, M, fb=False)[0]
     assert np.max(np.abs(no_fb[v] - line[v])) > 1e-3                # the averaging matters here
+
+
+def _wrap(a):
+    return (a + np.pi) % (2 * np.pi) - np.pi
+
+
+@pytest.mark.parametrize("M", [3, 6, 7])
+def test_block_phase_of_a_plane_wave(M):
+    """Eq. 15: for a linear phase alpha + wx x + wy y the block phase is that phase at the pixel."""
+    W, H, wx, wy, a = 41, 30, 0.9, -0.35, 2.2
+    g = wl.complex_tone(W, H, wx, wy, alpha=a, amp=1.5)
+    ox, oy = oracle.demodulate_block(g, M)
+    ph = oracle.block_phase(g, M, ox, oy)
+    y, x = np.mgrid[0:H, 0:W]
+    v = np.isfinite(ph)
+    assert v.sum() == (H - M + 1) * (W - M + 1)
+    assert np.max(np.abs(_wrap(ph - (a + wx * x + wy * y))[v])) < 1e-11
+
+
+def test_block_phase_matches_integrated_phase_on_a_chirp():
+    """A slowly varying frequency: the wrapped block phase and the trapezoid-integrated
+    phase differ by a constant (the anchor's phase) up to the windowing error."""
+    W, H, M = 80, 40, 5
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    phi = 0.6 * x + 1e-3 * x * x + 0.3 * y
+    g = np.exp(1j * phi)
+    ox, oy = oracle.demodulate_block(g, M)
+    ph = oracle.block_phase(g, M, ox, oy)
+    integ = oracle.integrate(ox, oy, M, M)
+    v = np.isfinite(ph) & np.isfinite(integ)
+    d = _wrap(ph[v] - integ[v])
+    d0 = d[0]
+    assert np.max(np.abs(_wrap(d - d0))) < 2e-3
+
+
+def test_block_phase_with_given_frequencies_and_an_envelope():
+    """With the true frequencies given, an amplitude envelope along x does not move the
+    phase: mean(A e^{j phi} e^{-j(omega . d)}) = mean(A) e^{j phi(pixel)} with mean(A) > 0."""
+    W, H, M, wx, wy, a = 50, 26, 5, 1.1, -0.5, -0.7
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    g = (1.0 + 0.5 * np.sin(0.3 * x)) * np.exp(1j * (a + wx * x + wy * y))
+    ph = oracle.block_phase(g, M, np.full((H, W), wx), np.full((H, W), wy))
+    v = np.isfinite(ph)
+    assert v.sum() == (H - M + 1) * (W - M + 1)
+    assert np.max(np.abs(_wrap(ph - (a + wx * x + wy * y))[v])) < 1e-11
