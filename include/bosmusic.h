@@ -124,6 +124,10 @@ typedef struct {
     float* omega_x;     /* width*height, row stride = width; required iff BM_DIR_X */
     float* omega_y;     /* width*height, row stride = width; required iff BM_DIR_Y */
     uint8_t* flags;     /* optional width*height flag bytes (BM_FLAG_*), or NULL */
+    float* phase;       /* optional, BM_BLOCK with both directions only: width*height, the
+                           wrapped phase of the block's linear model at the pixel, i.e.
+                           Eq. 15's alpha = arg(mean(Gamma_w e^{-j(omega_x x + omega_y y)}))
+                           with x, y measured from the pixel; NaN where omega is; or NULL */
 } bosmusic_frame;
 
 typedef struct {

@@ -44,7 +44,7 @@ class bosmusic_config(ctypes.Structure):
 class bosmusic_frame(ctypes.Structure):
     _fields_ = [("data", c_void_p), ("dtype", c_int32), ("width", c_int32), ("height", c_int32),
                 ("row_stride", c_int64), ("L", c_int32), ("N", c_int32), ("dirs", c_uint32),
-                ("omega_x", c_void_p), ("omega_y", c_void_p), ("flags", c_void_p)]
+                ("omega_x", c_void_p), ("omega_y", c_void_p), ("flags", c_void_p), ("phase", c_void_p)]
 
 
 class bosmusic_stats(ctypes.Structure):
@@ -169,6 +169,7 @@ class FrameSpec:
     omega_x: object = None
     omega_y: object = None
     flags: object = None
+    phase: object = None
 
 
 def _marshal(f: FrameSpec) -> bosmusic_frame:
@@ -176,12 +177,12 @@ def _marshal(f: FrameSpec) -> bosmusic_frame:
     if d.dim() != 2 or d.stride(1) != 1:
         raise ValueError("frame must be a 2-D tensor with unit column stride")
     H, W = d.shape
-    for out in (f.omega_x, f.omega_y, f.flags):
+    for out in (f.omega_x, f.omega_y, f.flags, f.phase):
         if out is not None and (tuple(out.shape) != (H, W) or not out.is_contiguous()):
             raise ValueError("outputs must be contiguous (H, W) tensors")
     ptr = lambda t: c_void_p(t.data_ptr()) if t is not None else c_void_p()
     return bosmusic_frame(c_void_p(d.data_ptr()), _dtype_code(d), W, H, d.stride(0), f.L, f.N, f.dirs,
-                          ptr(f.omega_x), ptr(f.omega_y), ptr(f.flags))
+                          ptr(f.omega_x), ptr(f.omega_y), ptr(f.flags), ptr(f.phase))
 
 
 def bosmusic_demodulate(h, frames, mode: int = BM_PLAIN, stream=None) -> None:
@@ -310,18 +311,25 @@ class Demodulator:
             pass
 
     def demodulate(self, frame, L: int, N: int, dirs: str = "xy", flags: bool = False, stream=None,
-                   mode: int = BM_PLAIN, block: bool = False):
-        """Returns (omega_x or None, omega_y or None[, flags]) for one device frame.
+                   mode: int = BM_PLAIN, block: bool = False, phase: bool = False):
+        """Returns (omega_x or None, omega_y or None[, flags][, phase]) for one device frame.
 
-        block=True: the paper's L x L block window (N must equal L)."""
+        block=True: the paper's L x L block window (N must equal L); phase=True
+        (block windows, both directions) also returns the wrapped block phase."""
         import torch
         H, W = frame.shape
         d = (BM_DIR_X if "x" in dirs else 0) | (BM_DIR_Y if "y" in dirs else 0) | (BM_BLOCK if block else 0)
         wx = torch.empty((H, W), dtype=torch.float32, device=frame.device) if "x" in dirs else None
         wy = torch.empty((H, W), dtype=torch.float32, device=frame.device) if "y" in dirs else None
         fl = torch.empty((H, W), dtype=torch.uint8, device=frame.device) if flags else None
-        bosmusic_demodulate(self.h, [FrameSpec(frame, L, N, d, wx, wy, fl)], mode, stream)
-        return (wx, wy, fl) if flags else (wx, wy)
+        ph = torch.empty((H, W), dtype=torch.float32, device=frame.device) if phase else None
+        bosmusic_demodulate(self.h, [FrameSpec(frame, L, N, d, wx, wy, fl, ph)], mode, stream)
+        out = (wx, wy)
+        if flags:
+            out += (fl,)
+        if phase:
+            out += (ph,)
+        return out
 
     def demodulate_many(self, specs, stream=None):
         bosmusic_demodulate(self.h, specs, BM_PLAIN, stream)

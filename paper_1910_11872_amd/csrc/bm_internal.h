@@ -39,8 +39,7 @@ struct RootTemplate {
 // Window kinds of a root-MUSIC job.
 enum RmKind : int {
     RM_LINE = 0,      // N samples along the line, length-L sub-snapshots
-    RM_BLOCK_X = 1,   // L x L block around the pixel, its rows as snapshots (omega_x)
-    RM_BLOCK_Y = 2,   // L x L block around the pixel, its columns as snapshots (omega_y)
+    RM_BLOCK = 1,     // L x L block around the pixel: its rows (omega_x) and columns (omega_y)
 };
 
 // One direction of one frame for the root-MUSIC kernel: `nlines` lines of
@@ -61,6 +60,10 @@ struct RmJob {
     int flag_shift;        // 0 for x, 4 for y
     int flag_or;           // 1: OR into existing flags, 0: overwrite
     int kind;              // RmKind
+    // RM_BLOCK only: `out` is omega_x; both maps and the phase share out_es / out_ls
+    int bdirs;             // BM_DIR_X | BM_DIR_Y
+    float* out_y;          // omega_y
+    float* phase;          // wrapped block phase, or nullptr
 };
 
 // All root-MUSIC work of one L: jobs[j] owns work items prefix[j] .. prefix[j+1)-1.
@@ -71,7 +74,7 @@ struct RmBatch {
     int total;             // prefix[njobs]
     int jacobi;            // 1: cyclic Jacobi eigen-split instead of the tridiagonal solver
     int full_roots;        // 1: always find every root (no certified-pair shortcut)
-    int block_windows;     // 1: every job is RM_BLOCK_X / RM_BLOCK_Y (256-lane blocks); 0: every job is RM_LINE
+    int block_windows;     // 1: every job is RM_BLOCK (256-lane blocks); 0: every job is RM_LINE
     unsigned long long* stats;  // kStatSlots x kStatFields counters, or nullptr
     RootTemplate tmpl;
 };

@@ -104,13 +104,38 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
 }
 
 
+// Block covariance of one lane: snapshots are the block's rows (along x,
+// rows = true) or its columns (along y), s_k[i] = G[k][t+i] or G[i][t+k],
+// summed into R = sum_k s_k s_k^H (Eq. 4).
+template <int L, int BLOCK>
+__device__ __forceinline__ void block_cov(const float2 (*sR)[BLOCK + L], int t, bool rows, Cov<L>& R) {
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = i; j < L; ++j) { R.re[i][j] = 0.f; R.im[i][j] = 0.f; }
+    for (int k = 0; k < L; ++k) {
+        float2 v[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = rows ? sR[k][t + i] : sR[i][t + k];
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int j = i; j < L; ++j) {
+                R.re[i][j] = fmaf(v[i].x, v[j].x, fmaf(v[i].y, v[j].y, R.re[i][j]));
+                if (i != j) R.im[i][j] = fmaf(v[i].y, v[j].x, fmaf(-v[i].x, v[j].y, R.im[i][j]));
+            }
+    }
+}
+
 // One block of pixels p0 .. p0+BLOCK-L of line `line` in block mode (the
 // paper's L x L moving window, Sec. 3): the rows line-h .. line-h+L-1 of the
-// window columns p0-h .. are staged in LDS, and each lane sums its L x L
-// block's snapshots -- the block's rows (RM_BLOCK_X: omega_x) or its columns
-// (RM_BLOCK_Y: omega_y) -- into R = sum_k s_k s_k^H (Eq. 4).  With snapshots
-// read in increasing x (or y), omega = +arg of the selected root in both
-// directions, the paper's -arg(z_x) for its E{Gamma^H Gamma} form.
+// window columns p0-h .. are staged in LDS; each lane forms its block's
+// covariance from the block's rows (omega_x) and from its columns (omega_y).
+// With the snapshots read in increasing x (or y), omega = +arg of the
+// selected root in both directions -- the paper's -arg(z_x) for its
+// E{Gamma^H Gamma} form.  With both frequencies, the block phase (Eq. 15's
+// alpha, block coordinates measured from the pixel) is
+// arg sum_{i,j} G[i][j] e^{-j(omega_x (j-h) + omega_y (i-h))}.
 template <int L, int BLOCK, bool JACOBI>
 __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int p0, float2 (*sR)[BLOCK + L],
                                                   const RootTemplate& tmpl, bool full_roots, LaneStats& ls) {
@@ -133,48 +158,57 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
     const int p = p0 + t;
     const bool inside_line = (t < WPB) && (p < len);
     const bool valid = inside_line && (c0 + t >= 0) && (c0 + t + L <= len) && (r0 >= 0) && (r0 + L <= nl);
-    float omega = __builtin_nanf("");
-    unsigned flag = 0;
+    float wx = __builtin_nanf(""), wy = __builtin_nanf(""), ph = __builtin_nanf("");
+    unsigned fx = 0, fy = 0;
     if (valid) {
-        Cov<L> R;
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-#pragma unroll
-            for (int j = i; j < L; ++j) { R.re[i][j] = 0.f; R.im[i][j] = 0.f; }
-        if (J.kind == RM_BLOCK_Y) {
-            // snapshots: the block's columns, s_k[i] = G[r0+i][c0+t+k]
-            for (int k = 0; k < L; ++k) {
-                float2 v[L];
-#pragma unroll
-                for (int i = 0; i < L; ++i) v[i] = sR[i][t + k];
-#pragma unroll
-                for (int i = 0; i < L; ++i)
-#pragma unroll
-                    for (int j = i; j < L; ++j) {
-                        R.re[i][j] = fmaf(v[i].x, v[j].x, fmaf(v[i].y, v[j].y, R.re[i][j]));
-                        if (i != j) R.im[i][j] = fmaf(v[i].y, v[j].x, fmaf(-v[i].x, v[j].y, R.im[i][j]));
-                    }
-            }
-        } else {
-            // snapshots: the block's rows, s_k[i] = G[r0+k][c0+t+i]
-            for (int k = 0; k < L; ++k) {
-                float2 v[L];
-#pragma unroll
-                for (int i = 0; i < L; ++i) v[i] = sR[k][t + i];
-#pragma unroll
-                for (int i = 0; i < L; ++i)
-#pragma unroll
-                    for (int j = i; j < L; ++j) {
-                        R.re[i][j] = fmaf(v[i].x, v[j].x, fmaf(v[i].y, v[j].y, R.re[i][j]));
-                        if (i != j) R.im[i][j] = fmaf(v[i].y, v[j].x, fmaf(-v[i].x, v[j].y, R.im[i][j]));
-                    }
-            }
+        if (J.bdirs & BM_DIR_X) {
+            Cov<L> R;
+            block_cov<L, BLOCK>(sR, t, true, R);
+            window_omega<L, JACOBI>(R, tmpl, full_roots, wx, fx, ls);
         }
-        window_omega<L, JACOBI>(R, tmpl, full_roots, omega, flag, ls);
+        if (J.bdirs & BM_DIR_Y) {
+            Cov<L> R;
+            block_cov<L, BLOCK>(sR, t, false, R);
+            window_omega<L, JACOBI>(R, tmpl, full_roots, wy, fy, ls);
+        }
+        if (J.phase && finitef(wx) && finitef(wy)) {
+            float exr[L], exi[L];
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                float sn, cs;
+                sincosf(wx * (float)(j - h), &sn, &cs);
+                exr[j] = cs;
+                exi[j] = -sn;
+            }
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                float rr = 0.f, ri = 0.f;     // sum_j G[i][j] e^{-j wx (j-h)}
+#pragma unroll
+                for (int j = 0; j < L; ++j) {
+                    const float2 v = sR[i][t + j];
+                    rr = fmaf(v.x, exr[j], fmaf(-v.y, exi[j], rr));
+                    ri = fmaf(v.x, exi[j], fmaf(v.y, exr[j], ri));
+                }
+                float sn, cs;
+                sincosf(wy * (float)(i - h), &sn, &cs);   // times e^{-j wy (i-h)}
+                ar = fmaf(rr, cs, fmaf(ri, sn, ar));
+                ai = fmaf(ri, cs, fmaf(-rr, sn, ai));
+            }
+            ph = atan2f(ai, ar);
+        }
     } else {
-        flag |= BM_FLAG_UNDEFINED;
+        fx = fy = BM_FLAG_UNDEFINED;
     }
-    if (inside_line) store_omega(J, line, p, omega, flag);
+    if (inside_line) {
+        const int64_t o = (int64_t)p * J.out_es + (int64_t)line * J.out_ls;
+        if (J.bdirs & BM_DIR_X) J.out[o] = wx;
+        if (J.bdirs & BM_DIR_Y) J.out_y[o] = wy;
+        if (J.phase) J.phase[o] = ph;
+        if (J.flags)
+            J.flags[(int64_t)p * J.flag_es + (int64_t)line * J.flag_ls] =
+                (uint8_t)(((J.bdirs & BM_DIR_X) ? fx : 0u) | (((J.bdirs & BM_DIR_Y) ? fy : 0u) << 4));
+    }
 }
 
 template <int BLOCK>

@@ -229,6 +229,8 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
         return fail(h, BM_E_INVALID_ARG, "frame %d: dirs=%u", idx, f.dirs);
     if ((f.dirs & BM_BLOCK) && f.N != f.L)
         return fail(h, BM_E_INVALID_ARG, "frame %d: block windows need N == L (got L=%d, N=%d)", idx, f.L, f.N);
+    if (f.phase && ((f.dirs & (BM_BLOCK | 3u)) != (BM_BLOCK | 3u)))
+        return fail(h, BM_E_INVALID_ARG, "frame %d: phase needs BM_BLOCK with both directions", idx);
     if ((f.dirs & BM_DIR_X) && !f.omega_x) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_x is NULL", idx);
     if ((f.dirs & BM_DIR_Y) && !f.omega_y) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_y is NULL", idx);
     if (f.dtype != BM_C32) {
@@ -333,25 +335,23 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 gam = gx;
                 gls = W;
             }
-            for (int d = 0; d < 2; ++d) {
-                if (!(f.dirs & (d == 0 ? BM_DIR_X : BM_DIR_Y))) continue;
-                bm::RmJob j{};
-                j.gamma = gam;
-                j.gamma_ls = gls;
-                j.out = d == 0 ? f.omega_x : f.omega_y;
-                j.out_es = 1;
-                j.out_ls = W;
-                j.flags = f.flags;
-                j.flag_es = 1;
-                j.flag_ls = W;
-                j.len = W;
-                j.nlines = H;
-                j.N = f.N;
-                j.flag_shift = d == 0 ? 0 : 4;
-                j.flag_or = (d == 1 && (f.dirs & BM_DIR_X)) ? 1 : 0;
-                j.kind = d == 0 ? bm::RM_BLOCK_X : bm::RM_BLOCK_Y;
-                add_rm(f.L, d == 1 && any_flags && (f.dirs & BM_DIR_X), j);
-            }
+            bm::RmJob j{};
+            j.gamma = gam;
+            j.gamma_ls = gls;
+            j.out = f.omega_x;
+            j.out_y = f.omega_y;
+            j.phase = f.phase;
+            j.bdirs = (int)(f.dirs & 3u);
+            j.out_es = 1;
+            j.out_ls = W;
+            j.flags = f.flags;
+            j.flag_es = 1;
+            j.flag_ls = W;
+            j.len = W;
+            j.nlines = H;
+            j.N = f.N;
+            j.kind = bm::RM_BLOCK;
+            add_rm(f.L, false, j);
             continue;
         }
         if (f.dirs & BM_DIR_X) {

@@ -81,8 +81,8 @@ def test_struct_layout_matches_compiled_header(tmp_path):
 
 def test_struct_layout_matches_header():
     pkg, _ = _lib()
-    # bosmusic_frame: pointer, 3 x int32, int64, 2 x int32, uint32, 3 pointers
-    assert ctypes.sizeof(pkg.bosmusic_frame) == 72
+    # bosmusic_frame: pointer, 3 x int32, int64, 2 x int32, uint32, 4 pointers
+    assert ctypes.sizeof(pkg.bosmusic_frame) == 80
     assert pkg.bosmusic_frame.row_stride.offset == 24
     assert pkg.bosmusic_frame.omega_x.offset == 48
     assert ctypes.sizeof(pkg.bosmusic_config) == 32

@@ -156,3 +156,36 @@ def test_block_argument_checks(bm, torch):
     torch.cuda.synchronize()
     assert torch.isnan(gx).all() and torch.isnan(gy).all()
     d.close()
+
+
+@pytest.mark.parametrize("M,dt", [(5, np.float32), (7, np.float16), (4, np.float64)])
+def test_block_phase_matches_oracle(bm, torch, M, dt):
+    d = bm.Demodulator(0, max_width=512, max_height=512)
+    img = wl.random_frame(320, 40, seed=3 * M, dtype=dt, snr_db=6.0)
+    gx, gy, ph = d.demodulate(dev(torch, img), M, M, "xy", block=True, phase=True)
+    torch.cuda.synchronize()
+    ox, oy = oracle.demodulate_block(img, M)
+    ref = oracle.block_phase(img, M, ox, oy)
+    got = ph.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    v = np.isfinite(ref)
+    e = np.abs(wrap(got[v] - ref[v]))
+    print(f"block phase M{M}: p99.9 {np.quantile(e, 0.999):.2e} max {e.max():.2e}")
+    assert np.quantile(e, 0.999) <= 1e-4
+    d.close()
+
+
+def test_block_phase_of_a_plane_wave(bm, torch):
+    d = bm.Demodulator(0, max_width=512, max_height=512)
+    W, H, wx, wy, a = 300, 50, 0.8, -0.45, 1.3
+    g = wl.complex_tone(W, H, wx, wy, alpha=a).astype(np.complex64)
+    _, _, ph = d.demodulate(dev(torch, g), 6, 6, "xy", block=True, phase=True)
+    torch.cuda.synchronize()
+    y, x = np.mgrid[0:H, 0:W]
+    got = ph.cpu().numpy()
+    v = np.isfinite(got)
+    assert v.sum() == (H - 5) * (W - 5)
+    assert np.max(np.abs(wrap(got[v] - (a + wx * x + wy * y)[v]))) < 5e-5
+    with pytest.raises(bm.BosmusicError):
+        d.demodulate(dev(torch, g), 6, 6, "x", block=True, phase=True)     # phase needs both directions
+    d.close()

@@ -327,6 +327,8 @@ def test_certified_pair_agrees_with_all_roots(bm, torch, L, N, snr):
         compare_omega(u, o, f"certified vs oracle L{L} {name}")
     frac = sc["sur_accepted"] / max(1, sc["windows"])
     print(f"L{L} N{N} {snr} dB: certified {frac:.4f} of {sc['windows']} windows")
-    assert frac > (0.5 if snr < 5 else 0.9)
+    # L = 2: the two roots of a quadratic conjugate-reciprocal polynomial often both lie on
+    # the unit circle, which is not a mate pair, so those windows find all roots
+    assert frac > (0.5 if snr < 5 or L == 2 else 0.9)
     dc.close()
     df.close()
