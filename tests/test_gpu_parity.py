@@ -251,13 +251,16 @@ def test_stats_count_windows(dem, torch):
 # Integration
 # ---------------------------------------------------------------------------
 def test_integrate_matches_oracle_on_same_omega(dem, torch):
+    """The integration step alone: both sides integrate the same omega maps, which
+    come from the oracle (FP32-rounded), never from the GPU."""
     f = wl.cfg2_frame(10)
-    img = to_dev(torch, f.data[:512, :600])
-    wx, wy = dem.demodulate(img, 6, 32, "xy")
+    img = f.data[:512, :600]
+    ox, oy = oracle.demodulate(img, 6, 32, "xy")
+    ox32, oy32 = ox.astype(np.float32), oy.astype(np.float32)
+    wx, wy = to_dev(torch, ox32), to_dev(torch, oy32)
     phi = dem.integrate(wx, wy, 32, 32, 0.3, 0.1)
     torch.cuda.synchronize()
-    wxn, wyn = wx.cpu().numpy(), wy.cpu().numpy()
-    ref = oracle.integrate(wxn, wyn, 32, 32, 0.3, 0.1)
+    ref = oracle.integrate(ox32, oy32, 32, 32, 0.3, 0.1)
     got = phi.cpu().numpy()
     assert np.array_equal(np.isnan(got), np.isnan(ref))
     m = np.isfinite(ref)
@@ -265,7 +268,7 @@ def test_integrate_matches_oracle_on_same_omega(dem, torch):
     # without omega_y
     phi2 = dem.integrate(wx, None, 32, 0)
     torch.cuda.synchronize()
-    ref2 = oracle.integrate(wxn, None, 32, 0)
+    ref2 = oracle.integrate(ox32, None, 32, 0)
     got2 = phi2.cpu().numpy()
     assert np.array_equal(np.isnan(got2), np.isnan(ref2))
     m = np.isfinite(ref2)

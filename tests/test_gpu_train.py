@@ -126,11 +126,12 @@ def test_adam_steps_match_oracle(bm, torch):
     Y = torch.empty((256, 2), device="cuda")
     bm.bosmusic_surrogate_forward(d.h, torch.from_numpy(X).cuda(), Y)
     torch.cuda.synchronize()
+    # the oracle's own parameters after its Adam steps (equal to the GPU's to 1e-6)
     newp = {}
     off = 0
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
         n = int(np.prod(S.SHAPES[k]))
-        newp[k] = got[off:off + n].astype(np.float32).reshape(S.SHAPES[k])
+        newp[k] = P["p"][off:off + n].astype(np.float32).reshape(S.SHAPES[k])
         off += n
     ref = S.forward(newp, X, quantize=True, fp32_acc=True)["Y"]
     err = np.abs(Y.cpu().numpy() - ref)
