@@ -189,8 +189,8 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
     sincosf(what, &sw, &cw);
     double rr = 2.0 * cw, ri = 2.0 * sw, s_r = -((double)cw * cw - (double)sw * sw), s_i = -2.0 * (double)cw * sw;
     double last = 0.0;
-    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last, 1e-13)) return false;
-    if (!(last <= 1e-9 * (fabs(rr) + fabs(ri)))) return false;
+    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last, kPairStepTol)) return false;
+    if (!(last <= kPairAcceptTol * (fabs(rr) + fabs(ri)))) return false;
     if (!certified_pair<L>(ar, ai, rr, ri, s_r, s_i)) return false;
     const float w = atan2f((float)ri, (float)rr);
     omega = w;

@@ -37,6 +37,12 @@ constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
 constexpr float kRootTol2 = BM_ROOT_TOL2;
 constexpr int kPolishIters = BM_POLISH_ITERS;
 constexpr int kCertIters = 8;     // at most this many FP64 Newton steps before the pair certificate
+// Newton on the quadratic factor converges quadratically: after a step of
+// relative size d the error is of order d^2, so iterating stops once a step
+// is below 1e-7 |r| (error ~1e-14), and a factor whose last step is above
+// 1e-6 |r| is not trusted.
+constexpr double kPairStepTol = 1e-7;
+constexpr double kPairAcceptTol = 1e-6;
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
 constexpr int kInverseIters = BM_INVERSE_ITERS;
 
@@ -544,8 +550,8 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
         double rr = 2.0 * cw0, ri = 2.0 * sw0;
         double s_r = -((double)cw0 * cw0 - (double)sw0 * sw0), s_i = -2.0 * (double)cw0 * sw0;
         double lastc = 0.0;
-        cert = bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kCertIters, lastc, 1e-13, &ls.pair_its) &&
-               lastc <= 1e-9 * (fabs(rr) + fabs(ri)) && certified_pair<L>(ar, ai, rr, ri, s_r, s_i);
+        cert = bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kCertIters, lastc, kPairStepTol, &ls.pair_its) &&
+               lastc <= kPairAcceptTol * (fabs(rr) + fabs(ri)) && certified_pair<L>(ar, ai, rr, ri, s_r, s_i);
         if (cert) omega = atan2f((float)ri, (float)rr);
     }
     ls.accepted += cert ? 1 : 0;
