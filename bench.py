@@ -316,10 +316,11 @@ def main():
             bm.bosmusic_surrogate_config(dm.h, 0.25, 1 if args.predictor == "lag1" else 0)
         return dm
 
+    maps = [(wx[i], wy[i], fr[i].N, fr[i].N, 0.0, 0.0, phi[i]) for i in range(nf)]
+
     def step(dm, m=None):
         bm.bosmusic_demodulate(dm.h, specs, mode if m is None else m, stream)
-        for i in range(nf):
-            bm.bosmusic_integrate(dm.h, wx[i], wy[i], fr[i].N, fr[i].N, 0.0, 0.0, phi[i], stream)
+        bm.bosmusic_integrate_many(dm.h, maps, stream)
 
     def timed(dm, m=None):
         for _ in range(args.warmup):

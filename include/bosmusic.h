@@ -267,6 +267,23 @@ bm_status bosmusic_surrogate_step(bosmusic_t h, const float* grad, float lr, voi
 bm_status bosmusic_surrogate_train(bosmusic_t h, const float* X, const float* T, int64_t M, int32_t batch,
                                    int32_t steps, float lr, float* losses, void* stream);
 
+/* One map of a batched integration: the arguments of bosmusic_integrate. */
+typedef struct {
+    const float* omega_x;   /* width*height, required */
+    const float* omega_y;   /* width*height, or NULL (every row then starts at 0) */
+    int32_t width, height;  /* width <= 8192 */
+    int32_t Nx, Ny;         /* window lengths the maps were made with (Ny ignored without omega_y) */
+    double carrier_x, carrier_y;
+    double* phi;            /* width*height FP64 output */
+} bosmusic_integrate_job;
+
+/* bosmusic_integrate for n maps in two launches (all anchor columns, then
+ * every row of every map), results identical to n single calls.  The job
+ * table is uploaded from pinned host memory on `stream`; the call may wait
+ * for its previous upload before reusing that buffer.  Maps must not overlap
+ * another job's phi. */
+bm_status bosmusic_integrate_many(bosmusic_t h, const bosmusic_integrate_job* jobs, int32_t n, void* stream);
+
 /* Autotune the root-MUSIC launch for covariance size L and window N on the
  * handle's device: times every candidate tile shape (128 or 256 lanes per
  * block) and grid size (one block per work item, or 1..16 resident blocks

@@ -32,7 +32,8 @@ ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "
                  "bosmusic_autotune", "bosmusic_get_stats", "bosmusic_status_string", "bosmusic_last_error",
                  "bosmusic_version", "bosmusic_surrogate_load", "bosmusic_surrogate_save",
                  "bosmusic_surrogate_config", "bosmusic_surrogate_forward", "bosmusic_surrogate_dataset",
-                 "bosmusic_surrogate_grad", "bosmusic_surrogate_step", "bosmusic_surrogate_train")
+                 "bosmusic_surrogate_grad", "bosmusic_surrogate_step", "bosmusic_surrogate_train",
+                 "bosmusic_integrate_many")
 MLP_PARAMS = 6402
 
 
@@ -45,6 +46,12 @@ class bosmusic_frame(ctypes.Structure):
     _fields_ = [("data", c_void_p), ("dtype", c_int32), ("width", c_int32), ("height", c_int32),
                 ("row_stride", c_int64), ("L", c_int32), ("N", c_int32), ("dirs", c_uint32),
                 ("omega_x", c_void_p), ("omega_y", c_void_p), ("flags", c_void_p), ("phase", c_void_p)]
+
+
+class bosmusic_integrate_job(ctypes.Structure):
+    _fields_ = [("omega_x", c_void_p), ("omega_y", c_void_p), ("width", c_int32), ("height", c_int32),
+                ("Nx", c_int32), ("Ny", c_int32), ("carrier_x", c_double), ("carrier_y", c_double),
+                ("phi", c_void_p)]
 
 
 class bosmusic_stats(ctypes.Structure):
@@ -90,6 +97,8 @@ def lib():
         L.bosmusic_surrogate_config.restype = c_int32
         L.bosmusic_surrogate_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
         L.bosmusic_surrogate_forward.restype = c_int32
+        L.bosmusic_integrate_many.argtypes = [c_void_p, POINTER(bosmusic_integrate_job), c_int32, c_void_p]
+        L.bosmusic_integrate_many.restype = c_int32
         L.bosmusic_surrogate_dataset.argtypes = [c_void_p, c_int64, c_int64, ctypes.c_uint64, c_void_p, c_void_p,
                                                  c_void_p, c_void_p]
         L.bosmusic_surrogate_dataset.restype = c_int32
@@ -248,6 +257,17 @@ def bosmusic_surrogate_forward(h, X, Y, stream=None) -> None:
     """Y[M, 2] = MLP(X[M, 32]); X, Y contiguous FP32 device tensors."""
     _check(lib().bosmusic_surrogate_forward(h, c_void_p(X.data_ptr()), c_void_p(Y.data_ptr()), X.shape[0],
                                             _stream_ptr(stream)), h)
+
+
+def bosmusic_integrate_many(h, maps, stream=None) -> None:
+    """maps: iterable of (omega_x, omega_y or None, Nx, Ny, carrier_x, carrier_y, phi) device tensors."""
+    items = list(maps)
+    arr = (bosmusic_integrate_job * max(1, len(items)))()
+    for i, (wx, wy, nx, ny, cx, cy, phi) in enumerate(items):
+        H, W = wx.shape
+        arr[i] = bosmusic_integrate_job(c_void_p(wx.data_ptr()), c_void_p(wy.data_ptr() if wy is not None else None),
+                                        W, H, nx, ny, cx, cy, c_void_p(phi.data_ptr()))
+    _check(lib().bosmusic_integrate_many(h, arr, len(items), _stream_ptr(stream)), h)
 
 
 def _ptr(t):

@@ -91,7 +91,87 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const float* __restri
     }
 }
 
+// Batched forms: job j = blockIdx.x for the anchors; rows of all jobs in one grid.
+__global__ __launch_bounds__(kAnchorThreads) void anchor_many_kernel(const IntJob* __restrict__ jobs, int njobs,
+                                                                     double* __restrict__ anchors) {
+    __shared__ double sh[kAnchorThreads];
+    const IntJob& J = jobs[blockIdx.x];
+    if (!J.wy || J.y1 < J.y0 || J.x1 < J.x0) return;
+    double* anchor = anchors + J.anchor_off;
+    const int nsteps = J.y1 - J.y0;
+    const int chunk = (nsteps + kAnchorThreads - 1) / kAnchorThreads;
+    const int t = threadIdx.x;
+    const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const double a = J.wy[(int64_t)(J.y0 + i) * J.W + J.x0], b = J.wy[(int64_t)(J.y0 + i + 1) * J.W + J.x0];
+        acc += 0.5 * (a + b) - J.cy;
+        anchor[J.y0 + i + 1] = acc;
+    }
+    const double off = block_scan_exclusive<kAnchorThreads>(acc, sh);
+    for (int i = i0; i < i1; ++i) anchor[J.y0 + i + 1] += off;
+    if (t == 0) anchor[J.y0] = 0.0;
+}
+
+__global__ __launch_bounds__(kRowThreads) void rows_many_kernel(const IntJob* __restrict__ jobs,
+                                                                const int* __restrict__ prefix, int njobs,
+                                                                const double* __restrict__ anchors) {
+    extern __shared__ double dyn[];
+    __shared__ double sh[kRowThreads];
+    int lo = 0, hi = njobs - 1;              // job of this row: last j with prefix[j] <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const IntJob& J = jobs[lo];
+    const int W = J.W;
+    const int y = blockIdx.x - prefix[lo];
+    double* sp = dyn;                              // W doubles
+    float* sw = reinterpret_cast<float*>(dyn + W);  // W floats
+    double* out = J.phi + (int64_t)y * W;
+    const double nan = __builtin_nan("");
+    if (y < J.y0 || y > J.y1 || J.x1 < J.x0) {
+        for (int x = threadIdx.x; x < W; x += kRowThreads) out[x] = nan;
+        return;
+    }
+    const float* row = J.wx + (int64_t)y * W;
+    for (int x = threadIdx.x; x < W; x += kRowThreads) sw[x] = row[x];
+    __syncthreads();
+    const int x0 = J.x0, nsteps = J.x1 - J.x0;
+    const int chunk = (nsteps + kRowThreads - 1) / kRowThreads;
+    const int t = threadIdx.x;
+    const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        acc += 0.5 * ((double)sw[x0 + i] + (double)sw[x0 + i + 1]) - J.cx;
+        sp[x0 + i + 1] = acc;
+    }
+    const double off = block_scan_exclusive<kRowThreads>(acc, sh);
+    const double base = J.wy ? anchors[J.anchor_off + y] : 0.0;
+    for (int i = i0; i < i1; ++i) sp[x0 + i + 1] += off;
+    __syncthreads();
+    for (int x = threadIdx.x; x < W; x += kRowThreads) {
+        double v = nan;
+        if (x == x0) v = base;
+        else if (x > x0 && x <= J.x1) v = base + sp[x];
+        out[x] = v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njobs, int total_rows, int max_w,
+                                 double* anchors, hipStream_t s) {
+    if (njobs <= 0 || total_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(anchor_many_kernel, dim3(njobs), dim3(kAnchorThreads), 0, s, jobs, njobs, anchors);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t shmem = (size_t)max_w * (sizeof(double) + sizeof(float));
+    hipLaunchKernelGGL(rows_many_kernel, dim3(total_rows), dim3(kRowThreads), shmem, s, jobs, prefix, njobs,
+                       anchors);
+    return hipGetLastError();
+}
 
 hipError_t launch_integrate(const float* wx, const float* wy, int W, int H, int Nx, int Ny, double cx, double cy,
                             double* anchor_ws, double* phi, hipStream_t s) {
@@ -114,7 +194,10 @@ hipError_t launch_integrate(const float* wx, const float* wy, int W, int H, int 
 }
 
 hipError_t integrate_set_attributes() {
-    return hipFuncSetAttribute((const void*)rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kMaxFFT * (int)(sizeof(double) + sizeof(float)));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)rows_many_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                kMaxFFT * (int)(sizeof(double) + sizeof(float)));
 }
 

@@ -181,6 +181,21 @@ hipError_t launch_synth(float2* g, int64_t n, float w0, float noise, hipStream_t
 hipError_t launch_integrate(const float* wx, const float* wy, int W, int H, int Nx, int Ny,
                             double cx, double cy, double* anchor_ws, double* phi, hipStream_t s);
 
+// One map of a batched integration: valid columns x0..x1, rows y0..y1 (the
+// whole height without omega_y), anchor column at anchors + anchor_off.
+struct IntJob {
+    const float* wx;
+    const float* wy;       // or nullptr
+    double* phi;
+    double cx, cy;
+    int64_t anchor_off;
+    int W, H, x0, x1, y0, y1;
+};
+// Anchors of every job (one block each), then every row of every job (rows
+// job j own prefix[j] .. prefix[j+1]-1); max_w sizes the row LDS.
+hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njobs, int total_rows, int max_w,
+                                 double* anchors, hipStream_t s);
+
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KiB; call
 // once per device with that device current.
 hipError_t analytic_set_attributes();

@@ -85,6 +85,14 @@ struct bosmusic_s {
     int losses_cap = 0;
     char* ds = nullptr;            // dataset generation buffers
     size_t ds_bytes = 0;
+    // batched integration: job tables (pinned staging + device copy) and anchor columns
+    char* int_pin = nullptr;
+    void* int_dev = nullptr;
+    size_t int_bytes = 0;
+    hipEvent_t int_ev = nullptr;
+    bool int_pending = false;
+    double* int_anchor = nullptr;
+    size_t int_anchor_cap = 0;
     std::string err;
 };
 
@@ -1091,6 +1099,10 @@ void release(bosmusic_s* h) {
     (void)hipFree(h->part);
     (void)hipFree(h->losses);
     (void)hipFree(h->ds);
+    (void)hipFree(h->int_dev);
+    (void)hipFree(h->int_anchor);
+    if (h->int_pin) (void)hipHostFree(h->int_pin);
+    if (h->int_ev) (void)hipEventDestroy(h->int_ev);
     if (h->pin) (void)hipHostFree(h->pin);
     for (auto& kv : h->twiddles) (void)hipFree(kv.second);
     for (auto* v : {&h->ev_free, &h->ev_pending})
@@ -1171,6 +1183,7 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         bool ok = hipMemset(h->stats, 0, bm::kStatFields * bm::kStatSlots * sizeof(unsigned long long)) == hipSuccess &&
                   bm::analytic_set_attributes() == hipSuccess && bm::integrate_set_attributes() == hipSuccess &&
                   hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&h->int_ev, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) == hipSuccess;
         for (int i = 0; ok && i < kMaxForks; ++i)
             ok = hipStreamCreateWithFlags(&h->cap[i], hipStreamNonBlocking) == hipSuccess &&
@@ -1283,6 +1296,91 @@ bm_status bosmusic_integrate(bosmusic_t h, const float* omega_x, const float* om
                      "integrate");
     } catch (...) {
         return fail(h, BM_E_NOMEM, "host exception in integrate");
+    }
+}
+
+bm_status bosmusic_integrate_many(bosmusic_t h, const bosmusic_integrate_job* jobs, int32_t n, void* stream) {
+    if (!h) return BM_E_INVALID_ARG;
+    try {
+        h->err.clear();
+        if (n < 0 || (n > 0 && !jobs)) return fail(h, BM_E_INVALID_ARG, "jobs/n");
+        std::vector<bm::IntJob> tab((size_t)n);
+        std::vector<int> prefix(1, 0);
+        int64_t anchors = 0;
+        int max_w = 1;
+        for (int i = 0; i < n; ++i) {
+            const bosmusic_integrate_job& q = jobs[i];
+            if (!q.omega_x || !q.phi) return fail(h, BM_E_INVALID_ARG, "job %d: omega_x/phi is NULL", i);
+            if (q.width < 1 || q.height < 1 || q.width > bm::kMaxFFT || q.height > 65536)
+                return fail(h, BM_E_INVALID_ARG, "job %d: size %dx%d", i, q.width, q.height);
+            if (q.Nx < 1 || q.Nx > bm::kMaxN || (q.omega_y && (q.Ny < 1 || q.Ny > bm::kMaxN)))
+                return fail(h, BM_E_INVALID_ARG, "job %d: Nx/Ny", i);
+            if (!std::isfinite(q.carrier_x) || !std::isfinite(q.carrier_y))
+                return fail(h, BM_E_INVALID_ARG, "job %d: carrier", i);
+            if ((int64_t)prefix.back() + q.height > INT32_MAX) return fail(h, BM_E_INVALID_ARG, "too many rows");
+            bm::IntJob& J = tab[i];
+            J.wx = q.omega_x;
+            J.wy = q.omega_y;
+            J.phi = q.phi;
+            J.cx = q.carrier_x;
+            J.cy = q.carrier_y;
+            J.W = q.width;
+            J.H = q.height;
+            J.x0 = q.Nx / 2;
+            J.x1 = q.width - q.Nx + q.Nx / 2;
+            J.y0 = q.omega_y ? q.Ny / 2 : 0;
+            J.y1 = q.omega_y ? q.height - q.Ny + q.Ny / 2 : q.height - 1;
+            J.anchor_off = anchors;
+            anchors += q.height;
+            max_w = std::max(max_w, q.width);
+            prefix.push_back(prefix.back() + q.height);
+        }
+        if (n == 0) return BM_OK;
+        DeviceGuard dg(h->device);
+        if (dg.status != hipSuccess) return check(h, dg.status, "hipSetDevice");
+        hipStream_t st = (hipStream_t)stream;
+        bm_status r;
+        const size_t toff = 0, poff = align_up(tab.size() * sizeof(bm::IntJob), 256);
+        const size_t bytes = poff + prefix.size() * sizeof(int);
+        if (bytes > h->int_bytes || (size_t)anchors > h->int_anchor_cap) {
+            // the old buffers may still be read by enqueued work
+            if ((r = check(h, hipStreamSynchronize(st), "sync before growing integration buffers"))) return r;
+            if (h->int_pending && (r = check(h, hipEventSynchronize(h->int_ev), "upload wait"))) return r;
+            h->int_pending = false;
+            if (bytes > h->int_bytes) {
+                const size_t nb = align_up(std::max<size_t>(bytes, 1 << 14) * 2, 4096);
+                (void)hipHostFree(h->int_pin);
+                (void)hipFree(h->int_dev);
+                h->int_pin = nullptr;
+                h->int_dev = nullptr;
+                h->int_bytes = 0;
+                if (hipHostMalloc((void**)&h->int_pin, nb, hipHostMallocDefault) != hipSuccess ||
+                    hipMalloc(&h->int_dev, nb) != hipSuccess)
+                    return fail(h, BM_E_NOMEM, "integration job tables");
+                h->int_bytes = nb;
+            }
+            if ((size_t)anchors > h->int_anchor_cap) {
+                (void)hipFree(h->int_anchor);
+                h->int_anchor = nullptr;
+                h->int_anchor_cap = 0;
+                if (hipMalloc(&h->int_anchor, (size_t)anchors * 2 * sizeof(double)) != hipSuccess)
+                    return fail(h, BM_E_NOMEM, "integration anchors");
+                h->int_anchor_cap = (size_t)anchors * 2;
+            }
+        }
+        if (h->int_pending && (r = check(h, hipEventSynchronize(h->int_ev), "upload wait"))) return r;
+        std::memcpy(h->int_pin + toff, tab.data(), tab.size() * sizeof(bm::IntJob));
+        std::memcpy(h->int_pin + poff, prefix.data(), prefix.size() * sizeof(int));
+        if ((r = check(h, hipMemcpyAsync(h->int_dev, h->int_pin, bytes, hipMemcpyHostToDevice, st), "upload")) ||
+            (r = check(h, hipEventRecord(h->int_ev, st), "upload event")))
+            return r;
+        h->int_pending = true;
+        const char* dev = (const char*)h->int_dev;
+        return check(h, bm::launch_integrate_many((const bm::IntJob*)(dev + toff), (const int*)(dev + poff), n,
+                                                  prefix.back(), max_w, h->int_anchor, st),
+                     "integrate_many");
+    } catch (...) {
+        return fail(h, BM_E_NOMEM, "host exception in integrate_many");
     }
 }
 

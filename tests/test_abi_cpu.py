@@ -63,9 +63,11 @@ def test_struct_layout_matches_compiled_header(tmp_path):
         "  printf(\"bosmusic_frame %zu\\n\", sizeof(bosmusic_frame));\n"
         "  printf(\"bosmusic_config %zu\\n\", sizeof(bosmusic_config));\n"
         "  printf(\"bosmusic_stats %zu\\n\", sizeof(bosmusic_stats));\n"
+        "  printf(\"bosmusic_integrate_job %zu\\n\", sizeof(bosmusic_integrate_job));\n"
         + "".join(f"  F({t}, {m})\n" for t, cls in (("bosmusic_frame", pkg.bosmusic_frame),
                                                     ("bosmusic_config", pkg.bosmusic_config),
-                                                    ("bosmusic_stats", pkg.bosmusic_stats))
+                                                    ("bosmusic_stats", pkg.bosmusic_stats),
+                                                    ("bosmusic_integrate_job", pkg.bosmusic_integrate_job))
                   for m, _ in cls._fields_)
         + "  return 0;\n}\n")
     exe = tmp_path / "layout"
@@ -73,7 +75,7 @@ def test_struct_layout_matches_compiled_header(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     got = dict(line.rsplit(" ", 1) for line in out if line)
     for t, cls in (("bosmusic_frame", pkg.bosmusic_frame), ("bosmusic_config", pkg.bosmusic_config),
-                   ("bosmusic_stats", pkg.bosmusic_stats)):
+                   ("bosmusic_stats", pkg.bosmusic_stats), ("bosmusic_integrate_job", pkg.bosmusic_integrate_job)):
         assert int(got[t]) == ctypes.sizeof(cls), t
         for m, _ in cls._fields_:
             assert int(got[f"{t}.{m}"]) == getattr(cls, m).offset, (t, m)

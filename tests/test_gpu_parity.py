@@ -275,6 +275,25 @@ def test_integrate_matches_oracle_on_same_omega(dem, torch):
     assert np.max(np.abs(got2[m] - ref2[m])) < 1e-9
 
 
+def test_integrate_many_equals_single_calls(dem, torch, bm):
+    """The batched integration gives bit for bit what one call per map gives."""
+    rng = np.random.default_rng(4)
+    maps = []
+    for (W, H, nx, ny, with_y) in [(300, 40, 20, 12, True), (64, 100, 8, 8, False), (1024, 7, 32, 5, True),
+                                   (50, 30, 60, 8, True)]:
+        wx = to_dev(torch, (0.5 + 0.1 * rng.standard_normal((H, W))).astype(np.float32))
+        wy = to_dev(torch, (0.2 + 0.1 * rng.standard_normal((H, W))).astype(np.float32)) if with_y else None
+        maps.append((wx, wy, nx, ny, 0.1, -0.2))
+    singles = [dem.integrate(wx, wy, nx, ny, cx, cy) for (wx, wy, nx, ny, cx, cy) in maps]
+    outs = [torch.empty(m[0].shape, dtype=torch.float64, device="cuda") for m in maps]
+    bm.bosmusic_integrate_many(dem.h, [m + (o,) for m, o in zip(maps, outs)])
+    bm.bosmusic_integrate_many(dem.h, [m + (o,) for m, o in zip(maps, outs)])       # reuse of the tables
+    torch.cuda.synchronize()
+    for a, b in zip(singles, outs):
+        assert torch.equal(torch.nan_to_num(a, 7.0), torch.nan_to_num(b, 7.0))
+    assert torch.isnan(outs[3]).all()                                # Nx > W: nothing valid
+
+
 def test_integrate_end_to_end_linear_phase(dem, torch):
     W, H = 240, 96
     wx0, wy0 = 2 * np.pi * 23 / W, 2 * np.pi * 9 / H
