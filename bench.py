@@ -30,6 +30,10 @@ import workloads as wl  # noqa: E402
 
 PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed), FLOP/s
 PEAK_HBM = 8.0e12
+# HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
+# certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
+# frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (39190.375 * 2.0 + 33792.0) * 1024 / (4 * 2 * 1024 * 1024)
 
 
 def bairstow_flops(n: int) -> int:
@@ -85,15 +89,16 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
 def surrogate_flops_per_window(L: int, N: int) -> dict:
     """Algorithmic flops of one window of the surrogate kernel, counted up to
     the first point where a window can be rejected (so a lower bound for the
-    accepted ones): features, the MLP (matrix-core flops kept apart, GELU as
-    its A&S erf: 16 flops), lag sums, the real transform, the power
+    accepted ones): features and the MLP of one window in four (matrix-core
+    flops kept apart, GELU as its A&S erf: 16 flops), lag sums, the real transform, the power
     iteration, the polynomial, three FP64 Newton steps on the quadratic
     factor and the certificate.  Transcendentals count as one flop."""
     K = N - L + 1
     n = 2 * L - 2
-    feat = 4 * N + 16 * 6 + 10
-    mlp_mfma = 2 * (32 * 64 + 64 * 64 + 64 * 2)
-    mlp_valu = 2 * 64 * (16 + 1) + 2
+    stride = 4                                        # one network prediction per 4 windows
+    feat = (4 * N + 16 * 6 + 10) / stride
+    mlp_mfma = 2 * (32 * 64 + 64 * 64 + 64 * 2) / stride
+    mlp_valu = (2 * 64 * (16 + 1) + 2) / stride
     lag = K * L * 8
     build_t = 3 * L * L + L + L * (L + 1) // 2
     power = 6 * (2 * L * L + 3 * L + 1) + 2 * L
@@ -376,6 +381,9 @@ def main():
             # the fallback windows (the surrogate kernel's own work is modelled below)
             iters = ss["root_iters"] / nwin
             pair_its, cert = ss["pair_iters"] / nwin, 0.0
+        elif args.full_roots:
+            iters = ss["root_iters"] / nwin
+            pair_its, cert = 0.0, 0.0
         else:
             iters = ss["root_iters"] / max(1, ss["sur_rejected"])
             pair_its = ss["pair_iters"] / nwin
@@ -406,8 +414,12 @@ def main():
     rm_s = st["rm_time_ns"] / 1e9 / args.steps          # root-MUSIC (or surrogate + fallback) time per step
     achieved = flops_step / rm_s
     kname = ("surrogate_kernel + rootmusic_gather_kernel fallback" if surrogate else "rootmusic_kernel")
+    traffic = None
+    if args.workload == "cfg2" and not (args.block or args.full_roots or surrogate):
+        traffic = TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 * 2 * total_px / max(1, st["rm_launches"] // args.steps)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+            "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, scaled per pixel)",
             "kernel": f"{kname}, {st['rm_launches'] // args.steps} timed region(s)/step, mean "
                       f"{st['rm_time_ns'] / max(1, st['rm_launches']) / 1e6:.3f} ms (HIP events on its stream), "
                       f"per L: {json.dumps(per_L)}"}

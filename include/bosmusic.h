@@ -191,8 +191,10 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
 /* ---- learned surrogate (BM_SURROGATE) -------------------------------------
  * An MLP 32 -> 64 -> 64 -> 2 (exact-erf GELU) maps the normalised window (16
  * central samples de-rotated by the central sample's phase, divided by the
- * window's RMS magnitude, [Re(16), Im(16)]) to (cos w, sin w).  Its estimate
- * w_hat seeds a power iteration for the signal eigenvector u1; the window is
+ * window's RMS magnitude, [Re(16), Im(16)]) to (cos w, sin w); it runs on
+ * every fourth window of a line and its estimate w_hat serves that window
+ * and its three neighbours.  w_hat seeds a power iteration for the signal
+ * eigenvector u1; the window is
  * rejected when the MUSIC null spectrum 1 - |u1^H a(w_hat)|^2 / L at the
  * prediction exceeds tau.  Newton iterations (FP64) on the quadratic factor
  * of the root-MUSIC polynomial (paper Eq. 12) started from the double root

@@ -36,6 +36,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kSurBlock = 256;
 constexpr int kPowerSteps = 6;
 constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps on the quadratic factor
+constexpr int kPredictStride = 4;     // one network prediction per this many windows
+static_assert(kSurBlock / kPredictStride == 16 * (kSurBlock / 64), "one 16-window MLP tile per wave");
 
 // C(16 x 16) += A(16 x 32) B(32 x 16) on one wave.  A(i, k) = a[i*lda + k],
 // B(k, j) = b[j*ldb + k]; both 16-byte aligned with k contiguous.  Lane l
@@ -203,9 +205,10 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
     constexpr int WPB = BLOCK - (L - 1);
     __shared__ MlpSmem sm;
     __shared__ float2 sg[BLOCK + kMaxN];
-    __shared__ float what[BLOCK];
-    // x [BLOCK][32] + per-wave h1, h2 [16][64]; later reused for the lag sums
-    constexpr int kXBytes = BLOCK * kMlpIn * 2, kHBytes = 4 * 2 * 16 * kMlpHidden * 2;
+    constexpr int NP = BLOCK / kPredictStride;     // predictions per block (one MLP tile per wave)
+    __shared__ float what[NP];
+    // x [NP][32] + per-wave h1, h2 [16][64]; later reused for the lag sums
+    constexpr int kXBytes = NP * kMlpIn * 2, kHBytes = 4 * 2 * 16 * kMlpHidden * 2;
     constexpr int kSBytes = L * BLOCK * 8;
     constexpr int kUBytes = (kXBytes + kHBytes) > kSBytes ? (kXBytes + kHBytes) : kSBytes;
     __shared__ alignas(16) unsigned char ubuf[kUBytes];
@@ -235,14 +238,25 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
     const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
 
     // ---- features and the MLP ------------------------------------------
+    // The local frequency varies slowly along a line, and the prediction only
+    // seeds the refinement that the certificate then judges, so the network
+    // runs on every kPredictStride-th window: prediction k is made at window
+    // kPredictStride k + kPredictStride/2 (moved inside the block's valid
+    // windows) and serves the windows kPredictStride k .. kPredictStride k +
+    // kPredictStride - 1.
     if (S.predictor == 0) {
-        {
-            const float2* w = sg + t;
+        // valid windows of this block: lanes lo .. hi
+        const int lo = max(0, half - p0);
+        const int hi = min(min(WPB - 1, len - 1 - p0), len - N + half - p0);
+        if (t < NP) {
+            const int pos = min(max(kPredictStride * t + kPredictStride / 2, lo), max(hi, lo));
+            const bool ok0 = hi >= lo;
+            const float2* w = sg + pos;
             float e = 0.f;
             for (int k = 0; k < N; ++k) e = fmaf(w[k].x, w[k].x, fmaf(w[k].y, w[k].y, e));
             const float2 gc = w[half];
             const float mc = fsqrt(gc.x * gc.x + gc.y * gc.y);
-            const bool ok = valid && mc > 0.f && e > 0.f;
+            const bool ok = ok0 && mc > 0.f && e > 0.f;
             const float sc = ok ? frcp(mc) * rsqrtf(e / (float)N) : 0.f;
             const float rc = gc.x * sc, rs = -gc.y * sc;           // conj(gc)/|gc|/rms
 #pragma unroll
@@ -253,10 +267,10 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
             }
         }
         __syncthreads();
-        for (int tile = wv; tile < BLOCK / 16; tile += BLOCK / 64) {
+        {
+            const int tile = wv;                                   // NP / 16 == number of waves
             const float2 y = mlp_tile(sm, xs + tile * 16 * kMlpIn, h1, h2);
             if ((t & 63) < 16) what[tile * 16 + (t & 15)] = atan2f(y.y, y.x);
-            __syncthreads();
         }
     }
     __syncthreads();
@@ -300,7 +314,7 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
             }
         float wh;
         if (S.predictor == 0) {
-            wh = what[t];
+            wh = what[min(NP - 1, t / kPredictStride)];
         } else {
             float sr = 0.f, si = 0.f;
 #pragma unroll
@@ -647,26 +661,39 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(MlpWeights w, const __bf
 
 // Gradient sums over the blocks in a fixed order, then (adam != 0) one Adam
 // step on the FP32 master parameters and fresh bfloat16 copies.
-__global__ void mlp_reduce_adam_kernel(const float* part, int nblocks, float* master, float* m, float* v, float* grad,
-                                       float* loss, __bf16* wts, int adam, float lr, float c1, float c2) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && loss && part) {
-        float s = 0.f;
-        for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kPartStride + kPartLoss];
-        *loss = s;
-    }
-    if (p >= kMlpParams) return;
-    // master layout: W1 [32][64], b1, W2 [64][64], b2, W3 [64][2], b3
-    int src, kind, i = 0, o = 0;
-    if (p < 2048) { i = p / 64; o = p % 64; src = kPartDW1 + o * 32 + i; kind = 1; }
-    else if (p < 2112) { src = kPartDB1 + p - 2048; kind = 0; }
-    else if (p < 6208) { const int q = p - 2112; i = q / 64; o = q % 64; src = kPartDW2 + o * 64 + i; kind = 2; }
-    else if (p < 6272) { src = kPartDB2 + p - 6208; kind = 0; }
-    else if (p < 6400) { const int q = p - 6272; i = q / 2; o = q % 2; src = kPartDW3 + o * 64 + i; kind = 3; }
-    else { src = kPartDB3 + p - 6400; kind = 0; }
+// Gradient sums over the blocks, in the partials' own layout so that the
+// loads are coalesced: a block of 256 lanes owns 64 partial entries, four
+// lanes per entry sum every fourth block, and the four sums are added in a
+// fixed order.  Then (adam != 0) one Adam step on the FP32 master parameter
+// the entry belongs to, and fresh bfloat16 copies.
+constexpr int kReduceItems = 64;
+
+__global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(const float* part, int nblocks, float* master, float* m,
+                                                             float* v, float* grad, float* loss, __bf16* wts,
+                                                             int adam, float lr, float c1, float c2) {
+    __shared__ float red[4][kReduceItems];
+    const int t = threadIdx.x, col = t & (kReduceItems - 1), slice = t / kReduceItems;
+    const int q = blockIdx.x * kReduceItems + col;     // partial-layout index, kPartLoss included
     float g = 0.f;
+    if (part && q <= kPartLoss)
+        for (int b = slice; b < nblocks; b += 4) g += part[(int64_t)b * kPartStride + q];
+    red[slice][col] = g;
+    __syncthreads();
+    if (slice != 0 || q > kPartLoss) return;
+    g = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+    if (q == kPartLoss) {
+        if (loss && part) *loss = g;
+        return;
+    }
+    // partial layout -> master layout (W1 [32][64], b1, W2 [64][64], b2, W3 [64][2], b3)
+    int p, kind, i = 0, o = 0;
+    if (q < kPartDB1) { o = q / 32; i = q % 32; p = i * 64 + o; kind = 1; }
+    else if (q < kPartDW2) { p = q; kind = 0; }
+    else if (q < kPartDB2) { const int r = q - kPartDW2; o = r / 64; i = r % 64; p = kPartDW2 + i * 64 + o; kind = 2; }
+    else if (q < kPartDW3) { p = q; kind = 0; }
+    else if (q < kPartDB3) { const int r = q - kPartDW3; o = r / 64; i = r % 64; p = kPartDW3 + i * 2 + o; kind = 3; }
+    else { p = q; kind = 0; }
     if (part) {
-        for (int b = 0; b < nblocks; ++b) g += part[(int64_t)b * kPartStride + src];
         if (grad) grad[p] = g;
     } else {
         g = grad[p];
@@ -746,8 +773,8 @@ hipError_t launch_mlp_train(const MlpWeights& w, const __bf16* w2, const float* 
 
 hipError_t launch_mlp_reduce_adam(const float* part, int nblocks, float* master, float* m, float* v, float* grad,
                                   float* loss, __bf16* wts, int adam, float lr, float c1, float c2, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, part, nblocks, master,
-                       m, v, grad, loss, wts, adam, lr, c1, c2);
+    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kPartLoss + 1 + kReduceItems - 1) / kReduceItems), dim3(256), 0, s,
+                       part, nblocks, master, m, v, grad, loss, wts, adam, lr, c1, c2);
     return hipGetLastError();
 }
 
