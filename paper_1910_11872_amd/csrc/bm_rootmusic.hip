@@ -57,27 +57,7 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
     }
     __syncthreads();
     // ---- lag sums S_d(base+t), d < L (every lane) -------------------------
-    {
-        float sr[L], si[L];
-#pragma unroll
-        for (int d = 0; d < L; ++d) { sr[d] = 0.f; si[d] = 0.f; }
-        float2 win[L];
-#pragma unroll
-        for (int d = 0; d < L - 1; ++d) win[d + 1] = sg[t + d];
-        for (int k = 0; k < K; ++k) {
-#pragma unroll
-            for (int d = 0; d < L - 1; ++d) win[d] = win[d + 1];
-            win[L - 1] = sg[t + k + L - 1];
-            // products g[k] conj(g[k+d]) with g[k] = win[0]
-#pragma unroll
-            for (int d = 0; d < L; ++d) {
-                sr[d] = fmaf(win[0].x, win[d].x, fmaf(win[0].y, win[d].y, sr[d]));
-                si[d] = fmaf(win[0].y, win[d].x, fmaf(-win[0].x, win[d].y, si[d]));
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < L; ++d) sS[d][t] = make_float2(sr[d], si[d]);
-    }
+    lag_sums<L, BLOCK + L>(sg, t, K, sS);
     __syncthreads();
 
     const int p = p0 + t;

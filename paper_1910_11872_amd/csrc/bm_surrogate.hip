@@ -16,7 +16,8 @@
 //      steering vector of omega_hat, and the MUSIC null spectrum at
 //      omega_hat (reject above tau);
 //   5. Newton iterations in FP64 on the quadratic factor of the root-MUSIC
-//      polynomial (paper Eq. 12) started from the double root e^{j omega_hat};
+//      polynomial (paper Eq. 12) started from the double root at the
+//      frequency of the eigenvector's lag-1 coefficient;
 //      accept when the factor converged to a conjugate-reciprocal pair and a
 //      Schur-Cohn count on the deflated polynomial shows no other root as
 //      near the unit circle, so that the pair is the one the plain path
@@ -186,9 +187,13 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
     signal_vector<L>(v, ur, ui);
     float ar[n + 1], ai[n + 1];
     poly_coeffs<L>(ur, ui, ar, ai);
-    // the factor of the double root e^{j what}: r = 2 e^{j what}, s = -e^{2 j what}
+    // The signal eigenvector seeded by the prediction now gives a sharper
+    // frequency than the prediction itself: u1[i+1]/u1[i] ~ e^{j w}, so the
+    // lag-1 coefficient c_1 ~ -((L-1)/L) e^{-j w}.  Newton starts from the
+    // factor of its double root e^{j w1}: r = 2 e^{j w1}, s = -e^{2 j w1}.
+    const float w1 = atan2f(ai[L], -ar[L]);
     float sw, cw;
-    sincosf(what, &sw, &cw);
+    sincosf(w1, &sw, &cw);
     double rr = 2.0 * cw, ri = 2.0 * sw, s_r = -((double)cw * cw - (double)sw * sw), s_i = -2.0 * (double)cw * sw;
     double last = 0.0;
     if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last, kPairStepTol)) return false;
@@ -274,28 +279,8 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
         }
     }
     __syncthreads();
-    // ---- lag sums (the MLP scratch is dead now) ---------------------------
-    {
-        float sr[L], si[L];
-#pragma unroll
-        for (int d = 0; d < L; ++d) { sr[d] = 0.f; si[d] = 0.f; }
-        float2 win[L];
-#pragma unroll
-        for (int d = 0; d < L - 1; ++d) win[d + 1] = sg[t + d];
-        for (int k = 0; k < K; ++k) {
-#pragma unroll
-            for (int d = 0; d < L - 1; ++d) win[d] = win[d + 1];
-            win[L - 1] = sg[t + k + L - 1];
-#pragma unroll
-            for (int d = 0; d < L; ++d) {
-                sr[d] = fmaf(win[0].x, win[d].x, fmaf(win[0].y, win[d].y, sr[d]));
-                si[d] = fmaf(win[0].y, win[d].x, fmaf(-win[0].x, win[d].y, si[d]));
-            }
-        }
-        __syncthreads();   // every lane has read the features before they are overwritten
-#pragma unroll
-        for (int d = 0; d < L; ++d) sS[d][t] = make_float2(sr[d], si[d]);
-    }
+    // ---- lag sums (the MLP scratch is dead now: every wave passed the barrier above) ---
+    lag_sums<L, BLOCK>(sg, t, K, sS);
     __syncthreads();
 
     float omega = __builtin_nanf("");

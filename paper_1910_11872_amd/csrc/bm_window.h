@@ -494,6 +494,47 @@ __device__ __forceinline__ bool certified_pair(const float (&ar)[2 * L - 1], con
     return zeros_inside_unit_disk<n - 2>(fr, fi) == L - 2;
 }
 
+// Lag sums of lane t: S_d = sum_{k<K} g[t+k] conj(g[t+k+d]), d < L, from the
+// staged signal g, stored to sS[d][t].  The last L samples live in a circular
+// register buffer indexed by k mod L, unrolled L steps at a time so that no
+// register moves are needed.
+template <int L, int STRIDE>
+__device__ __forceinline__ void lag_sums(const float2* g, int t, int K, float2 (*sS)[STRIDE]) {
+    float sr[L], si[L];
+#pragma unroll
+    for (int d = 0; d < L; ++d) { sr[d] = 0.f; si[d] = 0.f; }
+    float2 win[L];                      // win[m mod L] = g[t + m]
+#pragma unroll
+    for (int d = 0; d < L - 1; ++d) win[d] = g[t + d];
+    int k0 = 0;
+    for (; k0 + L <= K; k0 += L) {
+#pragma unroll
+        for (int u = 0; u < L; ++u) {
+            win[(u + L - 1) % L] = g[t + k0 + u + L - 1];
+#pragma unroll
+            for (int d = 0; d < L; ++d) {
+                const float2 a = win[u], b = win[(u + d) % L];
+                sr[d] = fmaf(a.x, b.x, fmaf(a.y, b.y, sr[d]));
+                si[d] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[d]));
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < L - 1; ++u) {
+        if (k0 + u < K) {
+            win[(u + L - 1) % L] = g[t + k0 + u + L - 1];
+#pragma unroll
+            for (int d = 0; d < L; ++d) {
+                const float2 a = win[u], b = win[(u + d) % L];
+                sr[d] = fmaf(a.x, b.x, fmaf(a.y, b.y, sr[d]));
+                si[d] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[d]));
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < L; ++d) sS[d][t] = make_float2(sr[d], si[d]);
+}
+
 // Trace-normalised T = Q^H R_fb Q from the covariance; false when R is zero
 // or not finite (no signal subspace).
 template <int L>
