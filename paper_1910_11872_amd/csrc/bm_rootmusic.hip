@@ -76,7 +76,7 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
                 R.re[i][j] = v.x;
                 R.im[i][j] = (i == j) ? 0.f : v.y;
             }
-        window_omega<L, JACOBI>(R, tmpl, full_roots, omega, flag, ls);
+        window_omega<L, JACOBI>(R, tmpl, full_roots, K, omega, flag, ls);
     } else {
         flag |= BM_FLAG_UNDEFINED;
     }
@@ -144,12 +144,12 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
         if (J.bdirs & BM_DIR_X) {
             Cov<L> R;
             block_cov<L, BLOCK>(sR, t, true, R);
-            window_omega<L, JACOBI>(R, tmpl, full_roots, wx, fx, ls);
+            window_omega<L, JACOBI>(R, tmpl, full_roots, L, wx, fx, ls);
         }
         if (J.bdirs & BM_DIR_Y) {
             Cov<L> R;
             block_cov<L, BLOCK>(sR, t, false, R);
-            window_omega<L, JACOBI>(R, tmpl, full_roots, wy, fy, ls);
+            window_omega<L, JACOBI>(R, tmpl, full_roots, L, wy, fy, ls);
         }
         if (J.phase && finitef(wx) && finitef(wy)) {
             float exr[L], exi[L];
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kGatherBlock) void rootmusic_gather_kernel(RmBatch 
         }
         float omega = __builtin_nanf("");
         unsigned flag = 0;
-        window_omega<L, JACOBI>(R, B.tmpl, B.full_roots != 0, omega, flag, ls);
+        window_omega<L, JACOBI>(R, B.tmpl, B.full_roots != 0, K, omega, flag, ls);
         store_omega(J, line, p, omega, flag);
     }
     // the surrogate kernel owns the accepted/rejected counters of its windows

@@ -15,14 +15,14 @@
 //      T = Q^H R_fb Q, its top eigenvector by power iteration seeded with the
 //      steering vector of omega_hat, and the MUSIC null spectrum at
 //      omega_hat (reject above tau);
-//   5. Newton iterations in FP64 on the quadratic factor of the root-MUSIC
-//      polynomial (paper Eq. 12) started from the double root at the
-//      frequency of the eigenvector's lag-1 coefficient;
-//      accept when the factor converged to a conjugate-reciprocal pair and a
-//      Schur-Cohn count on the deflated polynomial shows no other root as
-//      near the unit circle, so that the pair is the one the plain path
-//      selects: omega = arg(z1 + z2) as in the plain path; otherwise the
-//      window goes to the reject list, which the plain gather kernel finishes.
+//   5. Newton iterations in FP64 for the signal root of the root-MUSIC
+//      polynomial (paper Eq. 12), its mate divided out, started at the
+//      frequency of the eigenvector's lag-1 coefficient; accept when the
+//      root's pair divides the polynomial and a Schur-Cohn count on the
+//      quotient shows no other root as near the unit circle, so that the
+//      pair is the one the plain path selects: omega = arg(z1 + z2) as in the
+//      plain path; otherwise the window goes to the reject list, which the
+//      plain gather kernel finishes.
 #include "bm_window.h"
 
 #include <algorithm>
@@ -154,7 +154,7 @@ __device__ __forceinline__ void steering_real(float w, float (&v0)[L]) {
 // (Sec. 3): its roots are a conjugate-reciprocal pair (z, 1/conj z), and
 // the quotient polynomial has all its inner roots strictly inside |z| < |z_in|.
 template <int L>
-__device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, float& omega) {
+__device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, int K, float& omega) {
     constexpr int n = 2 * L - 2;
     Sym<L> T;
     if (!normalised_T<L>(R, T)) return false;
@@ -162,6 +162,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
     steering_real<L>(what, v0);
 #pragma unroll
     for (int i = 0; i < L; ++i) v[i] = v0[i];
+    float lam = 1.f;                        // |T v| of the last step: lambda_1 of the trace-1 T
     for (int it = 0; it < kPowerSteps; ++it) {
         float y[L];
 #pragma unroll
@@ -175,6 +176,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
 #pragma unroll
         for (int i = 0; i < L; ++i) n2 = fmaf(y[i], y[i], n2);
         const float in = frsq(n2);
+        lam = n2 * in;
 #pragma unroll
         for (int i = 0; i < L; ++i) v[i] = y[i] * in;
     }
@@ -189,16 +191,14 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, f
     poly_coeffs<L>(ur, ui, ar, ai);
     // The signal eigenvector seeded by the prediction now gives a sharper
     // frequency than the prediction itself: u1[i+1]/u1[i] ~ e^{j w}, so the
-    // lag-1 coefficient c_1 ~ -((L-1)/L) e^{-j w}.  Newton starts from the
-    // factor of its double root e^{j w1}: r = 2 e^{j w1}, s = -e^{2 j w1}.
+    // lag-1 coefficient c_1 ~ -((L-1)/L) e^{-j w}.  Newton for the signal
+    // root (its mate divided out) starts there.
     const float w1 = atan2f(ai[L], -ar[L]);
-    float sw, cw;
-    sincosf(w1, &sw, &cw);
-    double rr = 2.0 * cw, ri = 2.0 * sw, s_r = -((double)cw * cw - (double)sw * sw), s_i = -2.0 * (double)cw * sw;
-    double last = 0.0;
-    if (!bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kRefineIters, last, kPairStepTol)) return false;
-    if (!(last <= kPairAcceptTol * (fabs(rr) + fabs(ri)))) return false;
-    if (!certified_pair<L>(ar, ai, rr, ri, s_r, s_i)) return false;
+    double zr, zi, last = 0.0, rr = 0.0, ri = 0.0;
+    pair_start(w1, lam, K, zr, zi);
+    if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, kPairStepTol, last, nullptr)) return false;
+    if (!(last <= kPairAcceptTol * (fabs(zr) + fabs(zi)))) return false;
+    if (!certified_root<L>(ar, ai, zr, zi, rr, ri)) return false;
     const float w = atan2f((float)ri, (float)rr);
     omega = w;
     return finitef(w);
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
             for (int i = 0; i + 1 < L; ++i) { sr += R.re[i][i + 1]; si -= R.im[i][i + 1]; }
             wh = atan2f(si, sr);
         }
-        if (refine<L>(R, wh, S.tau, omega)) acc = 1;
+        if (refine<L>(R, wh, S.tau, K, omega)) acc = 1;
         else reject = true;
     } else {
         flag |= BM_FLAG_UNDEFINED;

@@ -37,10 +37,10 @@ constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
 constexpr float kRootTol2 = BM_ROOT_TOL2;
 constexpr int kPolishIters = BM_POLISH_ITERS;
 constexpr int kCertIters = 8;     // at most this many FP64 Newton steps before the pair certificate
-// Newton on the quadratic factor converges quadratically: after a step of
+// Newton with the mate divided out converges quadratically: after a step of
 // relative size d the error is of order d^2, so iterating stops once a step
-// is below 1e-7 |r| (error ~1e-14), and a factor whose last step is above
-// 1e-6 |r| is not trusted.
+// is below 1e-7 |z| (error ~1e-14), and a root whose last step is above
+// 1e-6 |z| is not trusted.
 constexpr double kPairStepTol = 1e-7;
 constexpr double kPairAcceptTol = 1e-6;
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
@@ -104,7 +104,7 @@ __device__ __forceinline__ void build_T(const Cov<L>& R, Sym<L>& T) {
 // Householder tridiagonalisation, Newton from above on det(xI - T_tri),
 // shifted inverse iteration on the tridiagonal matrix, back-transformation.
 template <int L>
-__device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int& its) {
+__device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int& its, float& lam) {
     float hv[L][L];   // reflector k lives in hv[k][k+1 .. L-1]
     float hb[L];
     float e[L];
@@ -176,6 +176,7 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
         x -= step;
         if (!(fabsf(step) > 1e-7f * x)) break;
     }
+    lam = x;
     // (sigma I - T_tri) y = y_prev, LDL^T without pivoting; sigma just above lambda_1
     const float sigma = x * 1.000002f + 1e-30f;
     float y[L];
@@ -222,7 +223,7 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
 
 // Same eigenvector by cyclic Jacobi rotations (selectable alternative).
 template <int L>
-__device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int& sweeps) {
+__device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int& sweeps, float& lam) {
     float V[L][L];
 #pragma unroll
     for (int i = 0; i < L; ++i)
@@ -276,6 +277,7 @@ __device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int&
 #pragma unroll
         for (int i = 0; i < L; ++i) v[i] = b ? V[i][k] : v[i];
     }
+    lam = best;
 }
 
 
@@ -444,46 +446,98 @@ __device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], doubl
 }
 
 
-constexpr double kMateTol = 1e-6;     // |z1 conj(z2) - 1| of a certified pair
 constexpr double kCertMargin = 1e-6;  // relative radius margin of the nearest-pair certificate
 
-// True when the converged quadratic factor z^2 - r z - s of the root-MUSIC
-// polynomial (coefficients ar, ai; paper Eq. 12) holds the root pair nearest
-// the unit circle, i.e. the pair the selection rule of Sec. 3 picks from all
-// roots.  Every root of this polynomial has its mate 1/conj(z) (c_{-k} =
-// conj(c_k)), so the nearest pair is the one with the largest inner radius:
-// the factor's roots must be such a pair, z1 conj(z2) = 1, and the quotient
-// Q = P / (z^2 - r z - s) must have all its L - 2 inner roots strictly inside
-// |z| < |z_in| (1 - margin), counted by Schur-Cohn on Q(rho z).
-template <int L>
-__device__ __forceinline__ bool certified_pair(const float (&ar)[2 * L - 1], const float (&ai)[2 * L - 1], double rr,
-                                               double ri, double s_r, double s_i) {
-    constexpr int n = 2 * L - 2;
-    // roots of the factor: (r +- sqrt(r^2 + 4 s)) / 2
-    const double dr = rr * rr - ri * ri + 4.0 * s_r, di = 2.0 * rr * ri + 4.0 * s_i;
-    const double md = sqrt(dr * dr + di * di);
-    const double qr = sqrt(fmax(0.0, 0.5 * (md + dr)));
-    const double qi = copysign(sqrt(fmax(0.0, 0.5 * (md - dr))), di);
-    const double z1r = 0.5 * (rr + qr), z1i = 0.5 * (ri + qi);
-    const double z2r = 0.5 * (rr - qr), z2i = 0.5 * (ri - qi);
-    const double pr = z1r * z2r + z1i * z2i, pi = z1i * z2r - z1r * z2i;
-    if (!(fabs(pr - 1.0) + fabs(pi) < kMateTol)) return false;
-    if (L == 2) return true;                       // no other roots
-    const double rin = sqrt(fmin(z1r * z1r + z1i * z1i, z2r * z2r + z2i * z2i));
-    // quotient by synthetic division, then Q(rho z)
-    double fr[n - 1], fi[n - 1];
-    {
-        double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * fma(-x, r, 2.0);              // two Newton steps on the hardware estimate
+    return r * fma(-x, r, 2.0);
+}
+
+// Newton's iteration for a root z of the root-MUSIC polynomial (coefficients
+// ar, ai; paper Eq. 12) whose mate 1/conj(z) is a root as well -- every root
+// of this polynomial has its mate, c_{-k} = conj(c_k) -- with the mate divided
+// out (Maehly's correction), which keeps the convergence quadratic although
+// the two roots nearly coincide near the unit circle:
+//   z <- z - P(z) / (P'(z) - P(z) / (z - 1/conj(z)))
+// At most `iters` steps, fewer once a step is below tol |z|; false when a
+// step is not finite.  `lastc` receives |dz| of the last step.
+template <int n>
+__device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const float (&ai)[n + 1], double& zr, double& zi,
+                                            int iters, double tol, double& lastc, int* its) {
+    for (int it = 0; it < iters; ++it) {
+        if (its) ++*its;
+        double Pr = ar[n], Pi = ai[n], Dr = 0.0, Di = 0.0;
 #pragma unroll
-        for (int k = n; k >= 2; --k) {
-            const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
-            const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
+        for (int j = n - 1; j >= 0; --j) {
+            const double nDr = fma(Dr, zr, fma(-Di, zi, Pr)), nDi = fma(Dr, zi, fma(Di, zr, Pi));
+            const double nPr = fma(Pr, zr, fma(-Pi, zi, (double)ar[j]));
+            const double nPi = fma(Pr, zi, fma(Pi, zr, (double)ai[j]));
+            Dr = nDr; Di = nDi; Pr = nPr; Pi = nPi;
+        }
+        // u = z - 1/conj(z) = z (1 - 1/|z|^2); step = P u / (P' u - P)
+        const double f = 1.0 - rcp64(fma(zr, zr, zi * zi));
+        const double ur = zr * f, ui = zi * f;
+        const double nr = fma(Pr, ur, -Pi * ui), ni = fma(Pr, ui, Pi * ur);
+        const double dr = fma(Dr, ur, -Di * ui) - Pr, di = fma(Dr, ui, Di * ur) - Pi;
+        const double q = rcp64(fma(dr, dr, di * di));
+        const double sr = fma(nr, dr, ni * di) * q, si = fma(ni, dr, -nr * di) * q;
+        if (!(__builtin_isfinite(sr) && __builtin_isfinite(si))) return false;
+        zr -= sr;
+        zi -= si;
+        lastc = fabs(sr) + fabs(si);
+        if (lastc <= tol * (fabs(zr) + fabs(zi))) break;
+    }
+    return true;
+}
+
+// True when the root z0 (with its mate 1/conj(z0)) is the root pair nearest
+// the unit circle, i.e. the pair the selection rule of Sec. 3 picks from all
+// roots.  Every root pair (z, 1/conj z) has its inner member at radius < 1,
+// and the nearest pair is the one with the largest inner radius, so with
+// z_in the inner member of z0's pair: (z - z_in)(z - 1/conj z_in) must divide
+// P (remainder below 1e-8 of the coefficients' size; a root on the circle,
+// its own mirror, fails here), and the quotient Q must have all its L - 2
+// inner roots strictly inside |z| < |z_in| (1 - margin), counted by
+// Schur-Cohn on Q(rho z).  On success (rr, ri) = z_in + 1/conj(z_in).
+template <int L>
+__device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], const float (&ai)[2 * L - 1], double z0r,
+                                               double z0i, double& rr, double& ri) {
+    constexpr int n = 2 * L - 2;
+    double m2 = fma(z0r, z0r, z0i * z0i);
+    if (!(m2 > 0.0) || !__builtin_isfinite(m2)) return false;
+    if (m2 > 1.0) {                                   // take the inner member
+        const double im = rcp64(m2);
+        z0r *= im;
+        z0i *= im;
+        m2 = fma(z0r, z0r, z0i * z0i);
+    }
+    const double rin = sqrt(m2);
+    if (!(1.0 - rin > 1e-9)) return false;
+    const double im2 = rcp64(m2);
+    const double z1r = z0r * im2, z1i = z0i * im2;   // 1/conj(z_in)
+    rr = z0r + z1r;
+    ri = z0i + z1i;
+    // z^2 - r z - s with s = -z_in / conj(z_in)
+    const double s_r = -(z0r * z1r - z0i * z1i), s_i = -(z0r * z1i + z0i * z1r);
+    double fr[n - 1], fi[n - 1];
+    double scale = 0.0;
+    double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
+#pragma unroll
+    for (int k = n; k >= 0; --k) {
+        const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
+        const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
+        scale += fabs((double)ar[k]) + fabs((double)ai[k]);
+        if (k >= 2) {
             fr[k - 2] = bkr;
             fi[k - 2] = bki;
-            b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
         }
+        b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
     }
-    const double rho = fmin(rin, 1.0) * (1.0 - kCertMargin);
+    // remainder b1 (z - r) + b0: here b2 = b_1 and b1 = b_0
+    if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= 1e-8 * scale)) return false;
+    if (L == 2) return true;                          // no other roots
+    const double rho = rin * (1.0 - kCertMargin);
     double rp = 1.0;
 #pragma unroll
     for (int k = 1; k <= n - 2; ++k) {
@@ -492,6 +546,17 @@ __device__ __forceinline__ bool certified_pair(const float (&ar)[2 * L - 1], con
         fi[k] *= rp;
     }
     return zeros_inside_unit_disk<n - 2>(fr, fi) == L - 2;
+}
+
+// Start of the pair iteration: the guessed frequency at the radius the
+// signal root typically has, 1 - r ~ 1.6 (1 - lambda_1) / K for K
+// snapshots and lambda_1 the trace-normalised top eigenvalue.
+__device__ __forceinline__ void pair_start(float w, float lam, int K, double& zr, double& zi) {
+    const float r0 = fminf(0.9999f, fmaxf(0.9f, 1.f - 1.6f * (1.f - lam) / (float)K));
+    float sw, cw;
+    sincosf(w, &sw, &cw);
+    zr = (double)(r0 * cw);
+    zi = (double)(r0 * sw);
 }
 
 // Lag sums of lane t: S_d = sum_{k<K} g[t+k] conj(g[t+k+d]), d < L, from the
@@ -557,7 +622,7 @@ __device__ __forceinline__ bool normalised_T(const Cov<L>& R, Sym<L>& T) {
 // FP64 pair polish.  omega stays NaN and BM_FLAG_UNDEFINED is set when the
 // covariance is zero or not finite.
 template <int L, bool JACOBI>
-__device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots,
+__device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots, int K,
                                              float& omega, unsigned& flag, LaneStats& ls) {
     constexpr int n = 2 * L - 2;
     Sym<L> T;
@@ -568,8 +633,9 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     ls.counted += 1;
     // ---- signal subspace (Eq. 6-11) ------------------------------------
     float v[L];
-    if (JACOBI) top_eigvec_jacobi<L>(T, v, ls.eig_its);
-    else top_eigvec_tridiag<L>(T, v, ls.eig_its);
+    float lam = 1.f;
+    if (JACOBI) top_eigvec_jacobi<L>(T, v, ls.eig_its, lam);
+    else top_eigvec_tridiag<L>(T, v, ls.eig_its, lam);
     float ur[L], ui[L];
     signal_vector<L>(v, ur, ui);
     // ---- polynomial coefficients (Eq. 12-14) -----------------------------
@@ -582,17 +648,16 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     sincosf(w0, &sw0, &cw0);
 
     // ---- certified pair ---------------------------------------------------
-    // FP64 Newton on the quadratic factor holding the double root e^{j w0};
-    // when the factor is certified as the pair nearest the unit circle it is
-    // the pair the selection rule picks from all roots, and its sum gives
-    // omega exactly as below.  Otherwise every root is found.
+    // FP64 Newton (with the mate divided out) for the signal root from the
+    // guess w0; when its pair is certified as the pair nearest the unit
+    // circle it is the pair the selection rule picks from all roots, and its
+    // sum gives omega exactly as below.  Otherwise every root is found.
     bool cert = false;
     if (!full_roots) {
-        double rr = 2.0 * cw0, ri = 2.0 * sw0;
-        double s_r = -((double)cw0 * cw0 - (double)sw0 * sw0), s_i = -2.0 * (double)cw0 * sw0;
-        double lastc = 0.0;
-        cert = bairstow<double, n>(ar, ai, rr, ri, s_r, s_i, kCertIters, lastc, kPairStepTol, &ls.pair_its) &&
-               lastc <= kPairAcceptTol * (fabs(rr) + fabs(ri)) && certified_pair<L>(ar, ai, rr, ri, s_r, s_i);
+        double zr0, zi0, lastc = 0.0, rr = 0.0, ri = 0.0;
+        pair_start(w0, lam, K, zr0, zi0);
+        cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, kPairStepTol, lastc, &ls.pair_its) &&
+               lastc <= kPairAcceptTol * (fabs(zr0) + fabs(zi0)) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
         if (cert) omega = atan2f((float)ri, (float)rr);
     }
     ls.accepted += cert ? 1 : 0;
