@@ -36,7 +36,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
 constexpr int kPowerSteps = 6;
-constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps on the quadratic factor
+constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps for the signal root
 constexpr int kPredictStride = 4;     // one network prediction per this many windows
 static_assert(kSurBlock / kPredictStride == 16 * (kSurBlock / 64), "one 16-window MLP tile per wave");
 
@@ -147,12 +147,12 @@ __device__ __forceinline__ void steering_real(float w, float (&v0)[L]) {
 
 // Refinement of a predicted frequency; true when the estimate is accepted.
 // The estimate is judged by the MUSIC null spectrum at the prediction, then
-// the quadratic factor z^2 - r z - s of the root-MUSIC polynomial (paper
-// Eq. 12) holding the predicted double root is found by Newton's method in
-// FP64, and the window is accepted only when that factor is the pair of
-// roots nearest the unit circle, which is the pair the plain path selects
-// (Sec. 3): its roots are a conjugate-reciprocal pair (z, 1/conj z), and
-// the quotient polynomial has all its inner roots strictly inside |z| < |z_in|.
+// the signal root of the root-MUSIC polynomial (paper Eq. 12) is found by
+// Newton's method in FP64 with its conjugate-reciprocal mate divided out,
+// and the window is accepted only when that pair (z, 1/conj z) is the pair
+// of roots nearest the unit circle, which is the pair the plain path
+// selects (Sec. 3): the polynomial divides by the pair's factor and the
+// quotient has all its inner roots strictly inside |z| < |z_in|.
 template <int L>
 __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, int K, float& omega) {
     constexpr int n = 2 * L - 2;
