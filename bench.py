@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
 # certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
 # frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (39190.375 * 2.0 + 33792.0) * 1024 / (4 * 2 * 1024 * 1024)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (39226.9375 * 2.0 + 33792.0) * 1024 / (4 * 2 * 1024 * 1024)
 
 
 def bairstow_flops(n: int) -> int:
@@ -42,13 +42,19 @@ def bairstow_flops(n: int) -> int:
     return 32 * (n + 1) + 60
 
 
+def pair_newton_flops(n: int) -> int:
+    """One FP64 Newton step for the signal root with its mate divided out: Horner for P and P'
+    (16 flops per coefficient) and the corrected step (two refined reciprocals, ~62 flops)."""
+    return 16 * n + 62
+
+
 def certificate_flops(L: int) -> int:
-    """Roots of the factor, mate test, deflation, scaling and the Schur-Cohn
-    recursion on the degree 2L-4 quotient (FP64)."""
+    """Inner member and mate of the root, division by the pair's factor with the remainder test,
+    scaling and the Schur-Cohn recursion on the degree 2L-4 quotient (FP64)."""
     n = 2 * L - 2
     m = n - 2
-    schur = sum(20 * (d // 2) + 10 for d in range(1, m + 1))
-    return 60 + 16 * (n - 1) + 3 * m + schur
+    schur = sum(20 * (d // 2) + 16 for d in range(1, m + 1))
+    return 40 + 18 * (n + 1) + 3 * m + schur
 
 
 def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,
@@ -57,8 +63,8 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
 
     FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` is the
     measured mean number of Newton steps for the largest eigenvalue per
-    window, `pair_iters` the mean FP64 Newton steps on the quadratic factor
-    before the certified-pair test, `cert_frac` the fraction of windows
+    window, `pair_iters` the mean FP64 Newton steps for the signal root
+    before the certificate, `cert_frac` the fraction of windows
     finished by the certificate, and `iters` the mean simultaneous root
     iterations of the windows whose roots were all found.  Certificate work
     of a window that fails it is not counted.  `block`: the L x L block
@@ -82,7 +88,7 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
     fp32 = common32 + full * (start + aberth + select)
-    fp64 = pair_iters * bairstow_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
+    fp64 = pair_iters * pair_newton_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
 
@@ -91,8 +97,8 @@ def surrogate_flops_per_window(L: int, N: int) -> dict:
     the first point where a window can be rejected (so a lower bound for the
     accepted ones): features and the MLP of one window in four (matrix-core
     flops kept apart, GELU as its A&S erf: 16 flops), lag sums, the real transform, the power
-    iteration, the polynomial, three FP64 Newton steps on the quadratic
-    factor and the certificate.  Transcendentals count as one flop."""
+    iteration, the polynomial, three FP64 Newton steps for the signal root
+    and the certificate.  Transcendentals count as one flop."""
     K = N - L + 1
     n = 2 * L - 2
     stride = 4                                        # one network prediction per 4 windows
@@ -104,7 +110,7 @@ def surrogate_flops_per_window(L: int, N: int) -> dict:
     power = 6 * (2 * L * L + 3 * L + 1) + 2 * L
     coef = 2 * L + 8 * L * (L + 1) // 2
     fp32 = feat + mlp_valu + lag + build_t + power + coef + 20
-    fp64 = 3 * bairstow_flops(n) + certificate_flops(L)
+    fp64 = 3 * pair_newton_flops(n) + certificate_flops(L)
     return {"fp32": fp32, "fp64": fp64, "mfma": mlp_mfma, "valu": fp32 + fp64}
 
 
@@ -237,6 +243,12 @@ def workload(name, nframes):
             desc = ("surrogate MLP 32-64-64-2 (GELU, BF16 MFMA, FP32 accumulate) trained on the GPU on 10M "
                     "method-generated windows (carrier 1/16-1/4 cyc/px, SNR 0-30 dB, root-MUSIC L=8 N=32 labels), "
                     "then surrogate + pseudospectrum check + root-MUSIC fallback on " + desc)
+    elif name == "exp":
+        fr = [wl.exp_frame(i) for i in range(nframes or 19)]
+        desc = (f"{len(fr)} time-lapsed 1850x700 8-bit frames (stand-in for the paper's experimental diffusion "
+                f"series), carrier 0.11 cyc/px at 35 deg, 5*erf phase, SNR 12 dB; x and y windows N=15, L=7; "
+                f"analytic step through Bluestein's identity (neither length is 5-smooth); "
+                f"plain root-MUSIC + FP64 phase integration")
     else:
         raise SystemExit(f"unknown workload {name}")
     return fr, desc
@@ -247,7 +259,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "exp"])
     ap.add_argument("--train-windows", type=int, default=10_000_000, help="cfg5: training set size")
     ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: Adam steps")
     ap.add_argument("--train-batch", type=int, default=16384, help="cfg5: minibatch")

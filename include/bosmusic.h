@@ -67,6 +67,7 @@ enum {
     BM_F32 = 2, /* real float       */
     BM_F64 = 3, /* real double      */
     BM_C32 = 4, /* interleaved complex float: Gamma of Eq. 1 given directly */
+    BM_U8 = 5,  /* real unsigned 8-bit, the camera's own samples (Sec. 4) */
 };
 
 /* directions, and the window shape */
@@ -114,7 +115,7 @@ typedef struct {
 
 typedef struct {
     const void* data;   /* device pointer to height rows of row_stride elements */
-    int32_t dtype;      /* BM_F16 / BM_F32 / BM_F64 / BM_C32 */
+    int32_t dtype;      /* BM_F16 / BM_F32 / BM_F64 / BM_C32 / BM_U8 */
     int32_t width;      /* pixels per row  (1 .. max_width)  */
     int32_t height;     /* number of rows  (1 .. max_height) */
     int64_t row_stride; /* elements between row starts, >= width */
@@ -139,8 +140,8 @@ typedef struct {
                                BM_PLAIN: windows finished by the certified pair */
     uint64_t sur_rejected;  /* BM_SURROGATE: windows sent to the plain fallback;
                                BM_PLAIN: windows whose roots were all found */
-    uint64_t pair_iters;    /* sum over windows of FP64 Newton steps on the quadratic factor
-                               before the certified-pair test (BM_PLAIN) */
+    uint64_t pair_iters;    /* sum over windows of FP64 Newton steps for the signal root
+                               (its mate divided out) before the certificate */
     uint64_t rm_launches;   /* root-MUSIC kernel launches timed (BM_OPT_TIMING) */
     uint64_t rm_time_ns;    /* their summed duration between HIP events, ns */
 } bosmusic_stats;
@@ -165,9 +166,11 @@ bm_status bosmusic_destroy(bosmusic_t h);
  * lag-1 predictor is configured, and N >= 16 for every frame).
  * Requirements per frame: 2 <= L <= 8, L <= N <= 64, width/height within
  * the handle's maximum, row_stride >= width; for real dtypes the length of
- * every requested direction must factor into 2, 3 and 5 and be <= 8192
- * (exact DFT analytic step).  A window longer than the frame is not an error:
- * the whole map is NaN. */
+ * every requested direction must either factor into 2, 3 and 5 and be
+ * <= 8192, or be <= 4096 (any factors: the exact DFT of the analytic step
+ * then goes through Bluestein's chirp-z identity at a 5-smooth length
+ * >= 2n - 1, about four times the transform work).  A window longer than the
+ * frame is not an error: the whole map is NaN. */
 bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_t n_frames,
                               int32_t mode, void* stream);
 
@@ -196,11 +199,12 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
  * and its three neighbours.  w_hat seeds a power iteration for the signal
  * eigenvector u1; the window is
  * rejected when the MUSIC null spectrum 1 - |u1^H a(w_hat)|^2 / L at the
- * prediction exceeds tau.  Newton iterations (FP64) on the quadratic factor
- * of the root-MUSIC polynomial (paper Eq. 12) started from the double root
- * e^{j w_hat} then find a root pair, and the window is accepted only when
- * the pair is conjugate-reciprocal and a Schur-Cohn count on the deflated
- * polynomial shows that no other root lies as near the unit circle: the
+ * prediction exceeds tau.  Newton iterations (FP64) for the signal root of
+ * the root-MUSIC polynomial (paper Eq. 12), its conjugate-reciprocal mate
+ * divided out, start just inside the unit circle at the eigenvector's
+ * lag-1 phase; the window is accepted only when the polynomial divides by
+ * the pair's factor (z - z_in)(z - 1/conj z_in) and a Schur-Cohn count on
+ * the quotient shows that no other root lies as near the unit circle: the
  * accepted pair is then the pair the plain path selects (Sec. 3, Eq. 15),
  * and w = arg(z1 + z2) as there.  Every other window is finished by the
  * plain path, so the output equals the plain output up to rounding.

@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libbosmusic.so")
 
 BM_OK, BM_E_INVALID_ARG, BM_E_UNSUPPORTED, BM_E_NOMEM, BM_E_DEVICE = 0, -1, -2, -3, -4
-BM_F16, BM_F32, BM_F64, BM_C32 = 1, 2, 3, 4
+BM_F16, BM_F32, BM_F64, BM_C32, BM_U8 = 1, 2, 3, 4, 5
 BM_DIR_X, BM_DIR_Y, BM_BLOCK = 1, 2, 4
 BM_PLAIN, BM_SURROGATE = 0, 1
 BM_OPT_STATS = 1
@@ -134,7 +134,8 @@ def _stream_ptr(stream):
 
 def _dtype_code(t):
     import torch
-    m = {torch.float16: BM_F16, torch.float32: BM_F32, torch.float64: BM_F64, torch.complex64: BM_C32}
+    m = {torch.float16: BM_F16, torch.float32: BM_F32, torch.float64: BM_F64, torch.complex64: BM_C32,
+         torch.uint8: BM_U8}
     if t.dtype not in m:
         raise TypeError(f"unsupported frame dtype {t.dtype}")
     return m[t.dtype]

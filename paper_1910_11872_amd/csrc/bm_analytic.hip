@@ -7,7 +7,11 @@
 // 0 < 2k < n, 0 otherwise, so DC and Nyquist are removed and the carrier is
 // kept), and transformed back with the same forward FFT applied to the
 // conjugate.  Twiddles come from a per-length table computed in FP64 on the
-// host and rounded once.
+// host and rounded once.  A length with a prime factor above 5 takes each DFT
+// by Bluestein's identity jk = (j^2 + k^2 - (k-j)^2) / 2: with the chirp
+// w_j = e^{-i pi j^2 / n}, X_k = w_k sum_j (x_j w_j) conj(w_{k-j}), a linear
+// convolution done as a circular one of 5-smooth length m >= 2n - 1 (two
+// length-m FFTs against the precomputed transform of the conjugate chirp).
 #include "bm_internal.h"
 
 namespace bm {
@@ -98,6 +102,32 @@ __device__ float2* fft_forward(float2* a, float2* b, int n, const FftPlan& plan,
     return a;
 }
 
+// DFT of the n samples at a[0..n): a direct mixed-radix FFT, or Bluestein's
+// chirp-z route through length plan.n = m.  a and b hold m elements each;
+// returns the buffer holding X[0..n) in natural order.
+__device__ float2* dft_line(float2* a, float2* b, const FftJob& J) {
+    const int n = J.n, m = J.plan.n;
+    if (!J.chirp) return fft_forward(a, b, n, J.plan, J.tw);
+    for (int i = threadIdx.x; i < m; i += kFftThreads)
+        a[i] = i < n ? cmul(a[i], J.chirp[i]) : make_float2(0.f, 0.f);
+    __syncthreads();
+    float2* P = fft_forward(a, b, m, J.plan, J.tw);
+    float2* Q = (P == a) ? b : a;
+    // circular convolution with conj(w): inverse DFT as the conjugate of a forward one
+    for (int k = threadIdx.x; k < m; k += kFftThreads) {
+        const float2 v = cmul(P[k], J.kern[k]);
+        P[k] = make_float2(v.x, -v.y);
+    }
+    __syncthreads();
+    float2* Y = fft_forward(P, Q, m, J.plan, J.tw);
+    for (int k = threadIdx.x; k < n; k += kFftThreads) {
+        const float2 v = Y[k];
+        Y[k] = cmul(make_float2(v.x, -v.y), J.chirp[k]);
+    }
+    __syncthreads();
+    return Y;
+}
+
 // Index of the job that owns work item w: prefix[j] <= w < prefix[j+1].
 __device__ __forceinline__ int find_job(const int* prefix, int njobs, int w) {
     int lo = 0, hi = njobs - 1;
@@ -112,6 +142,7 @@ __device__ __forceinline__ int find_job(const int* prefix, int njobs, int w) {
 __device__ __forceinline__ float load_real(const void* base, int64_t idx, int elem) {
     if (elem == (int)Elem::F16) return (float)static_cast<const _Float16*>(base)[idx];
     if (elem == (int)Elem::F64) return (float)static_cast<const double*>(base)[idx];
+    if (elem == (int)Elem::U8) return (float)static_cast<const unsigned char*>(base)[idx];
     return static_cast<const float*>(base)[idx];
 }
 
@@ -121,15 +152,14 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B) {
     const int j = find_job(B.prefix, B.njobs, blockIdx.x);
     const FftJob& J = B.jobs[j];
     const int line = blockIdx.x - B.prefix[j];
-    const int n = J.plan.n;
+    const int n = J.n;
     const int elem = J.elem;
     float2* a = lds;
-    float2* b = lds + n;
+    float2* b = lds + J.plan.n;
     const int64_t off = (int64_t)line * J.src_ls;
     for (int i = threadIdx.x; i < n; i += kFftThreads) a[i] = make_float2(load_real(J.src, off + i, elem), 0.f);
     __syncthreads();
-    const FftPlan& plan = J.plan;
-    float2* X = fft_forward(a, b, n, plan, J.tw);
+    float2* X = dft_line(a, b, J);
     float2* other = (X == a) ? b : a;
     // one-sided mask and 1/n, then conjugate so that a forward DFT inverts
     const float sc = 2.0f / (float)n;
@@ -139,7 +169,7 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B) {
         X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    float2* Y = fft_forward(X, other, n, plan, J.tw);
+    float2* Y = dft_line(X, other, J);
     float2* out = J.dst + (int64_t)line * n;
     for (int i = threadIdx.x; i < n; i += kFftThreads) {
         const float2 v = Y[i];

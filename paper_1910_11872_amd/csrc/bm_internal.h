@@ -25,7 +25,7 @@ struct FftPlan {
 };
 
 // Input element types of the analytic / transpose kernels.
-enum class Elem : int { F16 = 1, F32 = 2, F64 = 3, C32 = 4 };
+enum class Elem : int { F16 = 1, F32 = 2, F64 = 3, C32 = 4, U8 = 5 };
 
 // Starting points of the simultaneous root iteration: the roots of the
 // noise-free root-MUSIC polynomial of a single tone at frequency 0, with its
@@ -80,14 +80,19 @@ struct RmBatch {
 };
 
 // Lines of one frame direction for the analytic-signal kernel (one block per line).
+// A length n with a prime factor above 5 takes the DFT by Bluestein's chirp-z
+// identity through a circular convolution of 5-smooth length m = plan.n >= 2n-1.
 struct FftJob {
     const void* src;       // real lines, src_ls elements apart
     int64_t src_ls;
-    float2* dst;           // complex lines, plan.n apart
-    const float2* tw;      // twiddles e^{-2 pi i m / n}, m < n
+    float2* dst;           // complex lines, n apart
+    const float2* tw;      // twiddles e^{-2 pi i k / plan.n}, k < plan.n
+    const float2* chirp;   // Bluestein only: e^{-i pi j^2 / n}, j < n
+    const float2* kern;    // Bluestein only: DFT_m of the conjugate chirp, wrapped, divided by m
     int elem;              // Elem of src
     int nlines;
-    FftPlan plan;
+    int n;                 // line length
+    FftPlan plan;          // plan of n, or of m under Bluestein (chirp != nullptr)
 };
 
 struct FftBatch {

@@ -47,6 +47,7 @@ struct bosmusic_s {
     double* anchor = nullptr;     // integration anchor column (max_h)
     unsigned long long* stats = nullptr;
     std::map<int, float2*> twiddles;
+    std::map<int, float2*> bluestein;   // line length -> chirp (n) then kernel (m) in one allocation
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
     uint64_t rm_launches = 0, rm_time_ns = 0;
     bm::RootTemplate tmpl[bm::kMaxL + 1];
@@ -152,6 +153,37 @@ bool factors_235(int n) {
     return plan_fft(n, p);
 }
 
+// Transform length of Bluestein's route for a line of n samples: the least
+// 5-smooth m >= 2n - 1, or 0 when that exceeds the largest FFT.
+int bluestein_len(int n) {
+    for (int m = std::max(2 * n - 1, 1); m <= bm::kMaxFFT; ++m)
+        if (factors_235(m)) return m;
+    return 0;
+}
+
+// A line of n samples has an exact DFT here: directly or by Bluestein.
+bool dft_supported(int n) { return n >= 1 && (factors_235(n) || bluestein_len(n) > 0); }
+
+// In-place FP64 DFT of a 5-smooth length (recursive decimation in time).
+void dft64(std::vector<std::complex<double>>& x) {
+    const int n = (int)x.size();
+    if (n == 1) return;
+    const int p = n % 2 == 0 ? 2 : (n % 3 == 0 ? 3 : 5);
+    const int q = n / p;
+    std::vector<std::vector<std::complex<double>>> sub(p, std::vector<std::complex<double>>(q));
+    for (int r = 0; r < p; ++r)
+        for (int k = 0; k < q; ++k) sub[r][k] = x[(size_t)k * p + r];
+    for (auto& s : sub) dft64(s);
+    for (int k = 0; k < n; ++k) {
+        std::complex<double> acc = 0.0;
+        for (int r = 0; r < p; ++r) {
+            const double a = -2.0 * M_PI * (double)(((int64_t)r * k) % n) / (double)n;
+            acc += sub[r][k % q] * std::complex<double>(std::cos(a), std::sin(a));
+        }
+        x[k] = acc;
+    }
+}
+
 // Roots of the noise-free root-MUSIC polynomial of a tone at frequency 0.
 // With u1 = a(0)/sqrt(L), sum_k c_k w^{k+L-1} = L w^{L-1} - (1/L) (sum_{i<L} w^i)^2.
 // Its double root at w = 1 is divided out and replaced by (rho, 1/rho); the
@@ -224,9 +256,57 @@ bm_status get_twiddles(bosmusic_s* h, int n, const float2** out) {
     return BM_OK;
 }
 
+// Chirp w_j = e^{-i pi j^2 / n} (j < n) and the length-m DFT of the wrapped
+// conjugate chirp c_t = conj(w_t), |t| < n, divided by m; computed in FP64
+// (the angle reduced exactly as j^2 mod 2n) and rounded once.
+bm_status get_bluestein(bosmusic_s* h, int n, int m, const float2** chirp, const float2** kern) {
+    auto it = h->bluestein.find(n);
+    if (it == h->bluestein.end()) {
+        using cd = std::complex<double>;
+        std::vector<cd> w(n), c(m, cd(0.0, 0.0));
+        for (int j = 0; j < n; ++j) {
+            const int64_t r = ((int64_t)j * j) % (2 * (int64_t)n);
+            const double a = -M_PI * (double)r / (double)n;
+            w[j] = cd(std::cos(a), std::sin(a));
+        }
+        for (int t = 0; t < n; ++t) {
+            c[t] = std::conj(w[t]);
+            if (t > 0) c[m - t] = std::conj(w[t]);
+        }
+        dft64(c);
+        std::vector<float2> host((size_t)n + m);
+        for (int j = 0; j < n; ++j) host[j] = make_float2((float)w[j].real(), (float)w[j].imag());
+        for (int k = 0; k < m; ++k)
+            host[(size_t)n + k] = make_float2((float)(c[k].real() / m), (float)(c[k].imag() / m));
+        float2* d = nullptr;
+        if (hipMalloc(&d, sizeof(float2) * host.size()) != hipSuccess)
+            return fail(h, BM_E_NOMEM, "Bluestein tables of %d", n);
+        if (hipMemcpy(d, host.data(), sizeof(float2) * host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return fail(h, BM_E_DEVICE, "Bluestein table upload failed");
+        }
+        it = h->bluestein.emplace(n, d).first;
+    }
+    *chirp = it->second;
+    *kern = it->second + n;
+    return BM_OK;
+}
+
+// Plan, twiddles and (when n is not 5-smooth) Bluestein tables of a line length.
+bm_status make_fft_job(bosmusic_s* h, int n, bm::FftJob& fj) {
+    fj.n = n;
+    fj.chirp = fj.kern = nullptr;
+    if (plan_fft(n, fj.plan)) return get_twiddles(h, n, &fj.tw);
+    const int m = bluestein_len(n);
+    if (m == 0 || !plan_fft(m, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "line length %d", n);
+    bm_status st = get_twiddles(h, m, &fj.tw);
+    if (st != BM_OK) return st;
+    return get_bluestein(h, n, m, &fj.chirp, &fj.kern);
+}
+
 bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
     if (!f.data) return fail(h, BM_E_INVALID_ARG, "frame %d: data is NULL", idx);
-    if (f.dtype < BM_F16 || f.dtype > BM_C32) return fail(h, BM_E_INVALID_ARG, "frame %d: dtype %d", idx, f.dtype);
+    if (f.dtype < BM_F16 || f.dtype > BM_U8) return fail(h, BM_E_INVALID_ARG, "frame %d: dtype %d", idx, f.dtype);
     if (f.width < 1 || f.height < 1 || f.width > h->max_w || f.height > h->max_h)
         return fail(h, BM_E_INVALID_ARG, "frame %d: size %dx%d outside 1..%dx%d", idx, f.width, f.height, h->max_w,
                     h->max_h);
@@ -243,12 +323,12 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
     if ((f.dirs & BM_DIR_Y) && !f.omega_y) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_y is NULL", idx);
     if (f.dtype != BM_C32) {
         // block windows use the row-wise analytic signal for both directions
-        if (((f.dirs & BM_DIR_X) || (f.dirs & BM_BLOCK)) && !factors_235(f.width))
-            return fail(h, BM_E_UNSUPPORTED, "frame %d: width %d is not 2^a 3^b 5^c <= %d", idx, f.width,
-                        bm::kMaxFFT);
-        if ((f.dirs & BM_DIR_Y) && !(f.dirs & BM_BLOCK) && !factors_235(f.height))
-            return fail(h, BM_E_UNSUPPORTED, "frame %d: height %d is not 2^a 3^b 5^c <= %d", idx, f.height,
-                        bm::kMaxFFT);
+        if (((f.dirs & BM_DIR_X) || (f.dirs & BM_BLOCK)) && !dft_supported(f.width))
+            return fail(h, BM_E_UNSUPPORTED, "frame %d: width %d is neither 2^a 3^b 5^c <= %d nor <= %d", idx,
+                        f.width, bm::kMaxFFT, bm::kMaxFFT / 2);
+        if ((f.dirs & BM_DIR_Y) && !(f.dirs & BM_BLOCK) && !dft_supported(f.height))
+            return fail(h, BM_E_UNSUPPORTED, "frame %d: height %d is neither 2^a 3^b 5^c <= %d nor <= %d", idx,
+                        f.height, bm::kMaxFFT, bm::kMaxFFT / 2);
     }
     return BM_OK;
 }
@@ -331,15 +411,14 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 float2* gx = (float2*)(h->ws + cur);
                 cur += align_up(px * sizeof(float2), 256);
                 bm::FftJob fj{};
-                if (!plan_fft(W, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "width %d", W);
-                if ((st = get_twiddles(h, W, &fj.tw)) != BM_OK) return st;
+                if ((st = make_fft_job(h, W, fj)) != BM_OK) return st;
                 fj.src = f.data;
                 fj.src_ls = f.row_stride;
                 fj.dst = gx;
                 fj.elem = f.dtype;
                 fj.nlines = H;
                 gp.fft.push_back(fj);
-                gp.max_n = std::max(gp.max_n, W);
+                gp.max_n = std::max(gp.max_n, fj.plan.n);
                 gam = gx;
                 gls = W;
             }
@@ -371,15 +450,14 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 float2* gx = (float2*)(h->ws + cur);
                 cur += align_up(px * sizeof(float2), 256);
                 bm::FftJob fj{};
-                if (!plan_fft(W, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "width %d", W);
-                if ((st = get_twiddles(h, W, &fj.tw)) != BM_OK) return st;
+                if ((st = make_fft_job(h, W, fj)) != BM_OK) return st;
                 fj.src = f.data;
                 fj.src_ls = f.row_stride;
                 fj.dst = gx;
                 fj.elem = f.dtype;
                 fj.nlines = H;
                 gp.fft.push_back(fj);
-                gp.max_n = std::max(gp.max_n, W);
+                gp.max_n = std::max(gp.max_n, fj.plan.n);
                 j.gamma = gx;
                 j.gamma_ls = W;
             }
@@ -413,15 +491,14 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 cur += align_up(px * sizeof(float), 256);
                 tj.dst = tr;
                 bm::FftJob fj{};
-                if (!plan_fft(H, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "height %d", H);
-                if ((st = get_twiddles(h, H, &fj.tw)) != BM_OK) return st;
+                if ((st = make_fft_job(h, H, fj)) != BM_OK) return st;
                 fj.src = tr;
                 fj.src_ls = H;
                 fj.dst = gy;
                 fj.elem = BM_F32;
                 fj.nlines = W;
                 gp.fft.push_back(fj);
-                gp.max_n = std::max(gp.max_n, H);
+                gp.max_n = std::max(gp.max_n, fj.plan.n);
             }
             gp.tr.push_back(tj);
             // omega_y is written line-major (coalesced) into a scratch map, then
@@ -903,8 +980,7 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             h->ds_bytes = off;
         }
         bm::FftJob fj{};
-        if (!plan_fft(kLen, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "line length");
-        if ((r = get_twiddles(h, kLen, &fj.tw))) return r;
+        if ((r = make_fft_job(h, kLen, fj))) return r;
         float* lines = (float*)(h->ds + o_lines);
         float2* gamma = (float2*)(h->ds + o_gamma);
         for (int64_t c0 = 0; c0 < count; c0 += chunk) {
@@ -1105,6 +1181,7 @@ void release(bosmusic_s* h) {
     if (h->int_ev) (void)hipEventDestroy(h->int_ev);
     if (h->pin) (void)hipHostFree(h->pin);
     for (auto& kv : h->twiddles) (void)hipFree(kv.second);
+    for (auto& kv : h->bluestein) (void)hipFree(kv.second);
     for (auto* v : {&h->ev_free, &h->ev_pending})
         for (auto& e : *v) {
             (void)hipEventDestroy(e.first);

@@ -32,6 +32,7 @@ CASES = [
     (576, 36, 6, np.float32, 8.0),
     (250, 48, 7, np.float64, 3.0),
     (512, 33, 8, np.float16, 10.0),
+    (263, 30, 5, np.float32, 6.0),       # prime width: the row DFT goes through Bluestein's identity
 ]
 
 

@@ -70,6 +70,7 @@ CASES = [
     (250, 45, 7, 20, np.float64),
     (512, 32, 8, 32, np.float16),
     (360, 60, 8, 64, np.float32),
+    (384, 50, 7, 15, np.uint8),
 ]
 
 
@@ -148,6 +149,18 @@ def test_cfg4_frame_fp16_full_size_sampled(dem, torch):
     print("y", compare_omega(gy[:, cols].T, oracle_cols(f.data, cols, f.L, f.N), "cfg4 y"))
 
 
+def test_experimental_series_u8_sampled(dem, torch):
+    """Stand-in for the paper's experimental series: 1850 x 700 8-bit frames (neither
+    length is 5-smooth), line windows N = 15, L = 7, first and last frame."""
+    for i in (0, 18):
+        f = wl.exp_frame(i)
+        gx, gy = run(dem, torch, f.data, f.L, f.N, "xy")
+        rows = [0, 7, 349, 350, 699]
+        cols = [3, 925, 1849]
+        print("x", compare_omega(gx[rows], oracle_rows(f.data, rows, f.L, f.N), f"exp {i} x"))
+        print("y", compare_omega(gy[:, cols].T, oracle_cols(f.data, cols, f.L, f.N), f"exp {i} y"))
+
+
 # ---------------------------------------------------------------------------
 # Edge cases
 # ---------------------------------------------------------------------------
@@ -181,6 +194,29 @@ def test_max_fft_length_line(dem, torch, bm):
     ox, _ = oracle.demodulate(img, 6, 24, "x")
     compare_omega(wx.cpu().numpy(), ox, "8192 line")
     d.close()
+
+
+BLUESTEIN = [
+    # (W, H, L, N, dtype, dirs): line lengths with a prime factor above 5 take the
+    # analytic step's DFT through Bluestein's identity
+    (1850, 24, 7, 15, np.float32, "x"),      # the paper's experimental frame width (Sec. 4)
+    (48, 700, 5, 15, np.float32, "y"),       # and its height
+    (520, 36, 6, 20, np.float64, "xy"),
+    (263, 70, 4, 16, np.float16, "xy"),      # prime width; height 2 * 5 * 7
+    (4093, 3, 6, 24, np.float32, "x"),       # the largest prime length taken
+    (7, 11, 2, 5, np.float32, "xy"),         # shortest lines
+]
+
+
+@pytest.mark.parametrize("W,H,L,N,dt,dirs", BLUESTEIN)
+def test_any_line_length_by_bluestein(dem, torch, W, H, L, N, dt, dirs):
+    img = wl.random_frame(W, H, seed=W + H, dtype=dt, snr_db=8.0)
+    gx, gy = run(dem, torch, img, L, N, dirs)
+    ox, oy = oracle.demodulate(img, L, N, dirs)
+    if "x" in dirs:
+        print("x", compare_omega(gx, ox, f"x {W}x{H} L{L} N{N}"))
+    if "y" in dirs:
+        print("y", compare_omega(gy, oy, f"y {W}x{H} L{L} N{N}"))
 
 
 def test_flags_mark_borders(dem, torch):
@@ -220,10 +256,12 @@ def test_invalid_arguments_enqueue_nothing(dem, torch, bm):
         assert ei.value.status == bm.BM_E_INVALID_ARG
     torch.cuda.synchronize()
     assert torch.all(wx == 5.0)          # the valid first frame was not run either
-    odd = to_dev(torch, wl.random_frame(77, 64, seed=1))
+    wide = bm.Demodulator(0, max_width=8192, max_height=8)
+    odd = torch.zeros((4, 4099), device="cuda")          # 4099 is prime and above the Bluestein limit
     with pytest.raises(bm.BosmusicError) as ei:
-        bm.bosmusic_demodulate(dem.h, [bm.FrameSpec(odd, 6, 16, bm.BM_DIR_X, torch.empty((64, 77), device="cuda"))])
+        bm.bosmusic_demodulate(wide.h, [bm.FrameSpec(odd, 6, 16, bm.BM_DIR_X, torch.empty((4, 4099), device="cuda"))])
     assert ei.value.status == bm.BM_E_UNSUPPORTED
+    wide.close()
     big = torch.zeros((10, 5000), device="cuda")
     with pytest.raises(bm.BosmusicError) as ei:
         bm.bosmusic_demodulate(dem.h, [bm.FrameSpec(big, 6, 16, bm.BM_DIR_X, torch.empty((10, 5000), device="cuda"))])

@@ -29,6 +29,14 @@ Workload recipes (all seeded):
         N=32, L=8.
   cfg5  training lines of 128 samples, random carrier 1/16..1/4 cyc/px,
         SNR 0..30 dB (surrogate training set).
+  exp   stand-in for the paper's experimental series (Sec. 4): 19 frames of
+        1850x700 8-bit samples taken at 120, 240, ..., 600 s and then every
+        300 s to 4800 s; carrier 0.11 cyc/px at 35 degrees, phi = 5*erf((y-350)/w_t)
+        with w_t = 6*sqrt(t/120 s) (Fick diffusion), SNR 12 dB before
+        quantisation, seed 5000+i; line windows N = 15 (the paper's 2L+1 with
+        L = 7) and covariance size 7.
+
+8-bit frames are round(255 * I) clipped to 0..255.
 """
 from __future__ import annotations
 
@@ -90,6 +98,8 @@ def erf_fringe(W, H, f0, angle_deg, amp, y0, w, snr_db, seed, dtype):
         val = wy0 + amp * 2.0 / math.sqrt(math.pi) * np.exp(-((ys - y0) / w) ** 2) / w
         return np.broadcast_to(val, np.broadcast(ys, xs).shape)
 
+    if np.dtype(dtype) == np.uint8:
+        return np.clip(np.rint(img * 255.0), 0, 255).astype(np.uint8), truth_wx, truth_wy
     return img.astype(dtype), truth_wx, truth_wy
 
 
@@ -145,6 +155,23 @@ def cfg4_frame(t: int, size: int = 4096) -> Frame:
 
 def cfg4(frames=range(16)) -> list:
     return [cfg4_frame(t) for t in frames]
+
+
+EXP_TIMES_S = [120.0 * k for k in range(1, 6)] + [600.0 + 300.0 * k for k in range(1, 15)]
+
+
+def exp_frame(i: int) -> Frame:
+    """Frame i of the 19-frame 1850x700 8-bit stand-in series."""
+    W, H = 1850, 700
+    t = EXP_TIMES_S[i]
+    w_t = 6.0 * math.sqrt(t / 120.0)
+    img, twx, twy = erf_fringe(W, H, 0.11, 35.0, 5.0, H / 2.0, w_t, 12.0, 5000 + i, np.uint8)
+    return Frame(img, L=7, N=15, dirs="xy", truth_wx=twx, truth_wy=twy,
+                 meta={"cfg": "exp", "i": i, "t_s": t, "w": w_t})
+
+
+def exp_series(frames=range(19)) -> list:
+    return [exp_frame(i) for i in frames]
 
 
 def complex_tone(W, H, wx, wy, alpha=0.3, amp=1.0, snr_db=None, seed=0):
