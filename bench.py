@@ -69,6 +69,8 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     iterations of the windows whose roots were all found.  Certificate work
     of a window that fails it is not counted.  `block`: the L x L block
     window, whose covariance is summed directly from its L snapshots.
+    The eigenvalue Newton steps cost 8L flops each (the characteristic
+    polynomial and its derivative), after a 7L + 2 flop start bound.
     """
     K = N - L + 1
     n = 2 * L - 2
@@ -76,10 +78,12 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
         # block window: L snapshots, upper triangle of L x L complex products each
         lag = L * (L * (L + 1) // 2 * 8 - 4 * L)
     else:
-        lag = K * L * 8                               # lag sums, complex MAC = 4 FMA
+        # lag sums (complex MAC = 4 FMA): a lane sums its first start directly (K L MACs)
+        # and slides to its second (2 L MACs), so per window half of that
+        lag = (K * L * 8 + 16 * L) / 2
     build_t = 3 * L * L + L + L * (L + 1) // 2        # T from R, trace normalisation
     house = sum(2 * l * l + 2 * l * (l + 1) + 9 * l for l in range(2, L))
-    newton_f = newton * 8 * L
+    newton_f = newton * 8 * L + 7 * L + 2
     inverse = 6 * L + 2 * 8 * L + sum(4 * l for l in range(2, L))
     coef = 2 * L + 8 * L * (L + 1) // 2
     common32 = lag + build_t + house + newton_f + inverse + coef + 20

@@ -166,9 +166,9 @@ bm_status bosmusic_destroy(bosmusic_t h);
  * lag-1 predictor is configured, and N >= 16 for every frame).
  * Requirements per frame: 2 <= L <= 8, L <= N <= 64, width/height within
  * the handle's maximum, row_stride >= width; for real dtypes the length of
- * every requested direction must either factor into 2, 3 and 5 and be
- * <= 8192, or be <= 4096 (any factors: the exact DFT of the analytic step
- * then goes through Bluestein's chirp-z identity at a 5-smooth length
+ * every requested direction must either factor into 2, 3, 5, 7, 11 and 13
+ * and be <= 8192, or be <= 4096 (any factors: the exact DFT of the analytic
+ * step then goes through Bluestein's chirp-z identity at a 5-smooth length
  * >= 2n - 1, about four times the transform work).  A window longer than the
  * frame is not an error: the whole map is NaN. */
 bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_t n_frames,

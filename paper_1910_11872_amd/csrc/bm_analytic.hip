@@ -1,13 +1,16 @@
 // Complex analytic fringe signal (paper Sec. 2, Eq. 1) by an exact DFT mask,
 // plus the tiled transposes that turn the y direction into lines.
 //
-// analytic_kernel: one block per line.  The line is decoded to FP32, run
-// through a mixed-radix (4, 2, 3, 5) Stockham FFT ping-ponged between two LDS
-// buffers, multiplied by the one-sided mask H (H[0] = 0, H[k] = 2 for
-// 0 < 2k < n, 0 otherwise, so DC and Nyquist are removed and the carrier is
-// kept), and transformed back with the same forward FFT applied to the
-// conjugate.  Twiddles come from a per-length table computed in FP64 on the
-// host and rounded once.  A length with a prime factor above 5 takes each DFT
+// analytic_kernel: one block per line, or per pair of lines.  A line is
+// decoded to FP32, run through a mixed-radix (4, 2, 3, 5, 7, 11, 13) Stockham
+// FFT ping-ponged between LDS buffers, multiplied by the one-sided mask H
+// (H[0] = 0, H[k] = 2 for 0 < 2k < n, 0 otherwise, so DC and Nyquist are
+// removed and the carrier is kept), and transformed back with the same
+// forward FFT applied to the conjugate.  Two real lines x_a, x_b share one
+// forward transform of z = x_a + i x_b: X_a[k] = (Z[k] + conj Z[n-k]) / 2 and
+// X_b[k] = (Z[k] - conj Z[n-k]) / 2i, so a pair costs three transforms
+// instead of four.  Twiddles come from a per-length table computed in FP64 on the
+// host and rounded once.  A length with a prime factor above 13 takes each DFT
 // by Bluestein's identity jk = (j^2 + k^2 - (k-j)^2) / 2: with the chirp
 // w_j = e^{-i pi j^2 / n}, X_k = w_k sum_j (x_j w_j) conj(w_{k-j}), a linear
 // convolution done as a circular one of 5-smooth length m >= 2n - 1 (two
@@ -36,6 +39,16 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
                                               int Ns, const float2* __restrict__ tw) {
     const int nR = n / R;
     const int tws = n / (Ns * R);
+    // odd prime radices: cos and sin of 2 pi r / R from the length's own table
+    float cs[R], sn[R];
+    if constexpr (R >= 7) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float2 w = tw[r * nR];          // e^{-2 pi i r / R}
+            cs[r] = w.x;
+            sn[r] = -w.y;
+        }
+    }
     for (int j = threadIdx.x; j < nR; j += kFftThreads) {
         const int k = j % Ns;
         float2 v[R];
@@ -62,6 +75,36 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
             y[0] = cadd(v[0], s);
             y[1] = cadd(base, rot);
             y[2] = csub(base, rot);
+        } else if (R >= 7) {
+            // odd prime radix: pair the inputs r and R-r (in place: v[r] = sum,
+            // v[R-r] = difference), write each output pair as it is formed,
+            // y[q], y[R-q] = v0 + sum_r s_r cos(2 pi r q / R) -/+ i sum_r d_r sin(2 pi r q / R)
+            constexpr int h = (R - 1) / 2;
+            const int idx = (j / Ns) * Ns * R + k;
+            float2 y0 = v[0];
+#pragma unroll
+            for (int r = 1; r <= h; ++r) {
+                const float2 sr = cadd(v[r], v[R - r]);
+                v[R - r] = csub(v[r], v[R - r]);
+                v[r] = sr;
+                y0 = cadd(y0, sr);
+            }
+            dst[idx] = y0;
+#pragma unroll
+            for (int q = 1; q <= h; ++q) {
+                float2 a = v[0], b = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int r = 1; r <= h; ++r) {
+                    const int e = (r * q) % R;
+                    a.x = fmaf(v[r].x, cs[e], a.x);
+                    a.y = fmaf(v[r].y, cs[e], a.y);
+                    b.x = fmaf(v[R - r].x, sn[e], b.x);
+                    b.y = fmaf(v[R - r].y, sn[e], b.y);
+                }
+                dst[idx + q * Ns] = cadd(a, mul_mi(b));
+                dst[idx + (R - q) * Ns] = cadd(a, mul_pi(b));
+            }
+            continue;
         } else if (R == 5) {
             constexpr float c1 = 0.309016994374947424f, c2 = -0.809016994374947424f;
             constexpr float s1 = 0.951056516295153572f, s2 = 0.587785252292473129f;
@@ -83,16 +126,28 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
     }
 }
 
+template <int R>
+__device__ __forceinline__ void stockham_pass_odd(const float2* __restrict__ src, float2* __restrict__ dst, int n, int Ns,
+                                               const float2* __restrict__ tw) {
+    stockham_pass<R>(src, dst, n, Ns, tw);
+}
+
 // Forward DFT of the line held in `a` (scratch `b`); returns the buffer that
-// holds the result in natural order.
-__device__ float2* fft_forward(float2* a, float2* b, int n, const FftPlan& plan, const float2* tw) {
+// holds the result in natural order.  MAXR bounds the radices compiled in: the
+// radix-7/11/13 butterflies need several times the registers of the others,
+// so plans without them run in a kernel that does not carry them.
+template <int MAXR>
+__device__ __forceinline__ float2* fft_forward(float2* a, float2* b, int n, const FftPlan& plan, const float2* tw) {
     int Ns = 1;
     for (int ps = 0; ps < plan.passes; ++ps) {
         const int R = plan.radix[ps];
         if (R == 4) stockham_pass<4>(a, b, n, Ns, tw);
         else if (R == 2) stockham_pass<2>(a, b, n, Ns, tw);
         else if (R == 3) stockham_pass<3>(a, b, n, Ns, tw);
-        else stockham_pass<5>(a, b, n, Ns, tw);
+        else if (MAXR <= 5 || R == 5) stockham_pass<5>(a, b, n, Ns, tw);
+        else if (R == 7) stockham_pass_odd<7>(a, b, n, Ns, tw);
+        else if (R == 11) stockham_pass_odd<11>(a, b, n, Ns, tw);
+        else stockham_pass_odd<13>(a, b, n, Ns, tw);
         __syncthreads();
         float2* t = a;
         a = b;
@@ -105,13 +160,14 @@ __device__ float2* fft_forward(float2* a, float2* b, int n, const FftPlan& plan,
 // DFT of the n samples at a[0..n): a direct mixed-radix FFT, or Bluestein's
 // chirp-z route through length plan.n = m.  a and b hold m elements each;
 // returns the buffer holding X[0..n) in natural order.
-__device__ float2* dft_line(float2* a, float2* b, const FftJob& J) {
+template <int MAXR>
+__device__ __forceinline__ float2* dft_line(float2* a, float2* b, const FftJob& J) {
     const int n = J.n, m = J.plan.n;
-    if (!J.chirp) return fft_forward(a, b, n, J.plan, J.tw);
+    if (!J.chirp) return fft_forward<MAXR>(a, b, n, J.plan, J.tw);
     for (int i = threadIdx.x; i < m; i += kFftThreads)
         a[i] = i < n ? cmul(a[i], J.chirp[i]) : make_float2(0.f, 0.f);
     __syncthreads();
-    float2* P = fft_forward(a, b, m, J.plan, J.tw);
+    float2* P = fft_forward<MAXR>(a, b, m, J.plan, J.tw);
     float2* Q = (P == a) ? b : a;
     // circular convolution with conj(w): inverse DFT as the conjugate of a forward one
     for (int k = threadIdx.x; k < m; k += kFftThreads) {
@@ -119,7 +175,7 @@ __device__ float2* dft_line(float2* a, float2* b, const FftJob& J) {
         P[k] = make_float2(v.x, -v.y);
     }
     __syncthreads();
-    float2* Y = fft_forward(P, Q, m, J.plan, J.tw);
+    float2* Y = fft_forward<MAXR>(P, Q, m, J.plan, J.tw);
     for (int k = threadIdx.x; k < n; k += kFftThreads) {
         const float2 v = Y[k];
         Y[k] = cmul(make_float2(v.x, -v.y), J.chirp[k]);
@@ -146,35 +202,65 @@ __device__ __forceinline__ float load_real(const void* base, int64_t idx, int el
     return static_cast<const float*>(base)[idx];
 }
 
-// One block per line of any job.
-__global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B) {
+__device__ __forceinline__ float2 conjf2(float2 v) { return make_float2(v.x, -v.y); }
+
+// One block per work item of any job: a pair of lines (lines 2i, 2i+1) when
+// the transform is short enough for three LDS buffers, else one line.
+template <int MAXR>
+__global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int item0) {
     extern __shared__ float2 lds[];
-    const int j = find_job(B.prefix, B.njobs, blockIdx.x);
+    const int w = item0 + blockIdx.x;
+    const int j = find_job(B.prefix, B.njobs, w);
     const FftJob& J = B.jobs[j];
-    const int line = blockIdx.x - B.prefix[j];
-    const int n = J.n;
+    const int item = w - B.prefix[j];
+    const int n = J.n, m = J.plan.n;
     const int elem = J.elem;
+    const bool pairs = fft_pairs(m);
+    const int la = pairs ? 2 * item : item;
+    const bool two = pairs && la + 1 < J.nlines;
     float2* a = lds;
-    float2* b = lds + J.plan.n;
-    const int64_t off = (int64_t)line * J.src_ls;
-    for (int i = threadIdx.x; i < n; i += kFftThreads) a[i] = make_float2(load_real(J.src, off + i, elem), 0.f);
+    float2* b = lds + m;
+    float2* c = lds + 2 * m;            // pairs only
+    const int64_t off = (int64_t)la * J.src_ls;
+    for (int i = threadIdx.x; i < n; i += kFftThreads)
+        a[i] = make_float2(load_real(J.src, off + i, elem), two ? load_real(J.src, off + J.src_ls + i, elem) : 0.f);
     __syncthreads();
-    float2* X = dft_line(a, b, J);
+    float2* X = dft_line<MAXR>(a, b, J);
     float2* other = (X == a) ? b : a;
     // one-sided mask and 1/n, then conjugate so that a forward DFT inverts
     const float sc = 2.0f / (float)n;
+    if (!two) {
+        for (int k = threadIdx.x; k < n; k += kFftThreads) {
+            const float2 v = X[k];
+            const bool keep = (k >= 1) && (2 * k < n);
+            X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2* Y = dft_line<MAXR>(X, other, J);
+        float2* out = J.dst + (int64_t)la * n;
+        for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Y[i]);
+        return;
+    }
+    // split the spectra of the two real lines, masked and conjugated, into `other` (a) and `c` (b)
+    const float hs = 0.5f * sc;
     for (int k = threadIdx.x; k < n; k += kFftThreads) {
-        const float2 v = X[k];
-        const bool keep = (k >= 1) && (2 * k < n);
-        X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
+        float2 ma = make_float2(0.f, 0.f), mb = make_float2(0.f, 0.f);
+        if ((k >= 1) && (2 * k < n)) {
+            const float2 z = X[k], zn = X[n - k];
+            ma = make_float2(hs * (z.x + zn.x), -hs * (z.y - zn.y));      // conj(sc X_a[k])
+            mb = make_float2(hs * (z.y + zn.y), hs * (z.x - zn.x));       // conj(sc X_b[k])
+        }
+        other[k] = ma;
+        c[k] = mb;
     }
     __syncthreads();
-    float2* Y = dft_line(X, other, J);
-    float2* out = J.dst + (int64_t)line * n;
-    for (int i = threadIdx.x; i < n; i += kFftThreads) {
-        const float2 v = Y[i];
-        out[i] = make_float2(v.x, -v.y);
-    }
+    float2* Ya = dft_line<MAXR>(other, X, J);
+    float2* spare = (Ya == other) ? X : other;
+    float2* out = J.dst + (int64_t)la * n;
+    for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Ya[i]);
+    float2* Yb = dft_line<MAXR>(c, spare, J);
+    out += n;
+    for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Yb[i]);
 }
 
 // One block per 32 x 32 tile of any job; real input -> float, C32 -> float2.
@@ -211,14 +297,22 @@ __global__ __launch_bounds__(kTile * 8) void transpose_kernel(TrBatch B) {
 }  // namespace
 
 hipError_t analytic_set_attributes() {
-    return hipFuncSetAttribute((const void*)analytic_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               2 * kMaxFFT * (int)sizeof(float2));
+    const int elems = 2 * kMaxFFT > 3 * kFftPairMax ? 2 * kMaxFFT : 3 * kFftPairMax;
+    hipError_t e = hipFuncSetAttribute((const void*)analytic_kernel<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       elems * (int)sizeof(float2));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)analytic_kernel<13>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               elems * (int)sizeof(float2));
 }
 
 hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
     if (b.total <= 0) return hipSuccess;
-    const size_t shmem = 2u * (size_t)b.max_n * sizeof(float2);
-    hipLaunchKernelGGL(analytic_kernel, dim3(b.total), dim3(kFftThreads), shmem, s, b);
+    if (b.big_from > 0)
+        hipLaunchKernelGGL(analytic_kernel<5>, dim3(b.big_from), dim3(kFftThreads),
+                           (size_t)b.lds_small * sizeof(float2), s, b, 0);
+    if (b.big_from < b.total)
+        hipLaunchKernelGGL(analytic_kernel<13>, dim3(b.total - b.big_from), dim3(kFftThreads),
+                           (size_t)b.lds_big * sizeof(float2), s, b, b.big_from);
     return hipGetLastError();
 }
 

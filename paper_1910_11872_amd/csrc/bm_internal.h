@@ -17,7 +17,7 @@ constexpr int kStatSlots = 64;   // counter slots of the statistics buffer
 constexpr int kStatFields = 8;   // counters per slot (6 used)
 constexpr int kGatherBlock = 256;
 
-// Mixed-radix plan of one DFT length (radices 4, 2, 3, 5 in pass order).
+// Mixed-radix plan of one DFT length (radices 4, 2, 3, 5, 7, 11, 13 in pass order).
 struct FftPlan {
     int n;                       // transform length
     int passes;                  // number of radix passes
@@ -80,7 +80,7 @@ struct RmBatch {
 };
 
 // Lines of one frame direction for the analytic-signal kernel (one block per line).
-// A length n with a prime factor above 5 takes the DFT by Bluestein's chirp-z
+// A length n with a prime factor above 13 takes the DFT by Bluestein's chirp-z
 // identity through a circular convolution of 5-smooth length m = plan.n >= 2n-1.
 struct FftJob {
     const void* src;       // real lines, src_ls elements apart
@@ -95,12 +95,35 @@ struct FftJob {
     FftPlan plan;          // plan of n, or of m under Bluestein (chirp != nullptr)
 };
 
+// Transform lengths up to this take two real lines per block (one complex
+// forward DFT of x_a + i x_b, split by symmetry): three buffers in LDS.
+constexpr int kFftPairMax = 6144;
+
+__host__ __device__ inline bool fft_pairs(int m) { return m <= kFftPairMax; }
+
+// Work items (blocks) of one job: line pairs or lines.
+inline int fft_items(const FftJob& j) { return fft_pairs(j.plan.n) ? (j.nlines + 1) / 2 : j.nlines; }
+
+// LDS of one job's block, in complex elements.
+inline int fft_lds_elems(const FftJob& j) { return (fft_pairs(j.plan.n) ? 3 : 2) * j.plan.n; }
+
+// True when the job's plan has a radix above 5 (it runs in the kernel that carries them).
+inline bool fft_big_radix(const FftJob& j) {
+    for (int p = 0; p < j.plan.passes; ++p)
+        if (j.plan.radix[p] > 5) return true;
+    return false;
+}
+
+// Jobs without radices above 5 come first: items [0, big_from) run in the
+// kernel built for radices 2-5, the rest in the one built for all radices.
 struct FftBatch {
     const FftJob* jobs;
-    const int* prefix;     // lines: njobs + 1 entries
+    const int* prefix;     // work items (fft_items): njobs + 1 entries
     int njobs;
     int total;
-    int max_n;
+    int big_from;          // first item of a job with a radix above 5 (total if none)
+    int lds_small;         // max fft_lds_elems over the jobs before / from big_from
+    int lds_big;
 };
 
 // Transpose of one frame (rows x cols, src_ls elements per row) to cols x rows.
@@ -124,7 +147,10 @@ struct TrBatch {
 // threads; `grid` is the number of blocks of the grid-stride loop (<= 0: one
 // block per work item).
 hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStream_t s);
-int rootmusic_windows_per_block(int L, int block);
+// Output pixels per work item of a line: the line-window root-MUSIC kernel
+// (line_kernel) covers two starts per lane, the block-window and surrogate
+// kernels one.
+int rootmusic_windows_per_block(int L, int block, bool line_kernel);
 // Plain root-MUSIC on the *count windows of `list` ({job, line << 16 | pixel}),
 // grid-stride over `grid` blocks of kGatherBlock lanes.
 hipError_t launch_rootmusic_gather(int L, const RmBatch& b, const int2* list, const int* count, int grid,

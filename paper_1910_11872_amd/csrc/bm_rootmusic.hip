@@ -44,11 +44,29 @@
 namespace bm {
 namespace {
 
-// One block of windows: BLOCK-(L-1) consecutive pixels p0.. of one line of job J.
+// Line windows per lane: the lag sums of a lane's second start are slid from
+// its first, so each start costs about half the direct sum.  Blocks start at
+// even pixels, so which window starts are summed directly and which are slid
+// depends on the start alone, not on the tile size: results are the same for
+// every tiling.
+constexpr int kLineSpan = 2;
+
+constexpr int line_windows_per_block(int L, int block) { return (kLineSpan * block - (L - 1)) & ~1; }
+
+template <int L, int BLOCK>
+struct LineSpan {
+    static constexpr int span = kLineSpan * BLOCK;                  // window starts per block
+    static constexpr int wpb = line_windows_per_block(L, BLOCK);    // output pixels per block (even)
+    static constexpr int row = span + 8;                            // lag-sum row: >= span, 16-byte multiple
+};
+
+// One block of windows: SPAN-(L-1) consecutive pixels p0.. of one line of job J.
 template <int L, int BLOCK, bool JACOBI>
-__device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg, float2 (*sS)[BLOCK + L],
-                                                const RootTemplate& tmpl, bool full_roots, LaneStats& ls) {
-    constexpr int WPB = BLOCK - (L - 1);
+__device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg,
+                                                float2 (*sS)[LineSpan<L, BLOCK>::row], const RootTemplate& tmpl,
+                                                bool full_roots, LaneStats& ls) {
+    constexpr int SPAN = LineSpan<L, BLOCK>::span;
+    constexpr int WPB = LineSpan<L, BLOCK>::wpb;
     const int t = threadIdx.x;
     const int N = J.N;
     const int half = N >> 1;
@@ -56,38 +74,42 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
     const float2* g = J.gamma + (int64_t)line * J.gamma_ls;
     const int len = J.len;
 
-    // window of pixel p0+t starts at base+t
+    // window of pixel p0+s starts at base+s
     const int base = p0 - half;
-    for (int i = t; i < BLOCK + N - 1; i += BLOCK) {
+    for (int i = t; i < SPAN + N - 1; i += BLOCK) {
         const int q = base + i;
         sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    // ---- lag sums S_d(base+t), d < L (every lane) -------------------------
-    lag_sums<L, BLOCK + L>(sg, t, K, sS);
+    // ---- lag sums S_d(base+2t), S_d(base+2t+1), d < L ---------------------
+    lag_sums_pair<L, LineSpan<L, BLOCK>::row>(sg, kLineSpan * t, K, sS);
     __syncthreads();
 
-    const int p = p0 + t;
-    const bool inside_line = (t < WPB) && (p < len);
-    const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
-    float omega = __builtin_nanf("");
-    unsigned flag = 0;
-    if (valid) {
-        // covariance R_ij = S_{j-i}(s+i) (Eq. 4, up to the 1/K scale)
-        Cov<L> R;
+#pragma unroll 1
+    for (int r = 0; r < kLineSpan; ++r) {
+        const int s = r * BLOCK + t;
+        const int p = p0 + s;
+        const bool inside_line = (s < WPB) && (p < len);
+        const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
+        float omega = __builtin_nanf("");
+        unsigned flag = 0;
+        if (valid) {
+            // covariance R_ij = S_{j-i}(s+i) (Eq. 4, up to the 1/K scale)
+            Cov<L> R;
 #pragma unroll
-        for (int i = 0; i < L; ++i)
+            for (int i = 0; i < L; ++i)
 #pragma unroll
-            for (int j = i; j < L; ++j) {
-                const float2 v = sS[j - i][t + i];
-                R.re[i][j] = v.x;
-                R.im[i][j] = (i == j) ? 0.f : v.y;
-            }
-        window_omega<L, JACOBI>(R, tmpl, full_roots, K, omega, flag, ls);
-    } else {
-        flag |= BM_FLAG_UNDEFINED;
+                for (int j = i; j < L; ++j) {
+                    const float2 v = sS[j - i][s + i];
+                    R.re[i][j] = v.x;
+                    R.im[i][j] = (i == j) ? 0.f : v.y;
+                }
+            window_omega<L, JACOBI>(R, tmpl, full_roots, K, omega, flag, ls);
+        } else {
+            flag |= BM_FLAG_UNDEFINED;
+        }
+        if (inside_line) store_omega(J, line, p, omega, flag);
     }
-    if (inside_line) store_omega(J, line, p, omega, flag);
 }
 
 
@@ -224,9 +246,11 @@ __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long l
 // once; a smaller (persistent) grid walks the list.
 template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN>
 __global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
-    constexpr int WPB = BLOCK - (L - 1);
-    __shared__ float2 sg[BLOCK + kMaxN];
-    __shared__ float2 sS[L][BLOCK + L];   // lag sums (line windows) or staged rows (block windows)
+    // line windows: staged signal + lag sums; block windows: the block's staged rows
+    constexpr int ROW = BLOCKWIN ? BLOCK + L : LineSpan<L, BLOCK>::row;
+    constexpr int WPB = BLOCKWIN ? BLOCK - (L - 1) : LineSpan<L, BLOCK>::wpb;
+    __shared__ float2 sg[BLOCKWIN ? 1 : LineSpan<L, BLOCK>::span + kMaxN];
+    __shared__ __align__(16) float2 sS[L][ROW];
     LaneStats ls;
     for (int w = blockIdx.x; w < B.total; w += gridDim.x) {
         const int j = find_job(B.prefix, B.njobs, w);
@@ -236,7 +260,7 @@ __global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
         const int bx = local - line * J.bpl;
         // line and block windows are separate instantiations, so that neither
         // pays the other's registers
-        if (BLOCKWIN)
+        if constexpr (BLOCKWIN)
             rootmusic_block2d<L, BLOCK, JACOBI>(J, line, bx * WPB, sS, B.tmpl, B.full_roots != 0, ls);
         else
             rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, B.full_roots != 0, ls);
@@ -336,7 +360,9 @@ hipError_t launch_gather_L(const RmBatch& b, const int2* list, const int* count,
 
 }  // namespace
 
-int rootmusic_windows_per_block(int L, int block) { return block - (L - 1); }
+int rootmusic_windows_per_block(int L, int block, bool line_kernel) {
+    return line_kernel ? line_windows_per_block(L, block) : block - (L - 1);
+}
 
 hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStream_t s) {
     if (b.total <= 0 || b.njobs <= 0) return hipSuccess;

@@ -137,7 +137,7 @@ bool plan_fft(int n, bm::FftPlan& p) {
     p.n = n;
     p.passes = 0;
     int r = n;
-    const int order[4] = {4, 2, 3, 5};
+    const int order[7] = {4, 2, 3, 5, 7, 11, 13};
     for (int f : order) {
         while (r % f == 0) {
             if (p.passes >= bm::kMaxRadixPasses) return false;
@@ -148,27 +148,34 @@ bool plan_fft(int n, bm::FftPlan& p) {
     return r == 1;
 }
 
-bool factors_235(int n) {
+// The mixed-radix FFT takes n directly (factors 2, 3, 5, 7, 11, 13 only).
+bool fft_direct(int n) {
     bm::FftPlan p;
     return plan_fft(n, p);
 }
 
 // Transform length of Bluestein's route for a line of n samples: the least
-// 5-smooth m >= 2n - 1, or 0 when that exceeds the largest FFT.
+// 5-smooth m >= 2n - 1 (radix 2-5 passes only), or 0 when that exceeds the
+// largest FFT.
 int bluestein_len(int n) {
-    for (int m = std::max(2 * n - 1, 1); m <= bm::kMaxFFT; ++m)
-        if (factors_235(m)) return m;
+    for (int m = std::max(2 * n - 1, 1); m <= bm::kMaxFFT; ++m) {
+        int r = m;
+        for (int f : {2, 3, 5})
+            while (r % f == 0) r /= f;
+        if (r == 1) return m;
+    }
     return 0;
 }
 
 // A line of n samples has an exact DFT here: directly or by Bluestein.
-bool dft_supported(int n) { return n >= 1 && (factors_235(n) || bluestein_len(n) > 0); }
+bool dft_supported(int n) { return n >= 1 && (fft_direct(n) || bluestein_len(n) > 0); }
 
-// In-place FP64 DFT of a 5-smooth length (recursive decimation in time).
+// In-place FP64 DFT (recursive decimation in time by the smallest prime factor).
 void dft64(std::vector<std::complex<double>>& x) {
     const int n = (int)x.size();
     if (n == 1) return;
-    const int p = n % 2 == 0 ? 2 : (n % 3 == 0 ? 3 : 5);
+    int p = 2;
+    while (n % p) ++p;
     const int q = n / p;
     std::vector<std::vector<std::complex<double>>> sub(p, std::vector<std::complex<double>>(q));
     for (int r = 0; r < p; ++r)
@@ -292,7 +299,7 @@ bm_status get_bluestein(bosmusic_s* h, int n, int m, const float2** chirp, const
     return BM_OK;
 }
 
-// Plan, twiddles and (when n is not 5-smooth) Bluestein tables of a line length.
+// Plan, twiddles and (when n is not 13-smooth) Bluestein tables of a line length.
 bm_status make_fft_job(bosmusic_s* h, int n, bm::FftJob& fj) {
     fj.n = n;
     fj.chirp = fj.kern = nullptr;
@@ -324,10 +331,10 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
     if (f.dtype != BM_C32) {
         // block windows use the row-wise analytic signal for both directions
         if (((f.dirs & BM_DIR_X) || (f.dirs & BM_BLOCK)) && !dft_supported(f.width))
-            return fail(h, BM_E_UNSUPPORTED, "frame %d: width %d is neither 2^a 3^b 5^c <= %d nor <= %d", idx,
+            return fail(h, BM_E_UNSUPPORTED, "frame %d: width %d is neither 13-smooth and <= %d nor <= %d", idx,
                         f.width, bm::kMaxFFT, bm::kMaxFFT / 2);
         if ((f.dirs & BM_DIR_Y) && !(f.dirs & BM_BLOCK) && !dft_supported(f.height))
-            return fail(h, BM_E_UNSUPPORTED, "frame %d: height %d is neither 2^a 3^b 5^c <= %d nor <= %d", idx,
+            return fail(h, BM_E_UNSUPPORTED, "frame %d: height %d is neither 13-smooth and <= %d nor <= %d", idx,
                         f.height, bm::kMaxFFT, bm::kMaxFFT / 2);
     }
     return BM_OK;
@@ -365,7 +372,7 @@ struct GroupPlan {
     std::vector<int> tr_prefix;
     std::vector<bm::FftJob> fft;
     std::vector<int> fft_prefix;
-    int max_n = 0;
+    int fft_big_from = 0, lds_small = 0, lds_big = 0;
     std::vector<RmSet> rm;          // one (or two, with flags) per distinct L
     std::vector<bm::TrJob> back;    // omega_y from its line-major scratch to the caller's row-major map
     std::vector<int> back_prefix;
@@ -418,7 +425,6 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 fj.elem = f.dtype;
                 fj.nlines = H;
                 gp.fft.push_back(fj);
-                gp.max_n = std::max(gp.max_n, fj.plan.n);
                 gam = gx;
                 gls = W;
             }
@@ -457,7 +463,6 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 fj.elem = f.dtype;
                 fj.nlines = H;
                 gp.fft.push_back(fj);
-                gp.max_n = std::max(gp.max_n, fj.plan.n);
                 j.gamma = gx;
                 j.gamma_ls = W;
             }
@@ -498,7 +503,6 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
                 fj.elem = BM_F32;
                 fj.nlines = W;
                 gp.fft.push_back(fj);
-                gp.max_n = std::max(gp.max_n, fj.plan.n);
             }
             gp.tr.push_back(tj);
             // omega_y is written line-major (coalesced) into a scratch map, then
@@ -536,8 +540,19 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     if (cur > h->ws_bytes) return fail(h, BM_E_INVALID_ARG, "group exceeds the workspace");
     gp.tr_prefix.assign(1, 0);
     for (auto& t : gp.tr) gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
+    // jobs with radices above 5 last: they run in their own kernel
+    std::stable_partition(gp.fft.begin(), gp.fft.end(), [](const bm::FftJob& f) { return !bm::fft_big_radix(f); });
     gp.fft_prefix.assign(1, 0);
-    for (auto& f : gp.fft) gp.fft_prefix.push_back(gp.fft_prefix.back() + f.nlines);
+    gp.fft_big_from = -1;
+    gp.lds_small = gp.lds_big = 0;
+    for (auto& f : gp.fft) {
+        const bool big = bm::fft_big_radix(f);
+        if (big && gp.fft_big_from < 0) gp.fft_big_from = gp.fft_prefix.back();
+        int& l = big ? gp.lds_big : gp.lds_small;
+        l = std::max(l, bm::fft_lds_elems(f));
+        gp.fft_prefix.push_back(gp.fft_prefix.back() + bm::fft_items(f));
+    }
+    if (gp.fft_big_from < 0) gp.fft_big_from = gp.fft_prefix.back();
     gp.back_prefix.assign(1, 0);
     for (auto& t : gp.back) gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
     for (auto& kv : sets) {
@@ -547,7 +562,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         s.tune = h->tune[s.L][nmax];
         // the surrogate and block-window kernels run 256 lanes, one block per item
         if (mode == BM_SURROGATE || s.block_win) s.tune = Tune{};
-        const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block);
+        const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block, mode != BM_SURROGATE && !s.block_win);
         s.prefix.assign(1, 0);
         for (auto& j : s.jobs) {
             j.bpl = (j.len + wpb - 1) / wpb;
@@ -580,7 +595,9 @@ void bind_group(bosmusic_s* h, GroupPlan& gp, const char* dev) {
     gp.fftb.prefix = (const int*)(dev + gp.fftp_off);
     gp.fftb.njobs = (int)gp.fft.size();
     gp.fftb.total = gp.fft_prefix.back();
-    gp.fftb.max_n = gp.max_n;
+    gp.fftb.big_from = gp.fft_big_from;
+    gp.fftb.lds_small = gp.lds_small;
+    gp.fftb.lds_big = gp.lds_big;
     gp.backb.jobs = (const bm::TrJob*)(dev + gp.back_off);
     gp.backb.prefix = (const int*)(dev + gp.backp_off);
     gp.backb.njobs = (int)gp.back.size();
@@ -991,7 +1008,7 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             fj.dst = gamma;
             fj.elem = BM_F32;
             fj.nlines = n;
-            const int fprefix[2] = {0, n};
+            const int fprefix[2] = {0, bm::fft_items(fj)};
             std::vector<bm::RmJob> rj;
             std::vector<int> rp(1, 0);
             for (int j = 0; j * kPerJob < n; ++j) {
@@ -1021,8 +1038,9 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             fb.jobs = (const bm::FftJob*)(h->ds + o_fj);
             fb.prefix = (const int*)(h->ds + o_fp);
             fb.njobs = 1;
-            fb.total = n;
-            fb.max_n = kLen;
+            fb.total = fprefix[1];
+            fb.big_from = bm::fft_big_radix(fj) ? 0 : fb.total;
+            fb.lds_small = fb.lds_big = bm::fft_lds_elems(fj);
             bm::RmBatch rb{};
             rb.jobs = (const bm::RmJob*)(h->ds + o_rj);
             rb.prefix = (const int*)(h->ds + o_rp);
@@ -1511,7 +1529,7 @@ bm_status bosmusic_autotune(bosmusic_t h, int32_t L, int32_t N, int32_t width, i
             j.len = width;
             j.nlines = lines;
             j.N = N;
-            const int wpb = bm::rootmusic_windows_per_block(L, blocks[bi]);
+            const int wpb = bm::rootmusic_windows_per_block(L, blocks[bi], true);
             j.bpl = (width + wpb - 1) / wpb;
             int prefix[2] = {0, j.bpl * lines};
             // the previous candidate's launches read the table: wait before rewriting it

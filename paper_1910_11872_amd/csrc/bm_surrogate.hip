@@ -194,10 +194,9 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
     // lag-1 coefficient c_1 ~ -((L-1)/L) e^{-j w}.  Newton for the signal
     // root (its mate divided out) starts there.
     const float w1 = atan2f(ai[L], -ar[L]);
-    double zr, zi, last = 0.0, rr = 0.0, ri = 0.0;
+    double zr, zi, rr = 0.0, ri = 0.0;
     pair_start(w1, lam, K, zr, zi);
-    if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, kPairStepTol, last, nullptr)) return false;
-    if (!(last <= kPairAcceptTol * (fabs(zr) + fabs(zi)))) return false;
+    if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, nullptr)) return false;
     if (!certified_root<L>(ar, ai, zr, zi, rr, ri)) return false;
     const float w = atan2f((float)ri, (float)rr);
     omega = w;

@@ -37,12 +37,19 @@ constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
 constexpr float kRootTol2 = BM_ROOT_TOL2;
 constexpr int kPolishIters = BM_POLISH_ITERS;
 constexpr int kCertIters = 8;     // at most this many FP64 Newton steps before the pair certificate
-// Newton with the mate divided out converges quadratically: after a step of
-// relative size d the error is of order d^2, so iterating stops once a step
-// is below 1e-7 |z| (error ~1e-14), and a root whose last step is above
-// 1e-6 |z| is not trusted.
-constexpr double kPairStepTol = 1e-7;
-constexpr double kPairAcceptTol = 1e-6;
+// Newton with the mate divided out converges quadratically once the error is
+// small against the distance |z - 1/conj z| to the mate: iterating stops at
+// the first step below 1e-4 |z| and below 1e-2 |z - 1/conj z| (the error
+// after it is then of order 1e-8 |z| or less, under the FP32 resolution of
+// omega; without the second bound, windows whose pair lies within 1e-4 of
+// the circle stopped with errors up to 2e-5 in numpy trials), and a root that
+// has not met both within the step limit is not trusted.  With such a root
+// the division by the pair's factor leaves a remainder of order 1e-7 of the
+// coefficients' size (1e-6 at most in the same trials over L, N and SNR), so
+// the remainder test allows 1e-5; a lone root on the circle leaves O(1).
+constexpr double kPairStepTol = 1e-4;
+constexpr double kPairMateTol = 1e-2;
+constexpr double kCertRemTol = 1e-5;
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
 constexpr int kInverseIters = BM_INVERSE_ITERS;
 
@@ -151,16 +158,31 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
     float e2[L];
 #pragma unroll
     for (int i = 0; i < L - 1; ++i) e2[i] = e[i] * e[i];
-    // start above the largest eigenvalue: T is positive semidefinite with trace 1
-    float g = 0.f;
+    // start above the largest eigenvalue: T is positive semidefinite with
+    // trace 1, so lambda_1 <= 1; Gerschgorin's bound; and the trace bound of
+    // Wolkowicz and Styan (1980), lambda_1 <= mu + s sqrt(L - 1) with mu the
+    // mean eigenvalue and s^2 their variance, here sum (d_i - mu)^2 / L +
+    // 2 sum e_i^2 / L from the tridiagonal form (sums of squares, so no
+    // cancellation; the similarity keeps tr T^2).  The last is near lambda_1
+    // whenever the other eigenvalues are alike, the usual signal-plus-noise
+    // spectrum, and saves most Newton steps.
+    float g = 0.f, mu = 0.f;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         float r = d[i];
         if (i > 0) r += fabsf(e[i - 1]);
         if (i < L - 1) r += fabsf(e[i]);
         g = fmaxf(g, r);
+        mu += d[i];
     }
-    float x = fminf(g, 1.f) * 1.000001f + 1e-30f;
+    mu *= 1.f / (float)L;
+    float var = 0.f;
+#pragma unroll
+    for (int i = 0; i < L; ++i) var = fmaf(d[i] - mu, d[i] - mu, var);
+#pragma unroll
+    for (int i = 0; i < L - 1; ++i) var = fmaf(2.f * e[i], e[i], var);
+    const float ws = mu + fsqrt(var * ((float)(L - 1) / (float)L));
+    float x = fminf(fminf(g, 1.f), ws) * 1.00001f + 1e-30f;
     for (int it = 0; it < kNewtonIters; ++it) {
         ++its;
         float q0 = 1.f, q1 = x - d[0], dq0 = 0.f, dq1 = 1.f;
@@ -174,7 +196,8 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
         const float step = q1 * frcp(dq1);
         if (!finitef(step)) break;
         x -= step;
-        if (!(fabsf(step) > 1e-7f * x)) break;
+        // quadratic convergence: a step below 1e-5 x leaves an error of order 1e-10 x
+        if (!(fabsf(step) > 1e-5f * x)) break;
     }
     lam = x;
     // (sigma I - T_tri) y = y_prev, LDL^T without pivoting; sigma just above lambda_1
@@ -460,11 +483,11 @@ __device__ __forceinline__ double rcp64(double x) {
 // out (Maehly's correction), which keeps the convergence quadratic although
 // the two roots nearly coincide near the unit circle:
 //   z <- z - P(z) / (P'(z) - P(z) / (z - 1/conj(z)))
-// At most `iters` steps, fewer once a step is below tol |z|; false when a
-// step is not finite.  `lastc` receives |dz| of the last step.
+// At most `iters` steps; true once a step meets the stop rule above, false
+// when none did or a step is not finite.
 template <int n>
 __device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const float (&ai)[n + 1], double& zr, double& zi,
-                                            int iters, double tol, double& lastc, int* its) {
+                                            int iters, int* its) {
     for (int it = 0; it < iters; ++it) {
         if (its) ++*its;
         double Pr = ar[n], Pi = ai[n], Dr = 0.0, Di = 0.0;
@@ -485,10 +508,10 @@ __device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const floa
         if (!(__builtin_isfinite(sr) && __builtin_isfinite(si))) return false;
         zr -= sr;
         zi -= si;
-        lastc = fabs(sr) + fabs(si);
-        if (lastc <= tol * (fabs(zr) + fabs(zi))) break;
+        const double st = fabs(sr) + fabs(si);
+        if (st <= kPairStepTol * (fabs(zr) + fabs(zi)) && st <= kPairMateTol * (fabs(ur) + fabs(ui))) return true;
     }
-    return true;
+    return false;
 }
 
 // True when the root z0 (with its mate 1/conj(z0)) is the root pair nearest
@@ -496,7 +519,7 @@ __device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const floa
 // roots.  Every root pair (z, 1/conj z) has its inner member at radius < 1,
 // and the nearest pair is the one with the largest inner radius, so with
 // z_in the inner member of z0's pair: (z - z_in)(z - 1/conj z_in) must divide
-// P (remainder below 1e-8 of the coefficients' size; a root on the circle,
+// P (remainder below kCertRemTol of the coefficients' size; a root on the circle,
 // its own mirror, fails here), and the quotient Q must have all its L - 2
 // inner roots strictly inside |z| < |z_in| (1 - margin), counted by
 // Schur-Cohn on Q(rho z).  On success (rr, ri) = z_in + 1/conj(z_in).
@@ -535,7 +558,7 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
         b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
     }
     // remainder b1 (z - r) + b0: here b2 = b_1 and b1 = b_0
-    if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= 1e-8 * scale)) return false;
+    if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= kCertRemTol * scale)) return false;
     if (L == 2) return true;                          // no other roots
     const double rho = rin * (1.0 - kCertMargin);
     double rp = 1.0;
@@ -559,13 +582,12 @@ __device__ __forceinline__ void pair_start(float w, float lam, int K, double& zr
     zi = (double)(r0 * sw);
 }
 
-// Lag sums of lane t: S_d = sum_{k<K} g[t+k] conj(g[t+k+d]), d < L, from the
-// staged signal g, stored to sS[d][t].  The last L samples live in a circular
+// Lag sums at start t: S_d = sum_{k<K} g[t+k] conj(g[t+k+d]), d < L, from the
+// staged signal g, into registers.  The last L samples live in a circular
 // register buffer indexed by k mod L, unrolled L steps at a time so that no
 // register moves are needed.
-template <int L, int STRIDE>
-__device__ __forceinline__ void lag_sums(const float2* g, int t, int K, float2 (*sS)[STRIDE]) {
-    float sr[L], si[L];
+template <int L>
+__device__ __forceinline__ void lag_sum_regs(const float2* g, int t, int K, float (&sr)[L], float (&si)[L]) {
 #pragma unroll
     for (int d = 0; d < L; ++d) { sr[d] = 0.f; si[d] = 0.f; }
     float2 win[L];                      // win[m mod L] = g[t + m]
@@ -596,8 +618,32 @@ __device__ __forceinline__ void lag_sums(const float2* g, int t, int K, float2 (
             }
         }
     }
+}
+
+// Lag sums of lane t stored to sS[d][t].
+template <int L, int STRIDE>
+__device__ __forceinline__ void lag_sums(const float2* g, int t, int K, float2 (*sS)[STRIDE]) {
+    float sr[L], si[L];
+    lag_sum_regs<L>(g, t, K, sr, si);
 #pragma unroll
     for (int d = 0; d < L; ++d) sS[d][t] = make_float2(sr[d], si[d]);
+}
+
+// Lag sums at the two starts q and q+1 (q even), the second slid from the
+// first: S_d(q+1) = S_d(q) - g[q] conj(g[q+d]) + g[q+K] conj(g[q+K+d]).
+// Stored as one 16-byte pair per lag to sS[d][q .. q+1] (16-byte aligned rows).
+template <int L, int STRIDE>
+__device__ __forceinline__ void lag_sums_pair(const float2* g, int q, int K, float2 (*sS)[STRIDE]) {
+    float sr[L], si[L];
+    lag_sum_regs<L>(g, q, K, sr, si);
+    const float2 a0 = g[q], a1 = g[q + K];
+#pragma unroll
+    for (int d = 0; d < L; ++d) {
+        const float2 b0 = g[q + d], b1 = g[q + K + d];
+        const float tr = fmaf(a1.x, b1.x, fmaf(a1.y, b1.y, fmaf(-a0.x, b0.x, fmaf(-a0.y, b0.y, sr[d]))));
+        const float ti = fmaf(a1.y, b1.x, fmaf(-a1.x, b1.y, fmaf(-a0.y, b0.x, fmaf(a0.x, b0.y, si[d]))));
+        *reinterpret_cast<float4*>(&sS[d][q]) = make_float4(sr[d], si[d], tr, ti);
+    }
 }
 
 // Trace-normalised T = Q^H R_fb Q from the covariance; false when R is zero
@@ -654,10 +700,9 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     // sum gives omega exactly as below.  Otherwise every root is found.
     bool cert = false;
     if (!full_roots) {
-        double zr0, zi0, lastc = 0.0, rr = 0.0, ri = 0.0;
+        double zr0, zi0, rr = 0.0, ri = 0.0;
         pair_start(w0, lam, K, zr0, zi0);
-        cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, kPairStepTol, lastc, &ls.pair_its) &&
-               lastc <= kPairAcceptTol * (fabs(zr0) + fabs(zi0)) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
+        cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, &ls.pair_its) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
         if (cert) omega = atan2f((float)ri, (float)rr);
     }
     ls.accepted += cert ? 1 : 0;

@@ -196,20 +196,23 @@ def test_max_fft_length_line(dem, torch, bm):
     d.close()
 
 
-BLUESTEIN = [
-    # (W, H, L, N, dtype, dirs): line lengths with a prime factor above 5 take the
-    # analytic step's DFT through Bluestein's identity
-    (1850, 24, 7, 15, np.float32, "x"),      # the paper's experimental frame width (Sec. 4)
-    (48, 700, 5, 15, np.float32, "y"),       # and its height
-    (520, 36, 6, 20, np.float64, "xy"),
-    (263, 70, 4, 16, np.float16, "xy"),      # prime width; height 2 * 5 * 7
+ANY_LENGTH = [
+    # (W, H, L, N, dtype, dirs): line lengths with factors 7, 11, 13 take radix-7/11/13
+    # passes; a prime factor above 13 takes Bluestein's identity.  Odd line counts leave
+    # the last block of the two-line analytic kernel with a single line.
+    (1850, 24, 7, 15, np.float32, "x"),      # the paper's experimental width (Sec. 4): 2 * 5^2 * 37, Bluestein
+    (48, 700, 5, 15, np.float32, "y"),       # and its height: 2^2 * 5^2 * 7, radix 7
+    (1001, 30, 6, 20, np.float64, "xy"),     # 7 * 11 * 13; 1001 columns of 30
+    (520, 36, 6, 20, np.float64, "xy"),      # 2^3 * 5 * 13
+    (263, 70, 4, 16, np.float16, "xy"),      # prime width (Bluestein); height 2 * 5 * 7
     (4093, 3, 6, 24, np.float32, "x"),       # the largest prime length taken
-    (7, 11, 2, 5, np.float32, "xy"),         # shortest lines
+    (7, 11, 2, 5, np.float32, "xy"),         # shortest radix-7 and radix-11 lines
+    (17, 19, 2, 6, np.float32, "xy"),        # shortest Bluestein lines
 ]
 
 
-@pytest.mark.parametrize("W,H,L,N,dt,dirs", BLUESTEIN)
-def test_any_line_length_by_bluestein(dem, torch, W, H, L, N, dt, dirs):
+@pytest.mark.parametrize("W,H,L,N,dt,dirs", ANY_LENGTH)
+def test_any_line_length(dem, torch, W, H, L, N, dt, dirs):
     img = wl.random_frame(W, H, seed=W + H, dtype=dt, snr_db=8.0)
     gx, gy = run(dem, torch, img, L, N, dirs)
     ox, oy = oracle.demodulate(img, L, N, dirs)
