@@ -36,6 +36,11 @@ Workload recipes (all seeded):
         quantisation, seed 5000+i; line windows N = 15 (the paper's 2L+1 with
         L = 7) and covariance size 7.
 
+  sweep window-size sweep field: phi = w0 (x + y) + A sin(k x) + A sin(k y),
+        w0 = 1 rad/px, A k = 0.6 rad/px, k = 2 pi / 48, so the local frequency
+        swings over 0.4 .. 1.6 rad/px and the third derivative of the phase
+        (the bias of a window, which is exact for linear chirps) is 0.6 k^2.
+
 8-bit frames are round(255 * I) clipped to 0..255.
 """
 from __future__ import annotations
@@ -172,6 +177,35 @@ def exp_frame(i: int) -> Frame:
 
 def exp_series(frames=range(19)) -> list:
     return [exp_frame(i) for i in frames]
+
+
+def sweep_frame(W, H, snr_db, seed, w0=1.0, dev=0.6, period=48.0, dtype=np.float64) -> Frame:
+    """Fringe whose local frequency varies sinusoidally in x and y (window-size sweeps).
+
+    truth_wx(ys, xs) = w0 + dev cos(k xs), truth_wy(ys, xs) = w0 + dev cos(k ys), and
+    meta["phase"](ys, xs) is the fringe phase itself.
+    """
+    k = 2.0 * math.pi / period
+    A = dev / k
+    y = np.arange(H, dtype=np.float64)[:, None]
+    x = np.arange(W, dtype=np.float64)[None, :]
+    phase = w0 * (x + y) + A * np.sin(k * x) + A * np.sin(k * y)
+    img = A_DC + B_AC * np.cos(phase)
+    img = img + np.random.default_rng(seed).standard_normal((H, W)) * _noise_sigma(snr_db)
+
+    def truth_wx(ys, xs):
+        return w0 + dev * np.cos(k * np.asarray(xs, dtype=np.float64)) + 0.0 * np.asarray(ys, dtype=np.float64)
+
+    def truth_wy(ys, xs):
+        return w0 + dev * np.cos(k * np.asarray(ys, dtype=np.float64)) + 0.0 * np.asarray(xs, dtype=np.float64)
+
+    def phase_at(ys, xs):
+        ys = np.asarray(ys, dtype=np.float64)
+        xs = np.asarray(xs, dtype=np.float64)
+        return w0 * (xs + ys) + A * np.sin(k * xs) + A * np.sin(k * ys)
+
+    return Frame(img.astype(dtype), L=0, N=0, dirs="xy", truth_wx=truth_wx, truth_wy=truth_wy,
+                 meta={"cfg": "sweep", "snr": snr_db, "phase": phase_at})
 
 
 def complex_tone(W, H, wx, wy, alpha=0.3, amp=1.0, snr_db=None, seed=0):
