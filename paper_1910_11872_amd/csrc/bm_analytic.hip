@@ -38,7 +38,11 @@ template <int R>
 __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int n,
                                               int Ns, const float2* __restrict__ tw) {
     const int nR = n / R;
-    const int tws = n / (Ns * R);
+    // j / Ns by a float reciprocal: (j + 1/2) / Ns is at least 1/(2 Ns) from an
+    // integer and its rounding error stays below (n / Ns) 2^-22, so the
+    // truncation is exact for n <= 8192 (an integer division costs ~30 instructions)
+    const float inv_ns = 1.0f / (float)Ns;
+    const int tws = (int)((float)nR * inv_ns + 0.5f);     // n / (Ns R), an integer
     // odd prime radices: cos and sin of 2 pi r / R from the length's own table
     float cs[R], sn[R];
     if constexpr (R >= 7) {
@@ -50,7 +54,8 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
         }
     }
     for (int j = threadIdx.x; j < nR; j += kFftThreads) {
-        const int k = j % Ns;
+        const int g = (int)(((float)j + 0.5f) * inv_ns);
+        const int k = j - g * Ns;
         float2 v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = src[j + r * nR];
@@ -80,7 +85,7 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
             // v[R-r] = difference), write each output pair as it is formed,
             // y[q], y[R-q] = v0 + sum_r s_r cos(2 pi r q / R) -/+ i sum_r d_r sin(2 pi r q / R)
             constexpr int h = (R - 1) / 2;
-            const int idx = (j / Ns) * Ns * R + k;
+            const int idx = g * Ns * R + k;
             float2 y0 = v[0];
 #pragma unroll
             for (int r = 1; r <= h; ++r) {
@@ -120,7 +125,7 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
             y[2] = cadd(p2, mul_mi(q2));
             y[3] = cadd(p2, mul_pi(q2));
         }
-        const int idx = (j / Ns) * Ns * R + k;
+        const int idx = g * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[idx + r * Ns] = y[r];
     }
@@ -161,13 +166,13 @@ __device__ __forceinline__ float2* fft_forward(float2* a, float2* b, int n, cons
 // chirp-z route through length plan.n = m.  a and b hold m elements each;
 // returns the buffer holding X[0..n) in natural order.
 template <int MAXR>
-__device__ __forceinline__ float2* dft_line(float2* a, float2* b, const FftJob& J) {
+__device__ __forceinline__ float2* dft_line(float2* a, float2* b, const FftJob& J, const float2* tw) {
     const int n = J.n, m = J.plan.n;
-    if (!J.chirp) return fft_forward<MAXR>(a, b, n, J.plan, J.tw);
+    if (!J.chirp) return fft_forward<MAXR>(a, b, n, J.plan, tw);
     for (int i = threadIdx.x; i < m; i += kFftThreads)
         a[i] = i < n ? cmul(a[i], J.chirp[i]) : make_float2(0.f, 0.f);
     __syncthreads();
-    float2* P = fft_forward<MAXR>(a, b, m, J.plan, J.tw);
+    float2* P = fft_forward<MAXR>(a, b, m, J.plan, tw);
     float2* Q = (P == a) ? b : a;
     // circular convolution with conj(w): inverse DFT as the conjugate of a forward one
     for (int k = threadIdx.x; k < m; k += kFftThreads) {
@@ -175,7 +180,7 @@ __device__ __forceinline__ float2* dft_line(float2* a, float2* b, const FftJob& 
         P[k] = make_float2(v.x, -v.y);
     }
     __syncthreads();
-    float2* Y = fft_forward<MAXR>(P, Q, m, J.plan, J.tw);
+    float2* Y = fft_forward<MAXR>(P, Q, m, J.plan, tw);
     for (int k = threadIdx.x; k < n; k += kFftThreads) {
         const float2 v = Y[k];
         Y[k] = cmul(make_float2(v.x, -v.y), J.chirp[k]);
@@ -206,7 +211,7 @@ __device__ __forceinline__ float2 conjf2(float2 v) { return make_float2(v.x, -v.
 
 // One block per work item of any job: a pair of lines (lines 2i, 2i+1) when
 // the transform is short enough for three LDS buffers, else one line.
-template <int MAXR>
+template <int MAXR, bool TWL>
 __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int item0) {
     extern __shared__ float2 lds[];
     const int w = item0 + blockIdx.x;
@@ -221,11 +226,16 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
     float2* a = lds;
     float2* b = lds + m;
     float2* c = lds + 2 * m;            // pairs only
+    // twiddles: staged in LDS once per block (every pass reads them), or read from global memory
+    float2* twl = lds + (pairs ? 3 : 2) * m;
+    if (TWL)
+        for (int i = threadIdx.x; i < m; i += kFftThreads) twl[i] = J.tw[i];
+    const float2* tw = TWL ? twl : J.tw;
     const int64_t off = (int64_t)la * J.src_ls;
     for (int i = threadIdx.x; i < n; i += kFftThreads)
         a[i] = make_float2(load_real(J.src, off + i, elem), two ? load_real(J.src, off + J.src_ls + i, elem) : 0.f);
     __syncthreads();
-    float2* X = dft_line<MAXR>(a, b, J);
+    float2* X = dft_line<MAXR>(a, b, J, tw);
     float2* other = (X == a) ? b : a;
     // one-sided mask and 1/n, then conjugate so that a forward DFT inverts
     const float sc = 2.0f / (float)n;
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
             X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        float2* Y = dft_line<MAXR>(X, other, J);
+        float2* Y = dft_line<MAXR>(X, other, J, tw);
         float2* out = J.dst + (int64_t)la * n;
         for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Y[i]);
         return;
@@ -254,11 +264,11 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
         c[k] = mb;
     }
     __syncthreads();
-    float2* Ya = dft_line<MAXR>(other, X, J);
+    float2* Ya = dft_line<MAXR>(other, X, J, tw);
     float2* spare = (Ya == other) ? X : other;
     float2* out = J.dst + (int64_t)la * n;
     for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Ya[i]);
-    float2* Yb = dft_line<MAXR>(c, spare, J);
+    float2* Yb = dft_line<MAXR>(c, spare, J, tw);
     out += n;
     for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Yb[i]);
 }
@@ -297,22 +307,28 @@ __global__ __launch_bounds__(kTile * 8) void transpose_kernel(TrBatch B) {
 }  // namespace
 
 hipError_t analytic_set_attributes() {
-    const int elems = 2 * kMaxFFT > 3 * kFftPairMax ? 2 * kMaxFFT : 3 * kFftPairMax;
-    hipError_t e = hipFuncSetAttribute((const void*)analytic_kernel<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       elems * (int)sizeof(float2));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)analytic_kernel<13>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               elems * (int)sizeof(float2));
+    const int bytes = kFftLdsElems * (int)sizeof(float2);
+    const void* k[kFftClasses] = {(const void*)analytic_kernel<5, true>, (const void*)analytic_kernel<5, false>,
+                                  (const void*)analytic_kernel<13, true>, (const void*)analytic_kernel<13, false>};
+    for (const void* f : k) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
-    if (b.total <= 0) return hipSuccess;
-    if (b.big_from > 0)
-        hipLaunchKernelGGL(analytic_kernel<5>, dim3(b.big_from), dim3(kFftThreads),
-                           (size_t)b.lds_small * sizeof(float2), s, b, 0);
-    if (b.big_from < b.total)
-        hipLaunchKernelGGL(analytic_kernel<13>, dim3(b.total - b.big_from), dim3(kFftThreads),
-                           (size_t)b.lds_big * sizeof(float2), s, b, b.big_from);
+    for (int c = 0; c < kFftClasses; ++c) {
+        const int i0 = b.cls_from[c], cnt = b.cls_from[c + 1] - i0;
+        if (cnt <= 0) continue;
+        const size_t shmem = (size_t)b.lds[c] * sizeof(float2);
+        switch (c) {
+            case 0: hipLaunchKernelGGL((analytic_kernel<5, true>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
+            case 1: hipLaunchKernelGGL((analytic_kernel<5, false>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
+            case 2: hipLaunchKernelGGL((analytic_kernel<13, true>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
+            default: hipLaunchKernelGGL((analytic_kernel<13, false>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
+        }
+    }
     return hipGetLastError();
 }
 

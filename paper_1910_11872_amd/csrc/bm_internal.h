@@ -95,35 +95,48 @@ struct FftJob {
     FftPlan plan;          // plan of n, or of m under Bluestein (chirp != nullptr)
 };
 
+// LDS of the analytic kernel's block, in complex elements (128 KiB).
+constexpr int kFftLdsElems = 16384;
+
 // Transform lengths up to this take two real lines per block (one complex
-// forward DFT of x_a + i x_b, split by symmetry): three buffers in LDS.
-constexpr int kFftPairMax = 6144;
+// forward DFT of x_a + i x_b, split by symmetry): three line buffers in LDS,
+// plus the twiddle table.
+constexpr int kFftPairMax = 4096;
 
 __host__ __device__ inline bool fft_pairs(int m) { return m <= kFftPairMax; }
+
+// The twiddle table of the transform sits in LDS when it fits beside the line buffers.
+__host__ __device__ inline bool fft_tw_lds(int m) { return (fft_pairs(m) ? 4 : 3) * m <= kFftLdsElems; }
 
 // Work items (blocks) of one job: line pairs or lines.
 inline int fft_items(const FftJob& j) { return fft_pairs(j.plan.n) ? (j.nlines + 1) / 2 : j.nlines; }
 
 // LDS of one job's block, in complex elements.
-inline int fft_lds_elems(const FftJob& j) { return (fft_pairs(j.plan.n) ? 3 : 2) * j.plan.n; }
+inline int fft_lds_elems(const FftJob& j) {
+    const int m = j.plan.n;
+    return (fft_pairs(m) ? 3 : 2) * m + (fft_tw_lds(m) ? m : 0);
+}
 
-// True when the job's plan has a radix above 5 (it runs in the kernel that carries them).
+// True when the job's plan has a radix above 5.
 inline bool fft_big_radix(const FftJob& j) {
     for (int p = 0; p < j.plan.passes; ++p)
         if (j.plan.radix[p] > 5) return true;
     return false;
 }
 
-// Jobs without radices above 5 come first: items [0, big_from) run in the
-// kernel built for radices 2-5, the rest in the one built for all radices.
+// Kernel variant of a job: radices up to 5 or up to 13, twiddles in LDS or in global memory.
+constexpr int kFftClasses = 4;
+inline int fft_class(const FftJob& j) { return (fft_big_radix(j) ? 2 : 0) + (fft_tw_lds(j.plan.n) ? 0 : 1); }
+
+// Jobs are ordered by class: items [cls_from[c], cls_from[c+1]) run in the
+// kernel variant of class c, with lds[c] complex elements of LDS per block.
 struct FftBatch {
     const FftJob* jobs;
     const int* prefix;     // work items (fft_items): njobs + 1 entries
     int njobs;
     int total;
-    int big_from;          // first item of a job with a radix above 5 (total if none)
-    int lds_small;         // max fft_lds_elems over the jobs before / from big_from
-    int lds_big;
+    int cls_from[kFftClasses + 1];
+    int lds[kFftClasses];
 };
 
 // Transpose of one frame (rows x cols, src_ls elements per row) to cols x rows.

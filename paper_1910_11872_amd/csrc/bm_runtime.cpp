@@ -372,7 +372,8 @@ struct GroupPlan {
     std::vector<int> tr_prefix;
     std::vector<bm::FftJob> fft;
     std::vector<int> fft_prefix;
-    int fft_big_from = 0, lds_small = 0, lds_big = 0;
+    int fft_cls_from[bm::kFftClasses + 1] = {};
+    int fft_lds[bm::kFftClasses] = {};
     std::vector<RmSet> rm;          // one (or two, with flags) per distinct L
     std::vector<bm::TrJob> back;    // omega_y from its line-major scratch to the caller's row-major map
     std::vector<int> back_prefix;
@@ -540,19 +541,20 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     if (cur > h->ws_bytes) return fail(h, BM_E_INVALID_ARG, "group exceeds the workspace");
     gp.tr_prefix.assign(1, 0);
     for (auto& t : gp.tr) gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
-    // jobs with radices above 5 last: they run in their own kernel
-    std::stable_partition(gp.fft.begin(), gp.fft.end(), [](const bm::FftJob& f) { return !bm::fft_big_radix(f); });
+    // jobs ordered by kernel variant (radix range, twiddles in LDS or not): one launch per variant
+    std::stable_sort(gp.fft.begin(), gp.fft.end(),
+                     [](const bm::FftJob& x, const bm::FftJob& y) { return bm::fft_class(x) < bm::fft_class(y); });
     gp.fft_prefix.assign(1, 0);
-    gp.fft_big_from = -1;
-    gp.lds_small = gp.lds_big = 0;
+    for (int c = 0; c < bm::kFftClasses; ++c) gp.fft_lds[c] = 0;
+    int cls = 0;
+    gp.fft_cls_from[0] = 0;
     for (auto& f : gp.fft) {
-        const bool big = bm::fft_big_radix(f);
-        if (big && gp.fft_big_from < 0) gp.fft_big_from = gp.fft_prefix.back();
-        int& l = big ? gp.lds_big : gp.lds_small;
-        l = std::max(l, bm::fft_lds_elems(f));
+        const int c = bm::fft_class(f);
+        while (cls < c) gp.fft_cls_from[++cls] = gp.fft_prefix.back();
+        gp.fft_lds[c] = std::max(gp.fft_lds[c], bm::fft_lds_elems(f));
         gp.fft_prefix.push_back(gp.fft_prefix.back() + bm::fft_items(f));
     }
-    if (gp.fft_big_from < 0) gp.fft_big_from = gp.fft_prefix.back();
+    while (cls < bm::kFftClasses) gp.fft_cls_from[++cls] = gp.fft_prefix.back();
     gp.back_prefix.assign(1, 0);
     for (auto& t : gp.back) gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
     for (auto& kv : sets) {
@@ -595,9 +597,8 @@ void bind_group(bosmusic_s* h, GroupPlan& gp, const char* dev) {
     gp.fftb.prefix = (const int*)(dev + gp.fftp_off);
     gp.fftb.njobs = (int)gp.fft.size();
     gp.fftb.total = gp.fft_prefix.back();
-    gp.fftb.big_from = gp.fft_big_from;
-    gp.fftb.lds_small = gp.lds_small;
-    gp.fftb.lds_big = gp.lds_big;
+    for (int c = 0; c <= bm::kFftClasses; ++c) gp.fftb.cls_from[c] = gp.fft_cls_from[c];
+    for (int c = 0; c < bm::kFftClasses; ++c) gp.fftb.lds[c] = gp.fft_lds[c];
     gp.backb.jobs = (const bm::TrJob*)(dev + gp.back_off);
     gp.backb.prefix = (const int*)(dev + gp.backp_off);
     gp.backb.njobs = (int)gp.back.size();
@@ -1039,8 +1040,8 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             fb.prefix = (const int*)(h->ds + o_fp);
             fb.njobs = 1;
             fb.total = fprefix[1];
-            fb.big_from = bm::fft_big_radix(fj) ? 0 : fb.total;
-            fb.lds_small = fb.lds_big = bm::fft_lds_elems(fj);
+            for (int c = 0; c <= bm::kFftClasses; ++c) fb.cls_from[c] = c <= bm::fft_class(fj) ? 0 : fb.total;
+            for (int c = 0; c < bm::kFftClasses; ++c) fb.lds[c] = bm::fft_lds_elems(fj);
             bm::RmBatch rb{};
             rb.jobs = (const bm::RmJob*)(h->ds + o_rj);
             rb.prefix = (const int*)(h->ds + o_rp);

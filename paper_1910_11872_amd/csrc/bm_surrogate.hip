@@ -193,9 +193,10 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
     // frequency than the prediction itself: u1[i+1]/u1[i] ~ e^{j w}, so the
     // lag-1 coefficient c_1 ~ -((L-1)/L) e^{-j w}.  Newton for the signal
     // root (its mate divided out) starts there.
-    const float w1 = atan2f(ai[L], -ar[L]);
+    float c1w, s1w;
+    guess_direction(ar[L], ai[L], c1w, s1w);
     double zr, zi, rr = 0.0, ri = 0.0;
-    pair_start(w1, lam, K, zr, zi);
+    pair_start(c1w, s1w, lam, K, zr, zi);
     if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, nullptr)) return false;
     if (!certified_root<L>(ar, ai, zr, zi, rr, ri)) return false;
     const float w = atan2f((float)ri, (float)rr);

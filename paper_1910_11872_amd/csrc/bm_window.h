@@ -571,13 +571,22 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     return zeros_inside_unit_disk<n - 2>(fr, fi) == L - 2;
 }
 
-// Start of the pair iteration: the guessed frequency at the radius the
-// signal root typically has, 1 - r ~ 1.6 (1 - lambda_1) / K for K
+// Direction of the frequency guess from the lag-1 coefficient: u1[i+1]/u1[i]
+// ~ e^{j w}, so c_1 ~ -((L-1)/L) e^{-j w} and e^{j w} = -conj(c_1) / |c_1|
+// (no trigonometric functions needed); (1, 0) when c_1 vanishes.
+__device__ __forceinline__ void guess_direction(float c1r, float c1i, float& cw, float& sw) {
+    const float m2 = c1r * c1r + c1i * c1i;
+    const bool ok = m2 > 0.f && finitef(m2);
+    const float im = ok ? frsq(m2) : 0.f;
+    cw = ok ? -c1r * im : 1.f;
+    sw = ok ? c1i * im : 0.f;
+}
+
+// Start of the pair iteration: the guessed direction (cw, sw) at the radius
+// the signal root typically has, 1 - r ~ 1.6 (1 - lambda_1) / K for K
 // snapshots and lambda_1 the trace-normalised top eigenvalue.
-__device__ __forceinline__ void pair_start(float w, float lam, int K, double& zr, double& zi) {
+__device__ __forceinline__ void pair_start(float cw, float sw, float lam, int K, double& zr, double& zi) {
     const float r0 = fminf(0.9999f, fmaxf(0.9f, 1.f - 1.6f * (1.f - lam) / (float)K));
-    float sw, cw;
-    sincosf(w, &sw, &cw);
     zr = (double)(r0 * cw);
     zi = (double)(r0 * sw);
 }
@@ -688,10 +697,9 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     float ar[n + 1], ai[n + 1];
     poly_coeffs<L>(ur, ui, ar, ai);
 
-    // frequency guess: u1[i+1]/u1[i] ~ e^{j w}, so c_1 ~ -((L-1)/L) e^{-j w}
-    const float w0 = atan2f(ai[L], -ar[L]);
+    // frequency guess from the lag-1 coefficient c_1
     float sw0, cw0;
-    sincosf(w0, &sw0, &cw0);
+    guess_direction(ar[L], ai[L], cw0, sw0);
 
     // ---- certified pair ---------------------------------------------------
     // FP64 Newton (with the mate divided out) for the signal root from the
@@ -701,7 +709,7 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     bool cert = false;
     if (!full_roots) {
         double zr0, zi0, rr = 0.0, ri = 0.0;
-        pair_start(w0, lam, K, zr0, zi0);
+        pair_start(cw0, sw0, lam, K, zr0, zi0);
         cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, &ls.pair_its) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
         if (cert) omega = atan2f((float)ri, (float)rr);
     }
