@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
 # certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
 # frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35594.9375 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35584.8125 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
 
 
 def bairstow_flops(n: int) -> int:
@@ -58,13 +58,13 @@ def certificate_flops(L: int) -> int:
 
 
 def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,
-                     cert_frac: float = 0.0, block: bool = False) -> dict:
+                     cert_frac: float = 0.0, block: bool = False, pair_iters32: float = 0.0) -> dict:
     """Algorithmic flop count of one window of the root-MUSIC kernel.
 
     FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` is the
     measured mean number of Newton steps for the largest eigenvalue per
-    window, `pair_iters` the mean FP64 Newton steps for the signal root
-    before the certificate, `cert_frac` the fraction of windows
+    window, `pair_iters32` and `pair_iters` the mean FP32 and FP64 Newton
+    steps for the signal root before the certificate, `cert_frac` the fraction of windows
     finished by the certificate, and `iters` the mean simultaneous root
     iterations of the windows whose roots were all found.  Certificate work
     of a window that fails it is not counted.  `block`: the L x L block
@@ -91,7 +91,7 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     start = 4 * n + 40
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
-    fp32 = common32 + full * (start + aberth + select)
+    fp32 = common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(n)
     fp64 = pair_iters * pair_newton_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
@@ -418,6 +418,7 @@ def main():
         sdem.close()
         nwin = max(1, ss["windows"])
         newton = ss["eig_iters"] / nwin
+        pair_its32 = ss.get("pair_iters32", 0) / nwin
         if surrogate:
             # the fallback windows (the surrogate kernel's own work is modelled below)
             iters = ss["root_iters"] / nwin
@@ -436,11 +437,13 @@ def main():
                 wins += 2 * max(0, W - N + 1) * max(0, H - N + 1)
             else:
                 wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
-        fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert, block=bool(args.block))
+        fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert, block=bool(args.block),
+                              pair_iters32=pair_its32)
         entry = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2), "root_iters": round(iters, 2),
                  "windows_per_step": wins}
         if not surrogate:
-            entry.update({"pair_iters": round(pair_its, 2), "certified_fraction": round(cert, 5)})
+            entry.update({"pair_iters32": round(pair_its32, 2), "pair_iters": round(pair_its, 2),
+                          "certified_fraction": round(cert, 5)})
         if surrogate:
             acc, rej = ss["sur_accepted"], ss["sur_rejected"]
             frac_rej = rej / max(1, acc + rej)

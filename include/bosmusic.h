@@ -144,6 +144,8 @@ typedef struct {
                                (its mate divided out) before the certificate */
     uint64_t rm_launches;   /* root-MUSIC kernel launches timed (BM_OPT_TIMING) */
     uint64_t rm_time_ns;    /* their summed duration between HIP events, ns */
+    uint64_t pair_iters32;  /* sum over windows of FP32 Newton steps for the signal root,
+                               taken before the FP64 ones */
 } bosmusic_stats;
 
 /* Create a handle on cfg->device, allocating the workspace for frames up to

@@ -14,7 +14,7 @@ constexpr int kMaxN = 64;
 constexpr int kMaxFFT = 8192;
 constexpr int kMaxRadixPasses = 20;
 constexpr int kStatSlots = 64;   // counter slots of the statistics buffer
-constexpr int kStatFields = 8;   // counters per slot (6 used)
+constexpr int kStatFields = 8;   // counters per slot
 constexpr int kGatherBlock = 256;
 
 // Mixed-radix plan of one DFT length (radices 4, 2, 3, 5, 7, 11, 13 in pass order).

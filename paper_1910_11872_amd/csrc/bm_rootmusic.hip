@@ -222,20 +222,20 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
 
 template <int BLOCK>
 __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long long* stats) {
-    unsigned long long a[7] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
+    unsigned long long a[8] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
                                (unsigned long long)ls.iters, (unsigned long long)ls.pfail,
                                (unsigned long long)ls.accepted, (unsigned long long)ls.rejected,
-                               (unsigned long long)ls.pair_its};
+                               (unsigned long long)ls.pair_its, (unsigned long long)ls.pair_its32};
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int c = 0; c < 7; ++c) a[c] += __shfl_xor(a[c], off);
+        for (int c = 0; c < 8; ++c) a[c] += __shfl_xor(a[c], off);
     if ((threadIdx.x & 63) == 0) {
         // spread the counters over kStatSlots slots to avoid one hot address
         unsigned long long* sl =
             stats + kStatFields * ((blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) % kStatSlots);
 #pragma unroll
-        for (int c = 0; c < 7; ++c)
+        for (int c = 0; c < 8; ++c)
             if (a[c]) atomicAdd(sl + c, a[c]);
     }
 }

@@ -1613,6 +1613,7 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
         out->sur_accepted = v[4];
         out->sur_rejected = v[5];
         out->pair_iters = v[6];
+        out->pair_iters32 = v[7];
         out->rm_launches = h->rm_launches;
         out->rm_time_ns = h->rm_time_ns;
         if (reset) h->rm_launches = h->rm_time_ns = 0;

@@ -197,6 +197,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
     guess_direction(ar[L], ai[L], c1w, s1w);
     double zr, zi, rr = 0.0, ri = 0.0;
     pair_start(c1w, s1w, lam, K, zr, zi);
+    pair_newton32<n>(ar, ai, zr, zi, kCertIters32, nullptr);
     if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, nullptr)) return false;
     if (!certified_root<L>(ar, ai, zr, zi, rr, ri)) return false;
     const float w = atan2f((float)ri, (float)rr);

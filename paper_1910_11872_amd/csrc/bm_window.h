@@ -36,7 +36,8 @@ constexpr float kJacobiTol2 = BM_JACOBI_TOL2;
 constexpr int kMaxRootIters = BM_MAX_ROOT_ITERS;
 constexpr float kRootTol2 = BM_ROOT_TOL2;
 constexpr int kPolishIters = BM_POLISH_ITERS;
-constexpr int kCertIters = 8;     // at most this many FP64 Newton steps before the pair certificate
+constexpr int kCertIters32 = 6;   // at most this many FP32 Newton steps towards the signal root
+constexpr int kCertIters = 8;     // then at most this many FP64 Newton steps before the pair certificate
 // Newton with the mate divided out converges quadratically once the error is
 // small against the distance |z - 1/conj z| to the mate: iterating stops at
 // the first step below 1e-4 |z| and below 1e-2 |z - 1/conj z| (the error
@@ -328,7 +329,7 @@ __device__ __forceinline__ void store_omega(const RmJob& J, int line, int p, flo
 
 // Counters a lane accumulates over the windows it owns.
 struct LaneStats {
-    int counted = 0, eig_its = 0, iters = 0, pfail = 0, accepted = 0, rejected = 0, pair_its = 0;
+    int counted = 0, eig_its = 0, iters = 0, pfail = 0, accepted = 0, rejected = 0, pair_its = 0, pair_its32 = 0;
 };
 
 // u1 = Q v for the unitary transform used by build_T.
@@ -483,6 +484,44 @@ __device__ __forceinline__ double rcp64(double x) {
 // out (Maehly's correction), which keeps the convergence quadratic although
 // the two roots nearly coincide near the unit circle:
 //   z <- z - P(z) / (P'(z) - P(z) / (z - 1/conj(z)))
+// FP32 approach to the same root: at most `iters` steps of the iteration
+// above in FP32, ending at the first step below 1e-3 |z|.  Per-phase counters
+// of this kernel show its FP64 phases taking about twice the cycles per
+// instruction of its FP32 phases, and from the point reached here the FP64
+// steps below stop after about one step (numpy trials: FP64 steps of a
+// wave's slowest lane 3.4 -> 1.3 at 10 dB, plus 2.5 FP32 steps).  A
+// non-finite step leaves z at the last finite iterate.
+template <int n>
+__device__ __forceinline__ void pair_newton32(const float (&ar)[n + 1], const float (&ai)[n + 1], double& zr,
+                                              double& zi, int iters, int* its) {
+    float xr = (float)zr, xi = (float)zi;
+    for (int it = 0; it < iters; ++it) {
+        if (its) ++*its;
+        float Pr = ar[n], Pi = ai[n], Dr = 0.f, Di = 0.f;
+#pragma unroll
+        for (int j = n - 1; j >= 0; --j) {
+            const float nDr = fmaf(Dr, xr, fmaf(-Di, xi, Pr)), nDi = fmaf(Dr, xi, fmaf(Di, xr, Pi));
+            const float nPr = fmaf(Pr, xr, fmaf(-Pi, xi, ar[j]));
+            const float nPi = fmaf(Pr, xi, fmaf(Pi, xr, ai[j]));
+            Dr = nDr; Di = nDi; Pr = nPr; Pi = nPi;
+        }
+        const float f = 1.f - frcp(fmaf(xr, xr, xi * xi));
+        const float ur = xr * f, ui = xi * f;
+        const float nr = fmaf(Pr, ur, -Pi * ui), ni = fmaf(Pr, ui, Pi * ur);
+        const float dr = fmaf(Dr, ur, -Di * ui) - Pr, di = fmaf(Dr, ui, Di * ur) - Pi;
+        const float q = frcp(fmaf(dr, dr, di * di));
+        const float sr = fmaf(nr, dr, ni * di) * q, si = fmaf(ni, dr, -nr * di) * q;
+        if (!(finitef(sr) && finitef(si))) break;
+        xr -= sr;
+        xi -= si;
+        if (fabsf(sr) + fabsf(si) <= 1e-3f * (fabsf(xr) + fabsf(xi))) break;
+    }
+    if (finitef(xr) && finitef(xi)) {
+        zr = (double)xr;
+        zi = (double)xi;
+    }
+}
+
 // At most `iters` steps; true once a step meets the stop rule above, false
 // when none did or a step is not finite.
 template <int n>
@@ -710,6 +749,7 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     if (!full_roots) {
         double zr0, zi0, rr = 0.0, ri = 0.0;
         pair_start(cw0, sw0, lam, K, zr0, zi0);
+        pair_newton32<n>(ar, ai, zr0, zi0, kCertIters32, &ls.pair_its32);
         cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, &ls.pair_its) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
         if (cert) omega = atan2f((float)ri, (float)rr);
     }
