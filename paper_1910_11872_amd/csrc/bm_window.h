@@ -446,18 +446,18 @@ __device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], doubl
         const double g = p0 - pd;
         ok = ok && (fabs(g) > 1e-9 * (p0 + pd));
         neg |= (g < 0.0 ? 1u : 0u) << d;
-        const double sc = __builtin_amdgcn_rcp(p0 + pd);   // any positive scale: only signs are read
-        // new_i = conj(a0) a_i - a_d conj(a_{d-i}), in place over the pairs (i, d-i)
+        // any positive scale keeps the signs that are read; folded into a0 and a_d
+        const double sc = __builtin_amdgcn_rcp(p0 + pd);
+        const double br = a0r * sc, bi = a0i * sc, cr = adr * sc, ci = adi * sc;
+        // new_i = conj(a0) a_i - a_d conj(a_{d-i}) (times sc), in place over the pairs (i, d-i)
 #pragma unroll
         for (int i = 1; 2 * i <= d; ++i) {
             const int k = d - i;
             const double xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
-            const double nir = (a0r * xr + a0i * xi) - (adr * yr + adi * yi);
-            const double nii = (a0r * xi - a0i * xr) - (adi * yr - adr * yi);
-            const double nkr = (a0r * yr + a0i * yi) - (adr * xr + adi * xi);
-            const double nki = (a0r * yi - a0i * yr) - (adi * xr - adr * xi);
-            fr[i] = nir * sc; fi[i] = nii * sc;
-            fr[k] = nkr * sc; fi[k] = nki * sc;
+            fr[i] = fma(br, xr, fma(bi, xi, -fma(cr, yr, ci * yi)));
+            fi[i] = fma(br, xi, fma(-bi, xr, -fma(ci, yr, -cr * yi)));
+            fr[k] = fma(br, yr, fma(bi, yi, -fma(cr, xr, ci * xi)));
+            fi[k] = fma(br, yi, fma(-bi, yr, -fma(ci, xr, -cr * xi)));
         }
         fr[0] = g * sc;
         fi[0] = 0.0;
@@ -583,13 +583,13 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     // z^2 - r z - s with s = -z_in / conj(z_in)
     const double s_r = -(z0r * z1r - z0i * z1i), s_i = -(z0r * z1i + z0i * z1r);
     double fr[n - 1], fi[n - 1];
-    double scale = 0.0;
+    float scale = 0.f;                                // size of the (FP32) coefficients
     double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
 #pragma unroll
     for (int k = n; k >= 0; --k) {
         const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
         const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
-        scale += fabs((double)ar[k]) + fabs((double)ai[k]);
+        scale += fabsf(ar[k]) + fabsf(ai[k]);
         if (k >= 2) {
             fr[k - 2] = bkr;
             fi[k - 2] = bki;
@@ -597,7 +597,7 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
         b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
     }
     // remainder b1 (z - r) + b0: here b2 = b_1 and b1 = b_0
-    if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= kCertRemTol * scale)) return false;
+    if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= kCertRemTol * (double)scale)) return false;
     if (L == 2) return true;                          // no other roots
     const double rho = rin * (1.0 - kCertMargin);
     double rp = 1.0;
