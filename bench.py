@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
 # certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
 # frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35566.5625 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35602.0625 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
 
 
 def bairstow_flops(n: int) -> int:
@@ -78,9 +78,9 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
         # block window: L snapshots, upper triangle of L x L complex products each
         lag = L * (L * (L + 1) // 2 * 8 - 4 * L)
     else:
-        # lag sums (complex MAC = 4 FMA): a lane sums its first start directly (K L MACs)
-        # and slides to its second (2 L MACs), so per window half of that
-        lag = (K * L * 8 + 16 * L) / 2
+        # lag sums (complex MAC = 4 FMA; the zero lag is real, 2 FMA): a lane sums its first
+        # start directly (K L MACs) and slides to its second (2 L MACs), so per window half of that
+        lag = (K * (8 * L - 4) + 16 * L - 8) / 2
     build_t = 3 * L * L + L + L * (L + 1) // 2        # T from R, trace normalisation
     house = sum(2 * l * l + 2 * l * (l + 1) + 9 * l for l in range(2, L))
     newton_f = newton * 8 * L + 7 * L + 2

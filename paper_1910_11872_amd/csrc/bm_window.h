@@ -650,7 +650,7 @@ __device__ __forceinline__ void lag_sum_regs(const float2* g, int t, int K, floa
             for (int d = 0; d < L; ++d) {
                 const float2 a = win[u], b = win[(u + d) % L];
                 sr[d] = fmaf(a.x, b.x, fmaf(a.y, b.y, sr[d]));
-                si[d] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[d]));
+                if (d > 0) si[d] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[d]));   // S_0 is real
             }
         }
     }
@@ -662,7 +662,7 @@ __device__ __forceinline__ void lag_sum_regs(const float2* g, int t, int K, floa
             for (int d = 0; d < L; ++d) {
                 const float2 a = win[u], b = win[(u + d) % L];
                 sr[d] = fmaf(a.x, b.x, fmaf(a.y, b.y, sr[d]));
-                si[d] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[d]));
+                if (d > 0) si[d] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[d]));   // S_0 is real
             }
         }
     }
@@ -689,7 +689,7 @@ __device__ __forceinline__ void lag_sums_pair(const float2* g, int q, int K, flo
     for (int d = 0; d < L; ++d) {
         const float2 b0 = g[q + d], b1 = g[q + K + d];
         const float tr = fmaf(a1.x, b1.x, fmaf(a1.y, b1.y, fmaf(-a0.x, b0.x, fmaf(-a0.y, b0.y, sr[d]))));
-        const float ti = fmaf(a1.y, b1.x, fmaf(-a1.x, b1.y, fmaf(-a0.y, b0.x, fmaf(a0.x, b0.y, si[d]))));
+        const float ti = d == 0 ? 0.f : fmaf(a1.y, b1.x, fmaf(-a1.x, b1.y, fmaf(-a0.y, b0.x, fmaf(a0.x, b0.y, si[d]))));
         *reinterpret_cast<float4*>(&sS[d][q]) = make_float4(sr[d], si[d], tr, ti);
     }
 }

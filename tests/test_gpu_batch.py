@@ -167,3 +167,32 @@ def test_autotune_picks_a_candidate_and_caches_it(bm, torch, tmp_path):
     compare_omega(wx.cpu().numpy(), ox, "tuned x")
     compare_omega(wy.cpu().numpy(), oy, "tuned y")
     d.close()
+
+
+def test_every_analytic_kernel_variant_in_one_batch(bm, torch):
+    """One call whose line lengths need all four analytic kernel variants (radices up to 5 or
+    up to 13, twiddles in LDS or not) plus Bluestein: each frame equals its own single call
+    bit for bit and the oracle on sampled lines."""
+    shapes = [
+        (1024, 6, 6, 20, np.float32),     # radix 4: pairs, twiddles in LDS
+        (700, 5, 5, 15, np.uint8),        # radix 7: the large-radix kernel
+        (1850, 4, 7, 15, np.float32),     # Bluestein at m = 3750 (5-smooth)
+        (8192, 3, 6, 24, np.float32),     # single lines, twiddles in global memory
+        (7000, 3, 4, 16, np.float64),     # radix 7, single lines, twiddles in global memory
+    ]
+    d = bm.Demodulator(0, max_width=8192, max_height=16)
+    specs, imgs = [], []
+    for k, (W, H, L, N, dt) in enumerate(shapes):
+        img = wl.random_frame(W, H, seed=500 + k, dtype=dt, snr_db=8.0)
+        specs.append(bm.FrameSpec(torch.from_numpy(img).to("cuda"), L, N, bm.BM_DIR_X,
+                                  torch.full((H, W), -7.0, device="cuda")))
+        imgs.append(img)
+    bm.bosmusic_demodulate(d.h, specs)
+    got = outputs(torch, specs)
+    for k, (W, H, L, N, dt) in enumerate(shapes):
+        single, _ = d.demodulate(specs[k].data, L, N, "x")
+        torch.cuda.synchronize()
+        assert np.array_equal(got[3 * k], single.cpu().numpy(), equal_nan=True), shapes[k]
+        rows = [0, H - 1]
+        compare_omega(got[3 * k][rows], oracle_rows(imgs[k], rows, L, N), f"variant batch {W}")
+    d.close()

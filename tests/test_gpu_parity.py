@@ -285,6 +285,8 @@ def test_stats_count_windows(dem, torch):
     assert s["eig_iters"] >= s["windows"]
     assert s["sur_accepted"] + s["sur_rejected"] == s["windows"]        # certified pair or all roots
     assert s["pair_iters"] >= s["windows"] and s["root_iters"] >= s["sur_rejected"]
+    # FP32 steps towards the signal root come first, at least one per window that took them
+    assert s["pair_iters32"] >= s["sur_accepted"]
     print(s)
 
 
