@@ -34,6 +34,9 @@ __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.
 __device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
 
 // One forward Stockham pass of radix R over the whole line: src -> dst.
+// tw is the pass's own table: tw[(r-1) Ns + k] = e^{-2 pi i r k / (Ns R)} for
+// 0 < r < R, k < Ns (contiguous in k, so neighbouring lanes read neighbouring
+// entries), then tw[(R-1) Ns + r - 1] = e^{-2 pi i r / R}, the butterfly's own.
 template <int R>
 __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int n,
                                               int Ns, const float2* __restrict__ tw) {
@@ -42,13 +45,14 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
     // integer and its rounding error stays below (n / Ns) 2^-22, so the
     // truncation is exact for n <= 8192 (an integer division costs ~30 instructions)
     const float inv_ns = 1.0f / (float)Ns;
-    const int tws = (int)((float)nR * inv_ns + 0.5f);     // n / (Ns R), an integer
     // odd prime radices: cos and sin of 2 pi r / R from the length's own table
     float cs[R], sn[R];
     if constexpr (R >= 7) {
+        cs[0] = 1.f;
+        sn[0] = 0.f;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float2 w = tw[r * nR];          // e^{-2 pi i r / R}
+        for (int r = 1; r < R; ++r) {
+            const float2 w = tw[(R - 1) * Ns + r - 1];          // e^{-2 pi i r / R}
             cs[r] = w.x;
             sn[r] = -w.y;
         }
@@ -60,19 +64,19 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = src[j + r * nR];
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tws]);
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(r - 1) * Ns + k]);
         float2 y[R];
-        if (R == 2) {
+        if constexpr (R == 2) {
             y[0] = cadd(v[0], v[1]);
             y[1] = csub(v[0], v[1]);
-        } else if (R == 4) {
+        } else if constexpr (R == 4) {
             const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
             const float2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
             y[0] = cadd(t0, t2);
             y[2] = csub(t0, t2);
             y[1] = cadd(t1, mul_mi(t3));
             y[3] = cadd(t1, mul_pi(t3));
-        } else if (R == 3) {
+        } else if constexpr (R == 3) {
             constexpr float h = 0.866025403784438647f;  // sin(2 pi / 3)
             const float2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
             const float2 base = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
@@ -80,7 +84,7 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
             y[0] = cadd(v[0], s);
             y[1] = cadd(base, rot);
             y[2] = csub(base, rot);
-        } else if (R >= 7) {
+        } else if constexpr (R >= 7) {
             // odd prime radix: pair the inputs r and R-r (in place: v[r] = sum,
             // v[R-r] = difference), write each output pair as it is formed,
             // y[q], y[R-q] = v0 + sum_r s_r cos(2 pi r q / R) -/+ i sum_r d_r sin(2 pi r q / R)
@@ -110,7 +114,7 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
                 dst[idx + (R - q) * Ns] = cadd(a, mul_pi(b));
             }
             continue;
-        } else if (R == 5) {
+        } else if constexpr (R == 5) {
             constexpr float c1 = 0.309016994374947424f, c2 = -0.809016994374947424f;
             constexpr float s1 = 0.951056516295153572f, s2 = 0.587785252292473129f;
             const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
@@ -146,13 +150,15 @@ __device__ __forceinline__ float2* fft_forward(float2* a, float2* b, int n, cons
     int Ns = 1;
     for (int ps = 0; ps < plan.passes; ++ps) {
         const int R = plan.radix[ps];
-        if (R == 4) stockham_pass<4>(a, b, n, Ns, tw);
-        else if (R == 2) stockham_pass<2>(a, b, n, Ns, tw);
-        else if (R == 3) stockham_pass<3>(a, b, n, Ns, tw);
-        else if (MAXR <= 5 || R == 5) stockham_pass<5>(a, b, n, Ns, tw);
-        else if (R == 7) stockham_pass_odd<7>(a, b, n, Ns, tw);
-        else if (R == 11) stockham_pass_odd<11>(a, b, n, Ns, tw);
-        else stockham_pass_odd<13>(a, b, n, Ns, tw);
+        const float2* twp = tw;                 // this pass's table, then the next one's
+        tw += (R - 1) * (Ns + 1);
+        if (R == 4) stockham_pass<4>(a, b, n, Ns, twp);
+        else if (R == 2) stockham_pass<2>(a, b, n, Ns, twp);
+        else if (R == 3) stockham_pass<3>(a, b, n, Ns, twp);
+        else if (MAXR <= 5 || R == 5) stockham_pass<5>(a, b, n, Ns, twp);
+        else if (R == 7) stockham_pass_odd<7>(a, b, n, Ns, twp);
+        else if (R == 11) stockham_pass_odd<11>(a, b, n, Ns, twp);
+        else stockham_pass_odd<13>(a, b, n, Ns, twp);
         __syncthreads();
         float2* t = a;
         a = b;
@@ -229,7 +235,7 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
     // twiddles: staged in LDS once per block (every pass reads them), or read from global memory
     float2* twl = lds + (pairs ? 3 : 2) * m;
     if (TWL)
-        for (int i = threadIdx.x; i < m; i += kFftThreads) twl[i] = J.tw[i];
+        for (int i = threadIdx.x; i < J.tw_len; i += kFftThreads) twl[i] = J.tw[i];
     const float2* tw = TWL ? twl : J.tw;
     const int64_t off = (int64_t)la * J.src_ls;
     for (int i = threadIdx.x; i < n; i += kFftThreads)

@@ -86,7 +86,8 @@ struct FftJob {
     const void* src;       // real lines, src_ls elements apart
     int64_t src_ls;
     float2* dst;           // complex lines, n apart
-    const float2* tw;      // twiddles e^{-2 pi i k / plan.n}, k < plan.n
+    const float2* tw;      // per-pass twiddle tables of plan.n, tw_len entries in all
+    int tw_len;
     const float2* chirp;   // Bluestein only: e^{-i pi j^2 / n}, j < n
     const float2* kern;    // Bluestein only: DFT_m of the conjugate chirp, wrapped, divided by m
     int elem;              // Elem of src
@@ -95,8 +96,9 @@ struct FftJob {
     FftPlan plan;          // plan of n, or of m under Bluestein (chirp != nullptr)
 };
 
-// LDS of the analytic kernel's block, in complex elements (128 KiB).
-constexpr int kFftLdsElems = 16384;
+// LDS of the analytic kernel's block, in complex elements (132 KiB): three
+// 4096-sample buffers and their twiddle tables, or two 8192-sample buffers.
+constexpr int kFftLdsElems = 16896;
 
 // Transform lengths up to this take two real lines per block (one complex
 // forward DFT of x_a + i x_b, split by symmetry): three line buffers in LDS,
@@ -105,16 +107,28 @@ constexpr int kFftPairMax = 4096;
 
 __host__ __device__ inline bool fft_pairs(int m) { return m <= kFftPairMax; }
 
-// The twiddle table of the transform sits in LDS when it fits beside the line buffers.
-__host__ __device__ inline bool fft_tw_lds(int m) { return (fft_pairs(m) ? 4 : 3) * m <= kFftLdsElems; }
+// The twiddle tables of the transform sit in LDS when they fit beside the line buffers
+// (the tables hold at most plan.n + 64 entries).
+__host__ __device__ inline bool fft_tw_lds(int m) { return (fft_pairs(m) ? 4 : 3) * m + 64 <= kFftLdsElems; }
 
 // Work items (blocks) of one job: line pairs or lines.
 inline int fft_items(const FftJob& j) { return fft_pairs(j.plan.n) ? (j.nlines + 1) / 2 : j.nlines; }
 
+// Entries of the per-pass twiddle tables of a plan: (R - 1)(Ns + 1) per pass,
+// at most plan.n + 64.
+inline int fft_tw_len(const FftPlan& p) {
+    int len = 0, ns = 1;
+    for (int i = 0; i < p.passes; ++i) {
+        len += (p.radix[i] - 1) * (ns + 1);
+        ns *= p.radix[i];
+    }
+    return len;
+}
+
 // LDS of one job's block, in complex elements.
 inline int fft_lds_elems(const FftJob& j) {
     const int m = j.plan.n;
-    return (fft_pairs(m) ? 3 : 2) * m + (fft_tw_lds(m) ? m : 0);
+    return (fft_pairs(m) ? 3 : 2) * m + (fft_tw_lds(m) ? fft_tw_len(j.plan) : 0);
 }
 
 // True when the job's plan has a radix above 5.

@@ -241,20 +241,36 @@ void make_template(int L, bm::RootTemplate& t) {
     for (int i = n; i < 2 * bm::kMaxL - 2; ++i) t.re[i] = t.im[i] = 0.f;
 }
 
-bm_status get_twiddles(bosmusic_s* h, int n, const float2** out) {
+// Per-pass twiddle tables of the mixed-radix plan of n: for pass p with
+// radix R and stride Ns, e^{-2 pi i r k / (Ns R)} at (r - 1) Ns + k (0 < r < R,
+// k < Ns), then the butterfly constants e^{-2 pi i r / R} (0 < r < R); the
+// angle is reduced exactly (r k mod Ns R) and evaluated in FP64, rounded once.
+bm_status get_twiddles(bosmusic_s* h, int n, const float2** out, int* len) {
+    bm::FftPlan plan;
+    if (!plan_fft(n, plan)) return fail(h, BM_E_UNSUPPORTED, "twiddles of %d", n);
+    *len = bm::fft_tw_len(plan);
     auto it = h->twiddles.find(n);
     if (it != h->twiddles.end()) {
         *out = it->second;
         return BM_OK;
     }
-    std::vector<float2> tw(n);
-    for (int m = 0; m < n; ++m) {
-        const double a = -2.0 * M_PI * (double)m / (double)n;
-        tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    std::vector<float2> tw;
+    tw.reserve(*len);
+    auto put = [&](int64_t num, int64_t den) {
+        const double a = -2.0 * M_PI * (double)(num % den) / (double)den;
+        tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+    };
+    int ns = 1;
+    for (int p = 0; p < plan.passes; ++p) {
+        const int R = plan.radix[p];
+        for (int r = 1; r < R; ++r)
+            for (int k = 0; k < ns; ++k) put((int64_t)r * k, (int64_t)ns * R);
+        for (int r = 1; r < R; ++r) put(r, R);
+        ns *= R;
     }
     float2* d = nullptr;
-    if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return fail(h, BM_E_NOMEM, "twiddle table of %d", n);
-    if (hipMemcpy(d, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMalloc(&d, sizeof(float2) * tw.size()) != hipSuccess) return fail(h, BM_E_NOMEM, "twiddle table of %d", n);
+    if (hipMemcpy(d, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
         return fail(h, BM_E_DEVICE, "twiddle upload failed");
     }
@@ -303,10 +319,10 @@ bm_status get_bluestein(bosmusic_s* h, int n, int m, const float2** chirp, const
 bm_status make_fft_job(bosmusic_s* h, int n, bm::FftJob& fj) {
     fj.n = n;
     fj.chirp = fj.kern = nullptr;
-    if (plan_fft(n, fj.plan)) return get_twiddles(h, n, &fj.tw);
+    if (plan_fft(n, fj.plan)) return get_twiddles(h, n, &fj.tw, &fj.tw_len);
     const int m = bluestein_len(n);
     if (m == 0 || !plan_fft(m, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "line length %d", n);
-    bm_status st = get_twiddles(h, m, &fj.tw);
+    bm_status st = get_twiddles(h, m, &fj.tw, &fj.tw_len);
     if (st != BM_OK) return st;
     return get_bluestein(h, n, m, &fj.chirp, &fj.kern);
 }

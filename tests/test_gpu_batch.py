@@ -20,6 +20,8 @@ MIX = [
     (360, 90, 4, 12, np.float32, "y"),
     (300, 48, 6, 32, np.float32, "xy"),
     (270, 100, 5, 14, np.float64, "xy"),
+    (700, 56, 5, 15, np.uint8, "xy"),       # radix-7 lengths both ways, 8-bit samples
+    (263, 40, 4, 16, np.float32, "xy"),     # prime width: Bluestein
 ]
 
 
@@ -82,7 +84,7 @@ def test_mixed_batch_matches_single_frame_calls_and_oracle(bm, torch):
 
 def test_workspace_chunking_gives_identical_results(bm, torch):
     big = bm.Demodulator(0, max_width=1024, max_height=1024, max_batch_pixels=4 << 20)
-    small = bm.Demodulator(0, max_width=600, max_height=120)   # one frame per group
+    small = bm.Demodulator(0, max_width=700, max_height=120)   # about one frame per group
     specs, _ = make_batch(bm, torch)
     bm.bosmusic_demodulate(big.h, specs)
     a = outputs(torch, specs)
