@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
 # certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
 # frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35602.0625 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35577.0 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
 
 
 def bairstow_flops(n: int) -> int:
@@ -50,11 +50,12 @@ def pair_newton_flops(n: int) -> int:
 
 def certificate_flops(L: int) -> int:
     """Inner member and mate of the root, division by the pair's factor with the remainder test,
-    scaling and the Schur-Cohn recursion on the degree 2L-4 quotient (FP64)."""
+    the closed-form first Schur-Cohn step on the degree 2L-4 quotient (powers of rho and the
+    scaling) and the recursion on the degree 2L-5 remainder of it (FP64)."""
     n = 2 * L - 2
     m = n - 2
-    schur = sum(20 * (d // 2) + 16 for d in range(1, m + 1))
-    return 40 + 18 * (n + 1) + 3 * m + schur
+    schur = sum(20 * (d // 2) + 16 for d in range(1, m))
+    return 40 + 18 * (n + 1) + 5 * m + schur
 
 
 def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,

@@ -598,16 +598,28 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     }
     // remainder b1 (z - r) + b0: here b2 = b_1 and b1 = b_0
     if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= kCertRemTol * (double)scale)) return false;
-    if (L == 2) return true;                          // no other roots
+    if constexpr (L == 2) {
+        return true;                                  // no other roots
+    } else {
+    // Q is self-inversive (P and the pair's factor are), q_{m-k} = conj(q_k) q_m / conj(q_0)
+    // with m = 2L - 4, so the first Schur-Cohn step on f(z) = Q(rho z) has the closed form
+    // T f = conj(q_0) sum_{k<m} q_k (rho^k - rho^{2m-k}) z^k, with a positive constant term:
+    // f and T f have equally many zeros inside the unit disk.
+    constexpr int m = n - 2;
     const double rho = rin * (1.0 - kCertMargin);
-    double rp = 1.0;
+    double pw[2 * m + 1];
+    pw[0] = 1.0;
 #pragma unroll
-    for (int k = 1; k <= n - 2; ++k) {
-        rp *= rho;
-        fr[k] *= rp;
-        fi[k] *= rp;
+    for (int k = 1; k <= 2 * m; ++k) pw[k] = pw[k - 1] * rho;
+    double gr[m], gi[m];
+#pragma unroll
+    for (int k = 0; k < m; ++k) {
+        const double w = pw[k] - pw[2 * m - k];
+        gr[k] = fr[k] * w;
+        gi[k] = fi[k] * w;
     }
-    return zeros_inside_unit_disk<n - 2>(fr, fi) == L - 2;
+    return zeros_inside_unit_disk<m - 1>(gr, gi) == L - 2;
+    }
 }
 
 // Direction of the frequency guess from the lag-1 coefficient: u1[i+1]/u1[i]
