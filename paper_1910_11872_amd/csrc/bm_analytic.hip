@@ -9,8 +9,10 @@
 // forward FFT applied to the conjugate.  Two real lines x_a, x_b share one
 // forward transform of z = x_a + i x_b: X_a[k] = (Z[k] + conj Z[n-k]) / 2 and
 // X_b[k] = (Z[k] - conj Z[n-k]) / 2i, so a pair costs three transforms
-// instead of four.  Twiddles come from a per-length table computed in FP64 on the
-// host and rounded once.  A length with a prime factor above 13 takes each DFT
+// instead of four.  Twiddles come from per-pass tables of each length,
+// contiguous in the butterfly index, computed in FP64 on the host and
+// rounded once; they are read through the caches (staging them in LDS cost
+// more in blocks per CU than it saved in latency).  A length with a prime factor above 13 takes each DFT
 // by Bluestein's identity jk = (j^2 + k^2 - (k-j)^2) / 2: with the chirp
 // w_j = e^{-i pi j^2 / n}, X_k = w_k sum_j (x_j w_j) conj(w_{k-j}), a linear
 // convolution done as a circular one of 5-smooth length m >= 2n - 1 (two
@@ -21,7 +23,7 @@ namespace bm {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kTile = 32;
+constexpr int kTrRows = 8;       // tile rows a block's threads cover per step
 
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -217,7 +219,7 @@ __device__ __forceinline__ float2 conjf2(float2 v) { return make_float2(v.x, -v.
 
 // One block per work item of any job: a pair of lines (lines 2i, 2i+1) when
 // the transform is short enough for three LDS buffers, else one line.
-template <int MAXR, bool TWL>
+template <int MAXR>
 __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int item0) {
     extern __shared__ float2 lds[];
     const int w = item0 + blockIdx.x;
@@ -232,11 +234,7 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
     float2* a = lds;
     float2* b = lds + m;
     float2* c = lds + 2 * m;            // pairs only
-    // twiddles: staged in LDS once per block (every pass reads them), or read from global memory
-    float2* twl = lds + (pairs ? 3 : 2) * m;
-    if (TWL)
-        for (int i = threadIdx.x; i < J.tw_len; i += kFftThreads) twl[i] = J.tw[i];
-    const float2* tw = TWL ? twl : J.tw;
+    const float2* tw = J.tw;
     const int64_t off = (int64_t)la * J.src_ls;
     for (int i = threadIdx.x; i < n; i += kFftThreads)
         a[i] = make_float2(load_real(J.src, off + i, elem), two ? load_real(J.src, off + J.src_ls + i, elem) : 0.f);
@@ -279,18 +277,21 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
     for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Yb[i]);
 }
 
-// One block per 32 x 32 tile of any job; real input -> float, C32 -> float2.
-__global__ __launch_bounds__(kTile * 8) void transpose_kernel(TrBatch B) {
-    __shared__ float2 tile[kTile][kTile + 1];
+// One block per kTrTile x kTrTile tile of any job (kTrTile x kTrRows threads,
+// kTrTile / kTrRows elements each, so each thread has that many independent
+// loads in flight); real input -> float, C32 -> float2.  The tile is padded by
+// one element per row so that the column reads hit distinct banks.
+__global__ __launch_bounds__(kTrTile * kTrRows) void transpose_kernel(TrBatch B) {
+    __shared__ float2 tile[kTrTile][kTrTile + 1];
     const int j = find_job(B.prefix, B.njobs, blockIdx.x);
     const TrJob& J = B.jobs[j];
     const int tid = blockIdx.x - B.prefix[j];
-    const int bx = (tid % J.tiles_x) * kTile, by = (tid / J.tiles_x) * kTile;
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+    const int bx = (tid % J.tiles_x) * kTrTile, by = (tid / J.tiles_x) * kTrTile;
+    const int tx = threadIdx.x % kTrTile, ty = threadIdx.x / kTrTile;
     const int rows = J.rows, cols = J.cols, elem = J.elem;
     const bool cplx = elem == (int)Elem::C32;
 #pragma unroll
-    for (int jj = 0; jj < kTile; jj += 8) {
+    for (int jj = 0; jj < kTrTile; jj += kTrRows) {
         const int r = by + ty + jj, c = bx + tx;
         if (r < rows && c < cols) {
             const int64_t idx = (int64_t)r * J.src_ls + c;
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kTile * 8) void transpose_kernel(TrBatch B) {
     }
     __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < kTile; jj += 8) {
+    for (int jj = 0; jj < kTrTile; jj += kTrRows) {
         const int c = bx + ty + jj, r = by + tx;
         if (r < rows && c < cols) {
             const int64_t idx = (int64_t)c * rows + r;
@@ -314,13 +315,9 @@ __global__ __launch_bounds__(kTile * 8) void transpose_kernel(TrBatch B) {
 
 hipError_t analytic_set_attributes() {
     const int bytes = kFftLdsElems * (int)sizeof(float2);
-    const void* k[kFftClasses] = {(const void*)analytic_kernel<5, true>, (const void*)analytic_kernel<5, false>,
-                                  (const void*)analytic_kernel<13, true>, (const void*)analytic_kernel<13, false>};
-    for (const void* f : k) {
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)analytic_kernel<5>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)analytic_kernel<13>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
@@ -328,19 +325,15 @@ hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
         const int i0 = b.cls_from[c], cnt = b.cls_from[c + 1] - i0;
         if (cnt <= 0) continue;
         const size_t shmem = (size_t)b.lds[c] * sizeof(float2);
-        switch (c) {
-            case 0: hipLaunchKernelGGL((analytic_kernel<5, true>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
-            case 1: hipLaunchKernelGGL((analytic_kernel<5, false>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
-            case 2: hipLaunchKernelGGL((analytic_kernel<13, true>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
-            default: hipLaunchKernelGGL((analytic_kernel<13, false>), dim3(cnt), dim3(kFftThreads), shmem, s, b, i0); break;
-        }
+        if (c == 0) hipLaunchKernelGGL(analytic_kernel<5>, dim3(cnt), dim3(kFftThreads), shmem, s, b, i0);
+        else hipLaunchKernelGGL(analytic_kernel<13>, dim3(cnt), dim3(kFftThreads), shmem, s, b, i0);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_transpose(const TrBatch& b, hipStream_t s) {
     if (b.total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(transpose_kernel, dim3(b.total), dim3(kTile * 8), 0, s, b);
+    hipLaunchKernelGGL(transpose_kernel, dim3(b.total), dim3(kTrTile * kTrRows), 0, s, b);
     return hipGetLastError();
 }
 

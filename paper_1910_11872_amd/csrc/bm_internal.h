@@ -86,8 +86,8 @@ struct FftJob {
     const void* src;       // real lines, src_ls elements apart
     int64_t src_ls;
     float2* dst;           // complex lines, n apart
-    const float2* tw;      // per-pass twiddle tables of plan.n, tw_len entries in all
-    int tw_len;
+    const float2* tw;      // per-pass twiddle tables of plan.n (read from global memory: cached,
+                           // and leaving LDS to more blocks measured faster than staging them)
     const float2* chirp;   // Bluestein only: e^{-i pi j^2 / n}, j < n
     const float2* kern;    // Bluestein only: DFT_m of the conjugate chirp, wrapped, divided by m
     int elem;              // Elem of src
@@ -97,19 +97,14 @@ struct FftJob {
 };
 
 // LDS of the analytic kernel's block, in complex elements (132 KiB): three
-// 4096-sample buffers and their twiddle tables, or two 8192-sample buffers.
+// 5632-sample buffers, or two 8192-sample buffers.
 constexpr int kFftLdsElems = 16896;
 
 // Transform lengths up to this take two real lines per block (one complex
-// forward DFT of x_a + i x_b, split by symmetry): three line buffers in LDS,
-// plus the twiddle table.
-constexpr int kFftPairMax = 4096;
+// forward DFT of x_a + i x_b, split by symmetry): three line buffers in LDS.
+constexpr int kFftPairMax = 5632;
 
 __host__ __device__ inline bool fft_pairs(int m) { return m <= kFftPairMax; }
-
-// The twiddle tables of the transform sit in LDS when they fit beside the line buffers
-// (the tables hold at most plan.n + 64 entries).
-__host__ __device__ inline bool fft_tw_lds(int m) { return (fft_pairs(m) ? 4 : 3) * m + 64 <= kFftLdsElems; }
 
 // Work items (blocks) of one job: line pairs or lines.
 inline int fft_items(const FftJob& j) { return fft_pairs(j.plan.n) ? (j.nlines + 1) / 2 : j.nlines; }
@@ -126,10 +121,7 @@ inline int fft_tw_len(const FftPlan& p) {
 }
 
 // LDS of one job's block, in complex elements.
-inline int fft_lds_elems(const FftJob& j) {
-    const int m = j.plan.n;
-    return (fft_pairs(m) ? 3 : 2) * m + (fft_tw_lds(m) ? fft_tw_len(j.plan) : 0);
-}
+inline int fft_lds_elems(const FftJob& j) { return (fft_pairs(j.plan.n) ? 3 : 2) * j.plan.n; }
 
 // True when the job's plan has a radix above 5.
 inline bool fft_big_radix(const FftJob& j) {
@@ -138,9 +130,9 @@ inline bool fft_big_radix(const FftJob& j) {
     return false;
 }
 
-// Kernel variant of a job: radices up to 5 or up to 13, twiddles in LDS or in global memory.
-constexpr int kFftClasses = 4;
-inline int fft_class(const FftJob& j) { return (fft_big_radix(j) ? 2 : 0) + (fft_tw_lds(j.plan.n) ? 0 : 1); }
+// Kernel variant of a job: radices up to 5, or up to 13.
+constexpr int kFftClasses = 2;
+inline int fft_class(const FftJob& j) { return fft_big_radix(j) ? 1 : 0; }
 
 // Jobs are ordered by class: items [cls_from[c], cls_from[c+1]) run in the
 // kernel variant of class c, with lds[c] complex elements of LDS per block.
@@ -154,12 +146,15 @@ struct FftBatch {
 };
 
 // Transpose of one frame (rows x cols, src_ls elements per row) to cols x rows.
+// Square tile of the batched transpose (elements per side).
+constexpr int kTrTile = 32;
+
 struct TrJob {
     const void* src;
     int64_t src_ls;
     void* dst;             // float (real input) or float2 (C32)
     int rows, cols;
-    int tiles_x;           // 32-wide tiles along cols
+    int tiles_x;           // kTrTile-wide tiles along cols
     int elem;
 };
 

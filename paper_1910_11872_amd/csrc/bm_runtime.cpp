@@ -245,17 +245,16 @@ void make_template(int L, bm::RootTemplate& t) {
 // radix R and stride Ns, e^{-2 pi i r k / (Ns R)} at (r - 1) Ns + k (0 < r < R,
 // k < Ns), then the butterfly constants e^{-2 pi i r / R} (0 < r < R); the
 // angle is reduced exactly (r k mod Ns R) and evaluated in FP64, rounded once.
-bm_status get_twiddles(bosmusic_s* h, int n, const float2** out, int* len) {
+bm_status get_twiddles(bosmusic_s* h, int n, const float2** out) {
     bm::FftPlan plan;
     if (!plan_fft(n, plan)) return fail(h, BM_E_UNSUPPORTED, "twiddles of %d", n);
-    *len = bm::fft_tw_len(plan);
     auto it = h->twiddles.find(n);
     if (it != h->twiddles.end()) {
         *out = it->second;
         return BM_OK;
     }
     std::vector<float2> tw;
-    tw.reserve(*len);
+    tw.reserve(bm::fft_tw_len(plan));
     auto put = [&](int64_t num, int64_t den) {
         const double a = -2.0 * M_PI * (double)(num % den) / (double)den;
         tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
@@ -319,10 +318,10 @@ bm_status get_bluestein(bosmusic_s* h, int n, int m, const float2** chirp, const
 bm_status make_fft_job(bosmusic_s* h, int n, bm::FftJob& fj) {
     fj.n = n;
     fj.chirp = fj.kern = nullptr;
-    if (plan_fft(n, fj.plan)) return get_twiddles(h, n, &fj.tw, &fj.tw_len);
+    if (plan_fft(n, fj.plan)) return get_twiddles(h, n, &fj.tw);
     const int m = bluestein_len(n);
     if (m == 0 || !plan_fft(m, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "line length %d", n);
-    bm_status st = get_twiddles(h, m, &fj.tw, &fj.tw_len);
+    bm_status st = get_twiddles(h, m, &fj.tw);
     if (st != BM_OK) return st;
     return get_bluestein(h, n, m, &fj.chirp, &fj.kern);
 }
@@ -504,7 +503,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             tj.src_ls = f.row_stride;
             tj.rows = H;
             tj.cols = W;
-            tj.tiles_x = (W + 31) / 32;
+            tj.tiles_x = (W + bm::kTrTile - 1) / bm::kTrTile;
             tj.elem = f.dtype;
             if (e == bm::Elem::C32) {
                 tj.dst = gy;
@@ -533,7 +532,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             bj.dst = f.omega_y;
             bj.rows = W;
             bj.cols = H;
-            bj.tiles_x = (H + 31) / 32;
+            bj.tiles_x = (H + bm::kTrTile - 1) / bm::kTrTile;
             bj.elem = BM_F32;
             gp.back.push_back(bj);
             bm::RmJob j{};
@@ -556,7 +555,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     }
     if (cur > h->ws_bytes) return fail(h, BM_E_INVALID_ARG, "group exceeds the workspace");
     gp.tr_prefix.assign(1, 0);
-    for (auto& t : gp.tr) gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
+    for (auto& t : gp.tr)
+        gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + bm::kTrTile - 1) / bm::kTrTile));
     // jobs ordered by kernel variant (radix range, twiddles in LDS or not): one launch per variant
     std::stable_sort(gp.fft.begin(), gp.fft.end(),
                      [](const bm::FftJob& x, const bm::FftJob& y) { return bm::fft_class(x) < bm::fft_class(y); });
@@ -572,7 +572,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     }
     while (cls < bm::kFftClasses) gp.fft_cls_from[++cls] = gp.fft_prefix.back();
     gp.back_prefix.assign(1, 0);
-    for (auto& t : gp.back) gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + 31) / 32));
+    for (auto& t : gp.back)
+        gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + bm::kTrTile - 1) / bm::kTrTile));
     for (auto& kv : sets) {
         RmSet s = kv.second;
         int nmax = 0;
