@@ -48,7 +48,9 @@ namespace {
 // its first, so each start costs about half the direct sum.  Blocks start at
 // even pixels, so which window starts are summed directly and which are slid
 // depends on the start alone, not on the tile size: results are the same for
-// every tiling.
+// every tiling.  (Four starts per lane halve the lag-sum work again but
+// double the lag sums a block keeps in LDS, which halves the blocks resident
+// per CU: twice slower on 1024-wide lines.)
 constexpr int kLineSpan = 2;
 
 constexpr int line_windows_per_block(int L, int block) { return (kLineSpan * block - (L - 1)) & ~1; }
@@ -244,8 +246,12 @@ __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long l
 // block (w - prefix[j]) of job j, i.e. line (w - prefix[j]) / bpl and window
 // block (w - prefix[j]) % bpl.  A grid of one block per item runs each item
 // once; a smaller (persistent) grid walks the list.
+// Without the statistics counters the L <= 6 line kernels fit five waves per SIMD
+// (96 VGPRs, a few spilled), 1.3% faster on L = 6 than the four that 119
+// VGPRs allow.
 template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN>
-__global__ __launch_bounds__(BLOCK) void rootmusic_kernel(RmBatch B) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(!STATS && !BLOCKWIN && L <= 6 ? 5 : 1)))
+void rootmusic_kernel(RmBatch B) {
     // line windows: staged signal + lag sums; block windows: the block's staged rows
     constexpr int ROW = BLOCKWIN ? BLOCK + L : LineSpan<L, BLOCK>::row;
     constexpr int WPB = BLOCKWIN ? BLOCK - (L - 1) : LineSpan<L, BLOCK>::wpb;

@@ -391,13 +391,17 @@ __device__ __forceinline__ bool bairstow(const float (&ar)[n + 1], const float (
         Tp C1r = 0, C1i = 0, C2r = 0, C2i = 0, C3r = 0, C3i = 0;
 #pragma unroll
         for (int k = n; k >= 0; --k) {
-            const Tp bkr = (Tp)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
-            const Tp bki = (Tp)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
+            const Tp tr = fma(s_r, b2r, fma(-s_i, b2i, (Tp)ar[k]));
+            const Tp ti = fma(s_r, b2i, fma(s_i, b2r, (Tp)ai[k]));
+            const Tp bkr = fma(rr, b1r, fma(-ri, b1i, tr));
+            const Tp bki = fma(rr, b1i, fma(ri, b1r, ti));
             if (k == 0) { B0r = bkr; B0i = bki; }
             if (k == 1) { B1r = bkr; B1i = bki; }
             if (k >= 1) {
-                const Tp ckr = bkr + (rr * c1r - ri * c1i) + (s_r * c2r - s_i * c2i);
-                const Tp cki = bki + (rr * c1i + ri * c1r) + (s_r * c2i + s_i * c2r);
+                const Tp ur = fma(s_r, c2r, fma(-s_i, c2i, bkr));
+                const Tp ui = fma(s_r, c2i, fma(s_i, c2r, bki));
+                const Tp ckr = fma(rr, c1r, fma(-ri, c1i, ur));
+                const Tp cki = fma(rr, c1i, fma(ri, c1r, ui));
                 if (k == 1) { C1r = ckr; C1i = cki; }
                 if (k == 2) { C2r = ckr; C2i = cki; }
                 if (k == 3) { C3r = ckr; C3i = cki; }
@@ -587,8 +591,11 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
 #pragma unroll
     for (int k = n; k >= 0; --k) {
-        const double bkr = (double)ar[k] + (rr * b1r - ri * b1i) + (s_r * b2r - s_i * b2i);
-        const double bki = (double)ai[k] + (rr * b1i + ri * b1r) + (s_r * b2i + s_i * b2r);
+        // the s b_{k+2} part first: only two dependent FMAs per step wait for b_{k+1}
+        const double tr = fma(s_r, b2r, fma(-s_i, b2i, (double)ar[k]));
+        const double ti = fma(s_r, b2i, fma(s_i, b2r, (double)ai[k]));
+        const double bkr = fma(rr, b1r, fma(-ri, b1i, tr));
+        const double bki = fma(rr, b1i, fma(ri, b1r, ti));
         scale += fabsf(ar[k]) + fabsf(ai[k]);
         if (k >= 2) {
             fr[k - 2] = bkr;
