@@ -124,6 +124,9 @@ __device__ __forceinline__ void block_cov(const float2 (*sR)[BLOCK + L], int t, 
     for (int i = 0; i < L; ++i)
 #pragma unroll
         for (int j = i; j < L; ++j) { R.re[i][j] = 0.f; R.im[i][j] = 0.f; }
+    // one snapshot at a time: unrolled, the loads of all L snapshots would be
+    // hoisted and held in registers
+#pragma unroll 1
     for (int k = 0; k < L; ++k) {
         float2 v[L];
 #pragma unroll
@@ -183,11 +186,15 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
             window_omega<L, JACOBI>(R, tmpl, full_roots, L, wy, fy, ls);
         }
         if (J.phase && finitef(wx) && finitef(wy)) {
+            // the hardware sine and cosine: arguments stay within |w| (L/2) <= 4 pi,
+            // where their error (~1e-6) is far below the phase tolerance, and the
+            // library's large-argument reduction would hold registers the whole
+            // kernel pays for (two waves per SIMD instead of three or four)
             float exr[L], exi[L];
 #pragma unroll
             for (int j = 0; j < L; ++j) {
                 float sn, cs;
-                sincosf(wx * (float)(j - h), &sn, &cs);
+                __sincosf(wx * (float)(j - h), &sn, &cs);
                 exr[j] = cs;
                 exi[j] = -sn;
             }
@@ -202,7 +209,7 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
                     ri = fmaf(v.x, exi[j], fmaf(v.y, exr[j], ri));
                 }
                 float sn, cs;
-                sincosf(wy * (float)(i - h), &sn, &cs);   // times e^{-j wy (i-h)}
+                __sincosf(wy * (float)(i - h), &sn, &cs);   // times e^{-j wy (i-h)}
                 ar = fmaf(rr, cs, fmaf(ri, sn, ar));
                 ai = fmaf(ri, cs, fmaf(-rr, sn, ai));
             }
