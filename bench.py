@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
 # certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
 # frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (35577.0 * 2.0 + 33280.0) * 1024 / (4 * 2 * 1024 * 1024)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (36701.0 * 2.0 + 66146.0) * 1024 / (4 * 2 * 1024 * 1024)
 
 
 def bairstow_flops(n: int) -> int:
