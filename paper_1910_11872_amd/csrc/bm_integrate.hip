@@ -16,22 +16,26 @@ namespace {
 
 constexpr int kAnchorThreads = 1024;
 constexpr int kRowThreads = 256;
+constexpr int kRowsPerBlock = 4;
 
-// Inclusive block scan (Hillis-Steele) of one double per thread.
+// Exclusive block scan of one double per thread: a shuffle scan within each
+// wave, then the totals of the waves before it.
 template <int T>
 __device__ double block_scan_exclusive(double v, double* sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        const double a = (t >= off) ? sh[t - off] : 0.0;
-        __syncthreads();
-        sh[t] += a;
-        __syncthreads();
+    static_assert(T % 64 == 0 && T <= 64 * 64, "whole waves");
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    double x = v;                                  // inclusive scan within the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    const double incl = sh[t];
+    if (lane == 63) sh[wv] = x;                    // wave totals
     __syncthreads();
-    return incl - v;
+    double base = 0.0;
+    for (int k = 0; k < wv; ++k) base += sh[k];
+    __syncthreads();                               // sh is free for the next scan
+    return base + x - v;
 }
 
 __global__ __launch_bounds__(kAnchorThreads) void anchor_kernel(const float* __restrict__ wy, int W, int xa, int y0,
@@ -113,49 +117,59 @@ __global__ __launch_bounds__(kAnchorThreads) void anchor_many_kernel(const IntJo
     if (t == 0) anchor[J.y0] = 0.0;
 }
 
+// kRowsPerBlock consecutive rows of the job list per block (one job lookup
+// for all of them).
 __global__ __launch_bounds__(kRowThreads) void rows_many_kernel(const IntJob* __restrict__ jobs,
                                                                 const int* __restrict__ prefix, int njobs,
-                                                                const double* __restrict__ anchors) {
+                                                                int total_rows, const double* __restrict__ anchors) {
     extern __shared__ double dyn[];
     __shared__ double sh[kRowThreads];
-    int lo = 0, hi = njobs - 1;              // job of this row: last j with prefix[j] <= blockIdx.x
+    const int w0 = blockIdx.x * kRowsPerBlock;
+    int lo = 0, hi = njobs - 1;              // job of row w0: last j with prefix[j] <= w0
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= (int)blockIdx.x) lo = mid;
+        if (prefix[mid] <= w0) lo = mid;
         else hi = mid - 1;
     }
-    const IntJob& J = jobs[lo];
-    const int W = J.W;
-    const int y = blockIdx.x - prefix[lo];
-    double* sp = dyn;                              // W doubles
-    float* sw = reinterpret_cast<float*>(dyn + W);  // W floats
-    double* out = J.phi + (int64_t)y * W;
+    int jb = lo;
     const double nan = __builtin_nan("");
-    if (y < J.y0 || y > J.y1 || J.x1 < J.x0) {
-        for (int x = threadIdx.x; x < W; x += kRowThreads) out[x] = nan;
-        return;
-    }
-    const float* row = J.wx + (int64_t)y * W;
-    for (int x = threadIdx.x; x < W; x += kRowThreads) sw[x] = row[x];
-    __syncthreads();
-    const int x0 = J.x0, nsteps = J.x1 - J.x0;
-    const int chunk = (nsteps + kRowThreads - 1) / kRowThreads;
-    const int t = threadIdx.x;
-    const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
-    double acc = 0.0;
-    for (int i = i0; i < i1; ++i) {
-        acc += 0.5 * ((double)sw[x0 + i] + (double)sw[x0 + i + 1]) - J.cx;
-        sp[x0 + i + 1] = acc;
-    }
-    const double off = block_scan_exclusive<kRowThreads>(acc, sh);
-    const double base = J.wy ? anchors[J.anchor_off + y] : 0.0;
-    for (int i = i0; i < i1; ++i) sp[x0 + i + 1] += off;
-    __syncthreads();
-    for (int x = threadIdx.x; x < W; x += kRowThreads) {
-        double v = nan;
-        if (x == x0) v = base;
-        else if (x > x0 && x <= J.x1) v = base + sp[x];
-        out[x] = v;
+    for (int q = 0; q < kRowsPerBlock; ++q) {
+        const int w = w0 + q;
+        if (w >= total_rows) break;
+        while (w >= prefix[jb + 1]) ++jb;        // the next (non-empty) job
+        const IntJob& J = jobs[jb];
+        const int W = J.W;
+        const int y = w - prefix[jb];
+        double* sp = dyn;                              // W doubles
+        float* sw = reinterpret_cast<float*>(dyn + W);  // W floats
+        double* out = J.phi + (int64_t)y * W;
+        if (y < J.y0 || y > J.y1 || J.x1 < J.x0) {
+            for (int x = threadIdx.x; x < W; x += kRowThreads) out[x] = nan;
+            continue;
+        }
+        __syncthreads();                         // the previous row is out of LDS
+        const float* row = J.wx + (int64_t)y * W;
+        for (int x = threadIdx.x; x < W; x += kRowThreads) sw[x] = row[x];
+        __syncthreads();
+        const int x0 = J.x0, nsteps = J.x1 - J.x0;
+        const int chunk = (nsteps + kRowThreads - 1) / kRowThreads;
+        const int t = threadIdx.x;
+        const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
+        double acc = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            acc += 0.5 * ((double)sw[x0 + i] + (double)sw[x0 + i + 1]) - J.cx;
+            sp[x0 + i + 1] = acc;
+        }
+        const double off = block_scan_exclusive<kRowThreads>(acc, sh);
+        const double base = J.wy ? anchors[J.anchor_off + y] : 0.0;
+        for (int i = i0; i < i1; ++i) sp[x0 + i + 1] += off;
+        __syncthreads();
+        for (int x = threadIdx.x; x < W; x += kRowThreads) {
+            double v = nan;
+            if (x == x0) v = base;
+            else if (x > x0 && x <= J.x1) v = base + sp[x];
+            out[x] = v;
+        }
     }
 }
 
@@ -168,8 +182,8 @@ hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njob
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t shmem = (size_t)max_w * (sizeof(double) + sizeof(float));
-    hipLaunchKernelGGL(rows_many_kernel, dim3(total_rows), dim3(kRowThreads), shmem, s, jobs, prefix, njobs,
-                       anchors);
+    hipLaunchKernelGGL(rows_many_kernel, dim3((total_rows + kRowsPerBlock - 1) / kRowsPerBlock), dim3(kRowThreads),
+                       shmem, s, jobs, prefix, njobs, total_rows, anchors);
     return hipGetLastError();
 }
 
