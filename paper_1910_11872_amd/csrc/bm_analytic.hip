@@ -1,7 +1,8 @@
 // Complex analytic fringe signal (paper Sec. 2, Eq. 1) by an exact DFT mask,
 // plus the tiled transposes that turn the y direction into lines.
 //
-// analytic_kernel: one block per line, or per pair of lines.  A line is
+// analytic_kernel: one block per pair of lines (transforms up to 2048
+// samples, 256 threads) or per line (longer ones, 1024 threads).  A line is
 // decoded to FP32, run through a mixed-radix (4, 2, 3, 5, 7, 11, 13) Stockham
 // FFT ping-ponged between LDS buffers, multiplied by the one-sided mask H
 // (H[0] = 0, H[k] = 2 for 0 < 2k < n, 0 otherwise, so DC and Nyquist are
@@ -22,7 +23,6 @@
 namespace bm {
 namespace {
 
-constexpr int kFftThreads = 256;
 constexpr int kTrRows = 8;       // tile rows a block's threads cover per step
 
 
@@ -39,7 +39,7 @@ __device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.
 // tw is the pass's own table: tw[(r-1) Ns + k] = e^{-2 pi i r k / (Ns R)} for
 // 0 < r < R, k < Ns (contiguous in k, so neighbouring lanes read neighbouring
 // entries), then tw[(R-1) Ns + r - 1] = e^{-2 pi i r / R}, the butterfly's own.
-template <int R>
+template <int R, int T>
 __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int n,
                                               int Ns, const float2* __restrict__ tw) {
     const int nR = n / R;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
             sn[r] = -w.y;
         }
     }
-    for (int j = threadIdx.x; j < nR; j += kFftThreads) {
+    for (int j = threadIdx.x; j < nR; j += T) {
         const int g = (int)(((float)j + 0.5f) * inv_ns);
         const int k = j - g * Ns;
         float2 v[R];
@@ -137,30 +137,30 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, fl
     }
 }
 
-template <int R>
+template <int R, int T>
 __device__ __forceinline__ void stockham_pass_odd(const float2* __restrict__ src, float2* __restrict__ dst, int n, int Ns,
                                                const float2* __restrict__ tw) {
-    stockham_pass<R>(src, dst, n, Ns, tw);
+    stockham_pass<R, T>(src, dst, n, Ns, tw);
 }
 
 // Forward DFT of the line held in `a` (scratch `b`); returns the buffer that
 // holds the result in natural order.  MAXR bounds the radices compiled in: the
 // radix-7/11/13 butterflies need several times the registers of the others,
 // so plans without them run in a kernel that does not carry them.
-template <int MAXR>
+template <int MAXR, int T>
 __device__ __forceinline__ float2* fft_forward(float2* a, float2* b, int n, const FftPlan& plan, const float2* tw) {
     int Ns = 1;
     for (int ps = 0; ps < plan.passes; ++ps) {
         const int R = plan.radix[ps];
         const float2* twp = tw;                 // this pass's table, then the next one's
         tw += (R - 1) * (Ns + 1);
-        if (R == 4) stockham_pass<4>(a, b, n, Ns, twp);
-        else if (R == 2) stockham_pass<2>(a, b, n, Ns, twp);
-        else if (R == 3) stockham_pass<3>(a, b, n, Ns, twp);
-        else if (MAXR <= 5 || R == 5) stockham_pass<5>(a, b, n, Ns, twp);
-        else if (R == 7) stockham_pass_odd<7>(a, b, n, Ns, twp);
-        else if (R == 11) stockham_pass_odd<11>(a, b, n, Ns, twp);
-        else stockham_pass_odd<13>(a, b, n, Ns, twp);
+        if (R == 4) stockham_pass<4, T>(a, b, n, Ns, twp);
+        else if (R == 2) stockham_pass<2, T>(a, b, n, Ns, twp);
+        else if (R == 3) stockham_pass<3, T>(a, b, n, Ns, twp);
+        else if (MAXR <= 5 || R == 5) stockham_pass<5, T>(a, b, n, Ns, twp);
+        else if (R == 7) stockham_pass_odd<7, T>(a, b, n, Ns, twp);
+        else if (R == 11) stockham_pass_odd<11, T>(a, b, n, Ns, twp);
+        else stockham_pass_odd<13, T>(a, b, n, Ns, twp);
         __syncthreads();
         float2* t = a;
         a = b;
@@ -173,23 +173,23 @@ __device__ __forceinline__ float2* fft_forward(float2* a, float2* b, int n, cons
 // DFT of the n samples at a[0..n): a direct mixed-radix FFT, or Bluestein's
 // chirp-z route through length plan.n = m.  a and b hold m elements each;
 // returns the buffer holding X[0..n) in natural order.
-template <int MAXR>
+template <int MAXR, int T>
 __device__ __forceinline__ float2* dft_line(float2* a, float2* b, const FftJob& J, const float2* tw) {
     const int n = J.n, m = J.plan.n;
-    if (!J.chirp) return fft_forward<MAXR>(a, b, n, J.plan, tw);
-    for (int i = threadIdx.x; i < m; i += kFftThreads)
+    if (!J.chirp) return fft_forward<MAXR, T>(a, b, n, J.plan, tw);
+    for (int i = threadIdx.x; i < m; i += T)
         a[i] = i < n ? cmul(a[i], J.chirp[i]) : make_float2(0.f, 0.f);
     __syncthreads();
-    float2* P = fft_forward<MAXR>(a, b, m, J.plan, tw);
+    float2* P = fft_forward<MAXR, T>(a, b, m, J.plan, tw);
     float2* Q = (P == a) ? b : a;
     // circular convolution with conj(w): inverse DFT as the conjugate of a forward one
-    for (int k = threadIdx.x; k < m; k += kFftThreads) {
+    for (int k = threadIdx.x; k < m; k += T) {
         const float2 v = cmul(P[k], J.kern[k]);
         P[k] = make_float2(v.x, -v.y);
     }
     __syncthreads();
-    float2* Y = fft_forward<MAXR>(P, Q, m, J.plan, tw);
-    for (int k = threadIdx.x; k < n; k += kFftThreads) {
+    float2* Y = fft_forward<MAXR, T>(P, Q, m, J.plan, tw);
+    for (int k = threadIdx.x; k < n; k += T) {
         const float2 v = Y[k];
         Y[k] = cmul(make_float2(v.x, -v.y), J.chirp[k]);
     }
@@ -219,8 +219,8 @@ __device__ __forceinline__ float2 conjf2(float2 v) { return make_float2(v.x, -v.
 
 // One block per work item of any job: a pair of lines (lines 2i, 2i+1) when
 // the transform is short enough for three LDS buffers, else one line.
-template <int MAXR>
-__global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int item0) {
+template <int MAXR, int T>
+__global__ __launch_bounds__(T) void analytic_kernel(FftBatch B, int item0) {
     extern __shared__ float2 lds[];
     const int w = item0 + blockIdx.x;
     const int j = find_job(B.prefix, B.njobs, w);
@@ -236,28 +236,28 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
     float2* c = lds + 2 * m;            // pairs only
     const float2* tw = J.tw;
     const int64_t off = (int64_t)la * J.src_ls;
-    for (int i = threadIdx.x; i < n; i += kFftThreads)
+    for (int i = threadIdx.x; i < n; i += T)
         a[i] = make_float2(load_real(J.src, off + i, elem), two ? load_real(J.src, off + J.src_ls + i, elem) : 0.f);
     __syncthreads();
-    float2* X = dft_line<MAXR>(a, b, J, tw);
+    float2* X = dft_line<MAXR, T>(a, b, J, tw);
     float2* other = (X == a) ? b : a;
     // one-sided mask and 1/n, then conjugate so that a forward DFT inverts
     const float sc = 2.0f / (float)n;
     if (!two) {
-        for (int k = threadIdx.x; k < n; k += kFftThreads) {
+        for (int k = threadIdx.x; k < n; k += T) {
             const float2 v = X[k];
             const bool keep = (k >= 1) && (2 * k < n);
             X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        float2* Y = dft_line<MAXR>(X, other, J, tw);
+        float2* Y = dft_line<MAXR, T>(X, other, J, tw);
         float2* out = J.dst + (int64_t)la * n;
-        for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Y[i]);
+        for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Y[i]);
         return;
     }
     // split the spectra of the two real lines, masked and conjugated, into `other` (a) and `c` (b)
     const float hs = 0.5f * sc;
-    for (int k = threadIdx.x; k < n; k += kFftThreads) {
+    for (int k = threadIdx.x; k < n; k += T) {
         float2 ma = make_float2(0.f, 0.f), mb = make_float2(0.f, 0.f);
         if ((k >= 1) && (2 * k < n)) {
             const float2 z = X[k], zn = X[n - k];
@@ -268,13 +268,13 @@ __global__ __launch_bounds__(kFftThreads) void analytic_kernel(FftBatch B, int i
         c[k] = mb;
     }
     __syncthreads();
-    float2* Ya = dft_line<MAXR>(other, X, J, tw);
+    float2* Ya = dft_line<MAXR, T>(other, X, J, tw);
     float2* spare = (Ya == other) ? X : other;
     float2* out = J.dst + (int64_t)la * n;
-    for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Ya[i]);
-    float2* Yb = dft_line<MAXR>(c, spare, J, tw);
+    for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Ya[i]);
+    float2* Yb = dft_line<MAXR, T>(c, spare, J, tw);
     out += n;
-    for (int i = threadIdx.x; i < n; i += kFftThreads) out[i] = conjf2(Yb[i]);
+    for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Yb[i]);
 }
 
 // One block per kTrTile x kTrTile tile of any job (kTrTile x kTrRows threads,
@@ -315,9 +315,13 @@ __global__ __launch_bounds__(kTrTile * kTrRows) void transpose_kernel(TrBatch B)
 
 hipError_t analytic_set_attributes() {
     const int bytes = kFftLdsElems * (int)sizeof(float2);
-    hipError_t e = hipFuncSetAttribute((const void*)analytic_kernel<5>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)analytic_kernel<13>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void* k[kFftClasses] = {(const void*)analytic_kernel<5, 256>, (const void*)analytic_kernel<13, 256>,
+                                  (const void*)analytic_kernel<5, 1024>, (const void*)analytic_kernel<13, 1024>};
+    for (const void* f : k) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
@@ -325,8 +329,12 @@ hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
         const int i0 = b.cls_from[c], cnt = b.cls_from[c + 1] - i0;
         if (cnt <= 0) continue;
         const size_t shmem = (size_t)b.lds[c] * sizeof(float2);
-        if (c == 0) hipLaunchKernelGGL(analytic_kernel<5>, dim3(cnt), dim3(kFftThreads), shmem, s, b, i0);
-        else hipLaunchKernelGGL(analytic_kernel<13>, dim3(cnt), dim3(kFftThreads), shmem, s, b, i0);
+        switch (c) {
+            case 0: hipLaunchKernelGGL((analytic_kernel<5, 256>), dim3(cnt), dim3(256), shmem, s, b, i0); break;
+            case 1: hipLaunchKernelGGL((analytic_kernel<13, 256>), dim3(cnt), dim3(256), shmem, s, b, i0); break;
+            case 2: hipLaunchKernelGGL((analytic_kernel<5, 1024>), dim3(cnt), dim3(1024), shmem, s, b, i0); break;
+            default: hipLaunchKernelGGL((analytic_kernel<13, 1024>), dim3(cnt), dim3(1024), shmem, s, b, i0); break;
+        }
     }
     return hipGetLastError();
 }

@@ -40,7 +40,7 @@ __device__ double block_scan_exclusive(double v, double* sh) {
 
 __global__ __launch_bounds__(kAnchorThreads) void anchor_kernel(const float* __restrict__ wy, int W, int xa, int y0,
                                                                 int y1, double cy, double* __restrict__ anchor) {
-    __shared__ double sh[kAnchorThreads];
+    __shared__ double sh[kAnchorThreads / 64];
     const int nsteps = y1 - y0;
     const int chunk = (nsteps + kAnchorThreads - 1) / kAnchorThreads;
     const int t = threadIdx.x;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const float* __restri
                                                            int y0, int y1, double cx, const double* __restrict__ anchor,
                                                            double* __restrict__ phi) {
     extern __shared__ double dyn[];
-    __shared__ double sh[kRowThreads];
+    __shared__ double sh[kRowThreads / 64];
     double* sp = dyn;                              // W doubles
     float* sw = reinterpret_cast<float*>(dyn + W);  // W floats
     const int y = blockIdx.x;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const float* __restri
 // Batched forms: job j = blockIdx.x for the anchors; rows of all jobs in one grid.
 __global__ __launch_bounds__(kAnchorThreads) void anchor_many_kernel(const IntJob* __restrict__ jobs, int njobs,
                                                                      double* __restrict__ anchors) {
-    __shared__ double sh[kAnchorThreads];
+    __shared__ double sh[kAnchorThreads / 64];
     const IntJob& J = jobs[blockIdx.x];
     if (!J.wy || J.y1 < J.y0 || J.x1 < J.x0) return;
     double* anchor = anchors + J.anchor_off;
@@ -118,12 +118,12 @@ __global__ __launch_bounds__(kAnchorThreads) void anchor_many_kernel(const IntJo
 }
 
 // kRowsPerBlock consecutive rows of the job list per block (one job lookup
-// for all of them).
-__global__ __launch_bounds__(kRowThreads) void rows_many_kernel(const IntJob* __restrict__ jobs,
-                                                                const int* __restrict__ prefix, int njobs,
-                                                                int total_rows, const double* __restrict__ anchors) {
+// for all of them), T threads per row.
+template <int T>
+__global__ __launch_bounds__(T) void rows_many_kernel(const IntJob* __restrict__ jobs, const int* __restrict__ prefix,
+                                                      int njobs, int total_rows, const double* __restrict__ anchors) {
     extern __shared__ double dyn[];
-    __shared__ double sh[kRowThreads];
+    __shared__ double sh[T / 64];
     const int w0 = blockIdx.x * kRowsPerBlock;
     int lo = 0, hi = njobs - 1;              // job of row w0: last j with prefix[j] <= w0
     while (lo < hi) {
@@ -144,15 +144,15 @@ __global__ __launch_bounds__(kRowThreads) void rows_many_kernel(const IntJob* __
         float* sw = reinterpret_cast<float*>(dyn + W);  // W floats
         double* out = J.phi + (int64_t)y * W;
         if (y < J.y0 || y > J.y1 || J.x1 < J.x0) {
-            for (int x = threadIdx.x; x < W; x += kRowThreads) out[x] = nan;
+            for (int x = threadIdx.x; x < W; x += T) out[x] = nan;
             continue;
         }
         __syncthreads();                         // the previous row is out of LDS
         const float* row = J.wx + (int64_t)y * W;
-        for (int x = threadIdx.x; x < W; x += kRowThreads) sw[x] = row[x];
+        for (int x = threadIdx.x; x < W; x += T) sw[x] = row[x];
         __syncthreads();
         const int x0 = J.x0, nsteps = J.x1 - J.x0;
-        const int chunk = (nsteps + kRowThreads - 1) / kRowThreads;
+        const int chunk = (nsteps + T - 1) / T;
         const int t = threadIdx.x;
         const int i0 = t * chunk, i1 = min(nsteps, i0 + chunk);
         double acc = 0.0;
@@ -160,11 +160,11 @@ __global__ __launch_bounds__(kRowThreads) void rows_many_kernel(const IntJob* __
             acc += 0.5 * ((double)sw[x0 + i] + (double)sw[x0 + i + 1]) - J.cx;
             sp[x0 + i + 1] = acc;
         }
-        const double off = block_scan_exclusive<kRowThreads>(acc, sh);
+        const double off = block_scan_exclusive<T>(acc, sh);
         const double base = J.wy ? anchors[J.anchor_off + y] : 0.0;
         for (int i = i0; i < i1; ++i) sp[x0 + i + 1] += off;
         __syncthreads();
-        for (int x = threadIdx.x; x < W; x += kRowThreads) {
+        for (int x = threadIdx.x; x < W; x += T) {
             double v = nan;
             if (x == x0) v = base;
             else if (x > x0 && x <= J.x1) v = base + sp[x];
@@ -182,8 +182,12 @@ hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njob
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t shmem = (size_t)max_w * (sizeof(double) + sizeof(float));
-    hipLaunchKernelGGL(rows_many_kernel, dim3((total_rows + kRowsPerBlock - 1) / kRowsPerBlock), dim3(kRowThreads),
-                       shmem, s, jobs, prefix, njobs, total_rows, anchors);
+    const dim3 grid((total_rows + kRowsPerBlock - 1) / kRowsPerBlock);
+    if (max_w > 2048)          // wide rows: more waves per block, four samples per thread at 4096
+        hipLaunchKernelGGL(rows_many_kernel<1024>, grid, dim3(1024), shmem, s, jobs, prefix, njobs, total_rows, anchors);
+    else
+        hipLaunchKernelGGL(rows_many_kernel<kRowThreads>, grid, dim3(kRowThreads), shmem, s, jobs, prefix, njobs,
+                           total_rows, anchors);
     return hipGetLastError();
 }
 
@@ -211,7 +215,10 @@ hipError_t integrate_set_attributes() {
     hipError_t e = hipFuncSetAttribute((const void*)rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kMaxFFT * (int)(sizeof(double) + sizeof(float)));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)rows_many_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)rows_many_kernel<kRowThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kMaxFFT * (int)(sizeof(double) + sizeof(float)));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)rows_many_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                kMaxFFT * (int)(sizeof(double) + sizeof(float)));
 }
 

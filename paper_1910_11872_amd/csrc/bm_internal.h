@@ -102,7 +102,14 @@ constexpr int kFftLdsElems = 16896;
 
 // Transform lengths up to this take two real lines per block (one complex
 // forward DFT of x_a + i x_b, split by symmetry): three line buffers in LDS.
-constexpr int kFftPairMax = 5632;
+// Longer ones take one line per block: two buffers, so that two blocks fit
+// in a CU's LDS (pairs of 4096-sample lines, one block per CU, were 1.3x
+// slower than single lines).
+constexpr int kFftPairMax = 2048;
+
+// Transform lengths above this run 1024 threads per block (one radix-4
+// butterfly per thread and pass at 4096), shorter ones 256.
+constexpr int kFftWideMin = 2049;
 
 __host__ __device__ inline bool fft_pairs(int m) { return m <= kFftPairMax; }
 
@@ -130,9 +137,9 @@ inline bool fft_big_radix(const FftJob& j) {
     return false;
 }
 
-// Kernel variant of a job: radices up to 5, or up to 13.
-constexpr int kFftClasses = 2;
-inline int fft_class(const FftJob& j) { return fft_big_radix(j) ? 1 : 0; }
+// Kernel variant of a job: radices up to 5, or up to 13; 256 or 1024 threads.
+constexpr int kFftClasses = 4;
+inline int fft_class(const FftJob& j) { return (fft_big_radix(j) ? 1 : 0) + (j.plan.n >= kFftWideMin ? 2 : 0); }
 
 // Jobs are ordered by class: items [cls_from[c], cls_from[c+1]) run in the
 // kernel variant of class c, with lds[c] complex elements of LDS per block.
