@@ -256,10 +256,12 @@ __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long l
 // Without the statistics counters the L <= 6 line kernels fit five waves per
 // SIMD (96 VGPRs, a few spilled), 1.3% faster on L = 6 than the four that 119
 // VGPRs allow, and the L = 7, 8 ones four (128 VGPRs; L = 8 spills seven and
-// runs 3% faster than at the three waves of its 151).
+// runs 3% faster than at the three waves of its 151).  The block-window
+// kernels run four too (L = 7: 143 -> 128 VGPRs with no spill, 11% faster;
+// L = 8: 160 -> 128 with 14 spilled, 8% faster).
 template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN>
 __global__ __launch_bounds__(BLOCK)
-__attribute__((amdgpu_waves_per_eu(!STATS && !BLOCKWIN ? (L <= 6 ? 5 : 4) : 1)))
+__attribute__((amdgpu_waves_per_eu(!STATS ? (BLOCKWIN ? 4 : (L <= 6 ? 5 : 4)) : 1)))
 void rootmusic_kernel(RmBatch B) {
     // line windows: staged signal + lag sums; block windows: the block's staged rows
     constexpr int ROW = BLOCKWIN ? BLOCK + L : LineSpan<L, BLOCK>::row;
