@@ -23,7 +23,7 @@
 namespace bm {
 namespace {
 
-constexpr int kTrRows = 8;       // tile rows a block's threads cover per step
+constexpr int kTrThreads = 256;
 
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -277,37 +277,49 @@ __global__ __launch_bounds__(T) void analytic_kernel(FftBatch B, int item0) {
     for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Yb[i]);
 }
 
-// One block per kTrTile x kTrTile tile of any job (kTrTile x kTrRows threads,
-// kTrTile / kTrRows elements each, so each thread has that many independent
-// loads in flight); real input -> float, C32 -> float2.  The tile is padded by
-// one element per row so that the column reads hit distinct banks.
-__global__ __launch_bounds__(kTrTile * kTrRows) void transpose_kernel(TrBatch B) {
-    __shared__ float2 tile[kTrTile][kTrTile + 1];
+// One block of 256 threads per tile of any job: 64 x 64 for real input
+// (decoded to FP32, 16 elements per thread) and 32 x 32 float2 for C32 input
+// (4 per thread), both in the same LDS words.  Tiles are padded by one
+// element per row so that the column reads hit distinct banks.  (32 x 32
+// float2 tiles for real data too were 1.45x slower on the 1024^2 frames.)
+__global__ __launch_bounds__(kTrThreads) void transpose_kernel(TrBatch B) {
+    __shared__ __align__(16) float smem[kTrTile * (kTrTile + 1)];
     const int j = find_job(B.prefix, B.njobs, blockIdx.x);
     const TrJob& J = B.jobs[j];
     const int tid = blockIdx.x - B.prefix[j];
-    const int bx = (tid % J.tiles_x) * kTrTile, by = (tid / J.tiles_x) * kTrTile;
-    const int tx = threadIdx.x % kTrTile, ty = threadIdx.x / kTrTile;
     const int rows = J.rows, cols = J.cols, elem = J.elem;
-    const bool cplx = elem == (int)Elem::C32;
+    if (elem == (int)Elem::C32) {
+        constexpr int T = kTrTileC, S = kTrThreads / kTrTileC;
+        float2 (*tile)[T + 1] = reinterpret_cast<float2 (*)[T + 1]>(smem);
+        const int bx = (tid % J.tiles_x) * T, by = (tid / J.tiles_x) * T;
+        const int tx = threadIdx.x % T, ty = threadIdx.x / T;
 #pragma unroll
-    for (int jj = 0; jj < kTrTile; jj += kTrRows) {
-        const int r = by + ty + jj, c = bx + tx;
-        if (r < rows && c < cols) {
-            const int64_t idx = (int64_t)r * J.src_ls + c;
-            tile[ty + jj][tx] = cplx ? static_cast<const float2*>(J.src)[idx]
-                                     : make_float2(load_real(J.src, idx, elem), 0.f);
+        for (int jj = 0; jj < T; jj += S) {
+            const int r = by + ty + jj, c = bx + tx;
+            if (r < rows && c < cols) tile[ty + jj][tx] = static_cast<const float2*>(J.src)[(int64_t)r * J.src_ls + c];
         }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < T; jj += S) {
+            const int c = bx + ty + jj, r = by + tx;
+            if (r < rows && c < cols) static_cast<float2*>(J.dst)[(int64_t)c * rows + r] = tile[tx][ty + jj];
+        }
+        return;
+    }
+    constexpr int T = kTrTile, S = kTrThreads / kTrTile;
+    float (*tile)[T + 1] = reinterpret_cast<float (*)[T + 1]>(smem);
+    const int bx = (tid % J.tiles_x) * T, by = (tid / J.tiles_x) * T;
+    const int tx = threadIdx.x % T, ty = threadIdx.x / T;
+#pragma unroll
+    for (int jj = 0; jj < T; jj += S) {
+        const int r = by + ty + jj, c = bx + tx;
+        if (r < rows && c < cols) tile[ty + jj][tx] = load_real(J.src, (int64_t)r * J.src_ls + c, elem);
     }
     __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < kTrTile; jj += kTrRows) {
+    for (int jj = 0; jj < T; jj += S) {
         const int c = bx + ty + jj, r = by + tx;
-        if (r < rows && c < cols) {
-            const int64_t idx = (int64_t)c * rows + r;
-            if (cplx) static_cast<float2*>(J.dst)[idx] = tile[tx][ty + jj];
-            else static_cast<float*>(J.dst)[idx] = tile[tx][ty + jj].x;
-        }
+        if (r < rows && c < cols) static_cast<float*>(J.dst)[(int64_t)c * rows + r] = tile[tx][ty + jj];
     }
 }
 
@@ -341,7 +353,7 @@ hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
 
 hipError_t launch_transpose(const TrBatch& b, hipStream_t s) {
     if (b.total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(transpose_kernel, dim3(b.total), dim3(kTrTile * kTrRows), 0, s, b);
+    hipLaunchKernelGGL(transpose_kernel, dim3(b.total), dim3(kTrThreads), 0, s, b);
     return hipGetLastError();
 }
 

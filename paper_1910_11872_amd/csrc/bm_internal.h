@@ -154,16 +154,20 @@ struct FftBatch {
 
 // Transpose of one frame (rows x cols, src_ls elements per row) to cols x rows.
 // Square tile of the batched transpose (elements per side).
-constexpr int kTrTile = 32;
+constexpr int kTrTile = 64;       // real elements: 64 x 64 FP32 tiles
+constexpr int kTrTileC = 32;      // complex (C32) elements: 32 x 32 tiles of float2
 
 struct TrJob {
     const void* src;
     int64_t src_ls;
     void* dst;             // float (real input) or float2 (C32)
     int rows, cols;
-    int tiles_x;           // kTrTile-wide tiles along cols
+    int tiles_x;           // tr_tile()-wide tiles along cols
     int elem;
 };
+
+// Tile side of a transpose job: float2 tiles of complex elements are half as wide.
+inline int tr_tile(const TrJob& j) { return j.elem == (int)Elem::C32 ? kTrTileC : kTrTile; }
 
 struct TrBatch {
     const TrJob* jobs;

@@ -503,8 +503,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             tj.src_ls = f.row_stride;
             tj.rows = H;
             tj.cols = W;
-            tj.tiles_x = (W + bm::kTrTile - 1) / bm::kTrTile;
             tj.elem = f.dtype;
+            tj.tiles_x = (W + bm::tr_tile(tj) - 1) / bm::tr_tile(tj);
             if (e == bm::Elem::C32) {
                 tj.dst = gy;
             } else {
@@ -532,8 +532,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             bj.dst = f.omega_y;
             bj.rows = W;
             bj.cols = H;
-            bj.tiles_x = (H + bm::kTrTile - 1) / bm::kTrTile;
             bj.elem = BM_F32;
+            bj.tiles_x = (H + bm::tr_tile(bj) - 1) / bm::tr_tile(bj);
             gp.back.push_back(bj);
             bm::RmJob j{};
             j.gamma = gy;
@@ -556,7 +556,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     if (cur > h->ws_bytes) return fail(h, BM_E_INVALID_ARG, "group exceeds the workspace");
     gp.tr_prefix.assign(1, 0);
     for (auto& t : gp.tr)
-        gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + bm::kTrTile - 1) / bm::kTrTile));
+        gp.tr_prefix.push_back(gp.tr_prefix.back() + t.tiles_x * ((t.rows + bm::tr_tile(t) - 1) / bm::tr_tile(t)));
     // jobs ordered by kernel variant (radix range, twiddles in LDS or not): one launch per variant
     std::stable_sort(gp.fft.begin(), gp.fft.end(),
                      [](const bm::FftJob& x, const bm::FftJob& y) { return bm::fft_class(x) < bm::fft_class(y); });
@@ -573,7 +573,7 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
     while (cls < bm::kFftClasses) gp.fft_cls_from[++cls] = gp.fft_prefix.back();
     gp.back_prefix.assign(1, 0);
     for (auto& t : gp.back)
-        gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + bm::kTrTile - 1) / bm::kTrTile));
+        gp.back_prefix.push_back(gp.back_prefix.back() + t.tiles_x * ((t.rows + bm::tr_tile(t) - 1) / bm::tr_tile(t)));
     for (auto& kv : sets) {
         RmSet s = kv.second;
         int nmax = 0;
