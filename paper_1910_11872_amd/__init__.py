@@ -201,8 +201,23 @@ def bosmusic_demodulate(h, frames, mode: int = BM_PLAIN, stream=None) -> None:
     _check(lib().bosmusic_demodulate(h, arr, len(frames), mode, _stream_ptr(stream)), h)
 
 
+def _map_check(omega_x, omega_y, phi) -> None:
+    """The C ABI reads and writes the maps row-major with row stride = width: refuse
+    tensors laid out otherwise (a transposed view would be read in the wrong order)."""
+    import torch
+    H, W = omega_x.shape
+    for t, name, dt in ((omega_x, "omega_x", torch.float32), (omega_y, "omega_y", torch.float32),
+                        (phi, "phi", torch.float64)):
+        if t is None:
+            continue
+        if tuple(t.shape) != (H, W) or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous {dt} tensor of shape {(H, W)}, "
+                             f"got {t.dtype} {tuple(t.shape)} strides {t.stride()}")
+
+
 def bosmusic_integrate(h, omega_x, omega_y, Nx: int, Ny: int, carrier_x: float, carrier_y: float, phi,
                        stream=None) -> None:
+    _map_check(omega_x, omega_y, phi)
     H, W = omega_x.shape
     wy = c_void_p(omega_y.data_ptr()) if omega_y is not None else c_void_p()
     _check(lib().bosmusic_integrate(h, c_void_p(omega_x.data_ptr()), wy, W, H, Nx, Ny, carrier_x, carrier_y,
@@ -266,6 +281,7 @@ def bosmusic_integrate_many(h, maps, stream=None) -> None:
     items = list(maps)
     arr = (bosmusic_integrate_job * max(1, len(items)))()
     for i, (wx, wy, nx, ny, cx, cy, phi) in enumerate(items):
+        _map_check(wx, wy, phi)
         H, W = wx.shape
         arr[i] = bosmusic_integrate_job(c_void_p(wx.data_ptr()), c_void_p(wy.data_ptr() if wy is not None else None),
                                         W, H, nx, ny, cx, cy, c_void_p(phi.data_ptr()))

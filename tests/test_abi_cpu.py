@@ -122,3 +122,19 @@ def test_binding_has_no_cpu_fallback():
     src = open(os.path.join(ROOT, "paper_1910_11872_amd", "__init__.py")).read()
     assert "oracle" not in src
     assert "raise ImportError" in src
+
+
+def test_integrate_refuses_maps_not_row_major():
+    """The binding checks layout before any library call: a transposed omega_y view
+    (as numpy hands out for column-wise results) would otherwise be read in the wrong order."""
+    import torch
+    import paper_1910_11872_amd as pkg
+    wx = torch.zeros(6, 5)
+    wy_t = torch.zeros(5, 6).t()                     # shape (6, 5), column-major
+    phi = torch.zeros(6, 5, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        pkg.bosmusic_integrate(None, wx, wy_t, 2, 2, 0.0, 0.0, phi)
+    with pytest.raises(ValueError):
+        pkg.bosmusic_integrate_many(None, [(wx, wy_t, 2, 2, 0.0, 0.0, phi)])
+    with pytest.raises(ValueError):
+        pkg.bosmusic_integrate(None, wx, None, 2, 0, 0.0, 0.0, torch.zeros(6, 5))   # phi must be FP64
