@@ -120,3 +120,46 @@ def test_quantized_forward_close_to_exact():
     yq = S.forward(p, X)["Y"]
     ye = S.forward(p, X, quantize=False)["Y"]
     assert np.max(np.abs(yq - ye)) < 0.05 * max(1.0, np.max(np.abs(ye)))
+
+
+def test_gelu_values_fixed_by_the_normal_cdf():
+    """GELU(x) = x * Phi(x) with Phi the standard normal CDF.  Phi is taken here from
+    tabulated values and, independently, by quadrature of the normal density; this
+    fixes the 1/sqrt(2) inside erf and rules out the tanh approximation (which is off
+    by ~1e-4 at x = 1 and by ~1.6e-4 at x = -1.5)."""
+    from scipy.integrate import quad
+    table = {1.0: 0.8413447460685429, -1.0: 0.15865525393145707, 2.0: 0.9772498680518208,
+             -1.5: 0.06680720126885807, 0.5: 0.6914624612740131}
+    dens = lambda t: math.exp(-0.5 * t * t) / math.sqrt(2.0 * math.pi)
+    for x, phi in table.items():
+        cdf = 0.5 + quad(dens, 0.0, x, epsabs=1e-15, epsrel=1e-15)[0]
+        assert abs(cdf - phi) < 1e-13
+        assert abs(float(S.gelu(np.float64(x))) - x * phi) < 1e-13, x
+        # d/dx [x Phi(x)] = Phi(x) + x phi(x)
+        assert abs(float(S.gelu_grad(np.float64(x))) - (phi + x * dens(x))) < 1e-13, x
+    tanh_form = lambda x: 0.5 * x * (1 + math.tanh(math.sqrt(2 / math.pi) * (x + 0.044715 * x ** 3)))
+    assert abs(tanh_form(-1.5) - float(S.gelu(np.float64(-1.5)))) > 1e-4
+
+
+def test_features_fix_the_span_and_the_derotation_sample():
+    """A tone plus an impulse on the window's centre sample N/2: the impulse must land on
+    feature 8 (the 16-sample span is samples N/2-8 .. N/2+7), and the de-rotation must use
+    the phase of that centre sample (every feature of the tone part then has the phase
+    w (n - N/2)).  Values written out by hand for N = 32, w = 0.3, impulse 3 e^{j w 16}."""
+    N, w = 32, 0.3
+    n = np.arange(N)
+    win = np.exp(1j * w * n)
+    win[16] += 3.0 * np.exp(1j * w * 16)              # centre sample: 4 e^{j w 16}
+    rms = math.sqrt((31.0 + 16.0) / 32.0)
+    f = S.features(win[None])[0]
+    expect = np.empty(16, complex)
+    for k in range(16):
+        expect[k] = np.exp(1j * w * (k - 8)) / rms
+    expect[8] = 4.0 / rms
+    assert np.allclose(f[:16], expect.real, atol=1e-12)
+    assert np.allclose(f[16:], expect.imag, atol=1e-12)
+    # shifting the impulse by one sample moves it to feature 9 and changes the rotation
+    win2 = np.exp(1j * w * n)
+    win2[17] += 3.0 * np.exp(1j * w * 17)
+    f2 = S.features(win2[None])[0]
+    assert abs(f2[9] - 4.0 / rms * math.cos(w)) < 1e-12 and abs(f2[8] - 1.0 / rms) < 1e-12
