@@ -16,6 +16,8 @@ from .rootmusic import (  # noqa: F401
     covariance,
     fb_average,
     noise_projector,
+    degenerate,
+    DEGENERATE_REL,
     poly_coeffs,
     poly_roots,
     select_root_pair,

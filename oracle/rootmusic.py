@@ -64,11 +64,21 @@ Readings of points the paper leaves open (each also listed in the design notes):
   R9  Block phase: Eq. 15's alpha = angle(mean(Gamma_w e^{-j(omega_x x +
       omega_y y)})) with (x, y) measured from the pixel, i.e. the wrapped
       phase of the block's linear model at the pixel.
+  R10 The split of Eq. 6-11 into a one-dimensional signal subspace and the
+      noise subspace needs a largest eigenvalue that stands apart: when
+      lambda_1 <= lambda_2 (1 + DEGENERATE_REL) the signal eigenvector is not
+      determined (any unit vector of a two-dimensional eigenspace qualifies,
+      e.g. for two tones of equal power), and omega is NaN.  The bound,
+      1e-5, sits above the resolution of eigenvalues computed in FP32 (a few
+      1e-7 of the trace) so that the GPU's decision agrees with this one.
 """
 from __future__ import annotations
 
 import numpy as np
 from numpy.lib.stride_tricks import sliding_window_view
+
+# R10: relative gap below which the signal subspace counts as undetermined
+DEGENERATE_REL = 1e-5
 
 
 # ---------------------------------------------------------------------------
@@ -136,6 +146,12 @@ def noise_projector(R: np.ndarray):
     Un = V[..., :, :-1]
     C = Un @ np.swapaxes(Un.conj(), -1, -2)
     return C, lam
+
+
+def degenerate(lam: np.ndarray) -> np.ndarray:
+    """True where the two largest eigenvalues (ascending lam) are too close for
+    a one-dimensional signal subspace (Eq. 6-11; reading R10)."""
+    return lam[..., -1] <= lam[..., -2] * (1.0 + DEGENERATE_REL)
 
 
 def poly_coeffs(C: np.ndarray) -> np.ndarray:
@@ -220,7 +236,8 @@ def select_root_pair(roots: np.ndarray):
 def demod_windows(win: np.ndarray, L: int, fb: bool = True, details: bool = False):
     """Steps a3..a8 for a batch of windows (M, N) complex -> omega (M,).
 
-    Windows whose covariance is identically zero or non-finite give NaN (R7).
+    Windows whose covariance is identically zero or non-finite give NaN (R7),
+    and so do windows whose signal subspace is not determined (R10).
     """
     win = np.asarray(win, dtype=np.complex128)
     M = win.shape[0]
@@ -236,9 +253,10 @@ def demod_windows(win: np.ndarray, L: int, fb: bool = True, details: bool = Fals
         coef = poly_coeffs(C)
         rts = poly_roots(coef)
         sel = select_root_pair(rts)
-        omega[ok] = sel["omega"]
+        deg = degenerate(lam)
+        omega[ok] = np.where(deg, np.nan, sel["omega"])
         if details:
-            info.update(R=R, C=C, lam=lam, coef=coef, roots=rts, **sel)
+            info.update(R=R, C=C, lam=lam, coef=coef, roots=rts, degenerate=deg, **sel)
     if details:
         return omega, info
     return omega
@@ -301,15 +319,17 @@ def block_covariances(gamma: np.ndarray, M: int):
 
 
 def _omega_from_cov(R: np.ndarray, fb: bool) -> np.ndarray:
-    """Steps a4..a8 for covariances (n, M, M): pair-form angle, NaN if degenerate."""
+    """Steps a4..a8 for covariances (n, M, M): pair-form angle, NaN where R is zero or
+    not finite (R7) or the signal subspace is not determined (R10)."""
     if fb:
         R = fb_average(R)
     tr = np.real(np.trace(R, axis1=-2, axis2=-1))
     ok = np.isfinite(tr) & (tr > 0)
     out = np.full(R.shape[0], np.nan)
     if np.any(ok):
-        C, _ = noise_projector(R[ok])
-        out[ok] = select_root_pair(poly_roots(poly_coeffs(C)))["omega"]
+        C, lam = noise_projector(R[ok])
+        w = select_root_pair(poly_roots(poly_coeffs(C)))["omega"]
+        out[ok] = np.where(degenerate(lam), np.nan, w)
     return out
 
 

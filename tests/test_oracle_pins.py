@@ -388,3 +388,36 @@ def test_erf_phase_derivative_agreement():
     rows = slice(48, H - 48)
     err = np.abs(wy[rows, 20] - truth[rows])
     assert np.nanmax(err) < 3e-3
+
+
+def two_tone_windows(L, ratio, w1=0.4):
+    """Windows of two complex tones whose steering vectors are orthogonal over L samples
+    (frequency spacing 2 pi / L) and whose cross terms cancel over the K = 4L sub-snapshots
+    (K a multiple of L), so that R = P1 a1 a1^H + P2 a2 a2^H exactly, with eigenvalues
+    L P1, L P2 and 0 (Eq. 8 for two sources), and FB averaging leaves it unchanged."""
+    N = 5 * L - 1
+    n = np.arange(N)
+    w2 = w1 + 2 * np.pi / L
+    win = np.sqrt(ratio) * np.exp(1j * (w1 * n + 0.3)) + np.exp(1j * (w2 * n - 1.1))
+    return win[None], w1
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 8])
+def test_degenerate_signal_subspace_of_two_equal_tones(L):
+    """Two tones of equal power: lambda_1 = lambda_2 = L, the one-dimensional signal
+    subspace of Eq. 6-11 is not determined, omega is NaN (reading R10).  A power ratio of
+    1.001 separates them and the stronger tone's frequency comes out exactly (its steering
+    vector is then the top eigenvector); a ratio inside the bound is still degenerate."""
+    win, w1 = two_tone_windows(L, 1.0)
+    om, info = oracle.demod_windows(win, L, details=True)
+    lam = info["lam"][0]
+    assert np.allclose(lam[-2:], [L, L], rtol=0, atol=1e-10) and np.all(np.abs(lam[:-2]) < 1e-10)
+    assert info["degenerate"][0] and np.isnan(om[0])
+    win, w1 = two_tone_windows(L, 1.001)
+    om, info = oracle.demod_windows(win, L, details=True)
+    assert not info["degenerate"][0]
+    assert abs(om[0] - w1) < 1e-9
+    win, _ = two_tone_windows(L, 1.0 + 0.5 * oracle.DEGENERATE_REL)
+    assert np.isnan(oracle.demod_windows(win, L)[0])
+    win, _ = two_tone_windows(L, 1.0 + 3.0 * oracle.DEGENERATE_REL)
+    assert np.isfinite(oracle.demod_windows(win, L)[0])
