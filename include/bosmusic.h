@@ -20,9 +20,12 @@
  *   - signal/noise eigen-split with a one-dimensional signal subspace
  *     (Eq. 6-11);
  *   - root-MUSIC polynomial a(z)^H Un Un^H a(z) (Eq. 12) from the diagonal
- *     sums of the noise projector, degree 2L-2, and all its roots;
- *   - the root pair nearest the unit circle; omega = arg of the pair sum,
- *     equal to arg of the inner root (Eq. 15) in exact arithmetic.
+ *     sums of the noise projector, degree 2L-2;
+ *   - the root pair nearest the unit circle (Sec. 3, selection rule): found
+ *     alone by Newton's method for the signal root and proven nearest by a
+ *     root-count certificate, or, where that proof fails (or with
+ *     BM_OPT_FULL_ROOTS), selected from all 2L-2 roots; omega = arg of the
+ *     pair sum, equal to arg of the inner root (Eq. 15) in exact arithmetic.
  *
  * Conventions
  *   - Every call returns a bm_status; nothing throws or aborts across this
@@ -33,7 +36,8 @@
  *     `stream` is a hipStream_t (NULL = the default stream); calls only
  *     enqueue work and return without synchronising, except where noted.
  *   - omega is in rad/px in [-pi, pi]; border pixels whose window does not
- *     fit, and windows whose covariance is identically zero or non-finite,
+ *     fit, windows whose covariance is identically zero or non-finite, and
+ *     windows whose signal subspace is not determined (BM_FLAG_DEGENERATE)
  *     are NaN.  phi is in rad, FP64, NaN outside the integrated region.
  *   - A handle owns its workspace and serves one stream at a time; it is not
  *     thread-safe.  Separate handles are independent.
@@ -100,6 +104,10 @@ enum {
 enum {
     BM_FLAG_UNDEFINED = 1u, /* border pixel, zero/non-finite covariance: omega is NaN */
     BM_FLAG_NO_POLISH = 2u, /* the FP64 pair polish failed; the FP32 pair sum was kept */
+    BM_FLAG_DEGENERATE = 4u, /* the two largest eigenvalues of the covariance are within a
+                                relative 1e-5 (lambda_1 <= lambda_2 (1 + 1e-5)): the
+                                one-dimensional signal subspace of Eq. 6-11 is not
+                                determined, e.g. two tones of equal power; omega is NaN */
 };
 
 typedef struct {
@@ -129,10 +137,21 @@ typedef struct {
                            wrapped phase of the block's linear model at the pixel, i.e.
                            Eq. 15's alpha = arg(mean(Gamma_w e^{-j(omega_x x + omega_y y)}))
                            with x, y measured from the pixel; NaN where omega is; or NULL */
+    /* Temporal warm start (optional; line windows; ignored by BM_SURROGATE): the omega maps of
+     * the previous frame of a time-lapsed series, the same size, row stride =
+     * width (the paper's premise that the phase changes little between
+     * successive frames, Sec. 1 and 4).  Where the previous frequency at the
+     * pixel is finite, the Newton iteration for the window's signal root
+     * starts in its direction instead of the window's own lag-1 direction.
+     * The certified pair, hence omega, is the same either way (up to
+     * rounding); only the iteration counts change.  NULL: no warm start. */
+    const float* prev_omega_x;
+    const float* prev_omega_y;
 } bosmusic_frame;
 
 typedef struct {
-    uint64_t windows;       /* windows demodulated since the last reset */
+    uint64_t windows;       /* windows demodulated since the last reset (in BM_PLAIN:
+                               sur_accepted + sur_rejected + the BM_FLAG_DEGENERATE ones) */
     uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI) */
     uint64_t root_iters;    /* sum over windows of simultaneous root iterations (all-roots windows) */
     uint64_t polish_fail;   /* windows whose FP64 pair polish did not converge */
@@ -177,7 +196,10 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
                               int32_t mode, void* stream);
 
 /* Integrate omega maps to phase (FP64 trapezoid rule on the window-centre
- * grid), enqueued on `stream`.  Anchor phi = 0 at column floor(Nx/2) and,
+ * grid), enqueued on `stream`.  This replaces the paper's route from the
+ * frequencies to the phase (Sec. 3 after Eq. 15: the per-window offset alpha
+ * of Eq. 15, then phase unwrapping): the local frequencies are the phase
+ * derivatives, so their running sums give the unwrapped phase directly.  Anchor phi = 0 at column floor(Nx/2) and,
  * when omega_y is given, row floor(Ny/2): first down the anchor column with
  * omega_y - carrier_y, then along every row with omega_x - carrier_x.
  * Without omega_y (NULL) every row starts at 0 in the anchor column.  phi is

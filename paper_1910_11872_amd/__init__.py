@@ -26,7 +26,7 @@ BM_OPT_TIMING = 2
 BM_OPT_JACOBI = 4
 BM_OPT_GRAPH = 8
 BM_OPT_FULL_ROOTS = 16
-BM_FLAG_UNDEFINED, BM_FLAG_NO_POLISH = 1, 2
+BM_FLAG_UNDEFINED, BM_FLAG_NO_POLISH, BM_FLAG_DEGENERATE = 1, 2, 4
 
 ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "bosmusic_integrate",
                  "bosmusic_autotune", "bosmusic_get_stats", "bosmusic_status_string", "bosmusic_last_error",
@@ -45,7 +45,8 @@ class bosmusic_config(ctypes.Structure):
 class bosmusic_frame(ctypes.Structure):
     _fields_ = [("data", c_void_p), ("dtype", c_int32), ("width", c_int32), ("height", c_int32),
                 ("row_stride", c_int64), ("L", c_int32), ("N", c_int32), ("dirs", c_uint32),
-                ("omega_x", c_void_p), ("omega_y", c_void_p), ("flags", c_void_p), ("phase", c_void_p)]
+                ("omega_x", c_void_p), ("omega_y", c_void_p), ("flags", c_void_p), ("phase", c_void_p),
+                ("prev_omega_x", c_void_p), ("prev_omega_y", c_void_p)]
 
 
 class bosmusic_integrate_job(ctypes.Structure):
@@ -181,19 +182,48 @@ class FrameSpec:
     omega_y: object = None
     flags: object = None
     phase: object = None
+    prev_omega_x: object = None   # temporal warm start: the previous frame's maps
+    prev_omega_y: object = None
+
+
+def _device_check(tensors, device) -> None:
+    """Every buffer the C ABI touches is device memory of the handle's GPU: refuse host
+    tensors and tensors on another device (a kernel would fault or read the wrong memory)."""
+    for t, name in tensors:
+        if t is None:
+            continue
+        if t.device.type != "cuda":
+            raise ValueError(f"{name}: need a GPU (cuda) tensor, got one on {t.device}")
+        if device is not None and t.device != device:
+            raise ValueError(f"{name}: on {t.device}, the frame is on {device}")
 
 
 def _marshal(f: FrameSpec) -> bosmusic_frame:
+    """Frame descriptor of the C ABI.  The kernels store 4-byte omega and phase values and
+    1-byte flags row-major with row stride = width, so any other dtype, shape, layout or
+    device is refused here (a float16 map would take out-of-bounds stores)."""
+    import torch
     d = f.data
     if d.dim() != 2 or d.stride(1) != 1:
         raise ValueError("frame must be a 2-D tensor with unit column stride")
+    code = _dtype_code(d)
     H, W = d.shape
-    for out in (f.omega_x, f.omega_y, f.flags, f.phase):
-        if out is not None and (tuple(out.shape) != (H, W) or not out.is_contiguous()):
-            raise ValueError("outputs must be contiguous (H, W) tensors")
+    for out, name, dt in ((f.omega_x, "omega_x", torch.float32), (f.omega_y, "omega_y", torch.float32),
+                          (f.flags, "flags", torch.uint8), (f.phase, "phase", torch.float32),
+                          (f.prev_omega_x, "prev_omega_x", torch.float32),
+                          (f.prev_omega_y, "prev_omega_y", torch.float32)):
+        if out is None:
+            continue
+        if tuple(out.shape) != (H, W) or out.dtype != dt or not out.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous {dt} tensor of shape {(H, W)}, "
+                             f"got {out.dtype} {tuple(out.shape)} strides {out.stride()}")
+    _device_check([(d, "frame")], None)
+    _device_check([(f.omega_x, "omega_x"), (f.omega_y, "omega_y"), (f.flags, "flags"), (f.phase, "phase"),
+                   (f.prev_omega_x, "prev_omega_x"), (f.prev_omega_y, "prev_omega_y")], d.device)
     ptr = lambda t: c_void_p(t.data_ptr()) if t is not None else c_void_p()
-    return bosmusic_frame(c_void_p(d.data_ptr()), _dtype_code(d), W, H, d.stride(0), f.L, f.N, f.dirs,
-                          ptr(f.omega_x), ptr(f.omega_y), ptr(f.flags), ptr(f.phase))
+    return bosmusic_frame(c_void_p(d.data_ptr()), code, W, H, d.stride(0), f.L, f.N, f.dirs,
+                          ptr(f.omega_x), ptr(f.omega_y), ptr(f.flags), ptr(f.phase),
+                          ptr(f.prev_omega_x), ptr(f.prev_omega_y))
 
 
 def bosmusic_demodulate(h, frames, mode: int = BM_PLAIN, stream=None) -> None:
@@ -213,6 +243,8 @@ def _map_check(omega_x, omega_y, phi) -> None:
         if tuple(t.shape) != (H, W) or t.dtype != dt or not t.is_contiguous():
             raise ValueError(f"{name}: need a contiguous {dt} tensor of shape {(H, W)}, "
                              f"got {t.dtype} {tuple(t.shape)} strides {t.stride()}")
+    _device_check([(omega_x, "omega_x")], None)
+    _device_check([(omega_y, "omega_y"), (phi, "phi")], omega_x.device)
 
 
 def bosmusic_integrate(h, omega_x, omega_y, Nx: int, Ny: int, carrier_x: float, carrier_y: float, phi,
@@ -272,6 +304,7 @@ def bosmusic_surrogate_config(h, tau: float = 0.25, predictor: int = 0) -> None:
 
 def bosmusic_surrogate_forward(h, X, Y, stream=None) -> None:
     """Y[M, 2] = MLP(X[M, 32]); X, Y contiguous FP32 device tensors."""
+    _buf_check([(X, "X", (X.shape[0], 32)), (Y, "Y", (X.shape[0], 2))])
     _check(lib().bosmusic_surrogate_forward(h, c_void_p(X.data_ptr()), c_void_p(Y.data_ptr()), X.shape[0],
                                             _stream_ptr(stream)), h)
 
@@ -292,24 +325,45 @@ def _ptr(t):
     return c_void_p(t.data_ptr()) if t is not None else c_void_p(None)
 
 
+def _buf_check(items) -> None:
+    """Surrogate buffers: contiguous FP32 device tensors of the stated shapes, all on
+    the first one's device (None entries are optional buffers left out)."""
+    import torch
+    dev = None
+    for t, name, shape in items:
+        if t is None:
+            continue
+        if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: need a contiguous torch.float32 tensor of shape {tuple(shape)}, "
+                             f"got {t.dtype} {tuple(t.shape)} strides {t.stride()}")
+        _device_check([(t, name)], dev)
+        dev = t.device
+
+
 def bosmusic_surrogate_dataset(h, first_line: int, X, T, omega=None, seed: int = 0, stream=None) -> None:
     """Fill X[M, 32], T[M, 2] (and omega[M]) with training lines first_line .. first_line+M-1."""
+    M = X.shape[0]
+    _buf_check([(X, "X", (M, 32)), (T, "T", (M, 2)), (omega, "omega", (M,))])
     _check(lib().bosmusic_surrogate_dataset(h, first_line, X.shape[0], seed, _ptr(X), _ptr(T), _ptr(omega),
                                             _stream_ptr(stream)), h)
 
 
 def bosmusic_surrogate_grad(h, X, T, grad, loss=None, stream=None) -> None:
+    M = X.shape[0]
+    _buf_check([(X, "X", (M, 32)), (T, "T", (M, 2)), (grad, "grad", (MLP_PARAMS,)), (loss, "loss", (1,))])
     _check(lib().bosmusic_surrogate_grad(h, _ptr(X), _ptr(T), X.shape[0], _ptr(grad), _ptr(loss),
                                          _stream_ptr(stream)), h)
 
 
 def bosmusic_surrogate_step(h, grad, lr: float, stream=None) -> None:
+    _buf_check([(grad, "grad", (MLP_PARAMS,))])
     _check(lib().bosmusic_surrogate_step(h, _ptr(grad), lr, _stream_ptr(stream)), h)
 
 
 def bosmusic_surrogate_train(h, X, T, batch: int, steps: int, lr: float, want_losses: bool = True, stream=None):
     """Minibatch Adam over (X, T); returns the per-step losses (host) when want_losses."""
     import numpy as np
+    _buf_check([(X, "X", (X.shape[0], 32)), (T, "T", (X.shape[0], 2))])
     losses = np.empty(max(steps, 1), np.float32) if want_losses else None
     _check(lib().bosmusic_surrogate_train(h, _ptr(X), _ptr(T), X.shape[0], batch, steps, lr,
                                           losses.ctypes.data_as(c_void_p) if want_losses else c_void_p(None),

@@ -1,16 +1,14 @@
 // Complex analytic fringe signal (paper Sec. 2, Eq. 1) by an exact DFT mask,
 // plus the tiled transposes that turn the y direction into lines.
 //
-// analytic_kernel: one block per pair of lines (transforms up to 2048
-// samples, 256 threads) or per line (longer ones, 1024 threads).  A line is
-// decoded to FP32, run through a mixed-radix (4, 2, 3, 5, 7, 11, 13) Stockham
-// FFT ping-ponged between LDS buffers, multiplied by the one-sided mask H
-// (H[0] = 0, H[k] = 2 for 0 < 2k < n, 0 otherwise, so DC and Nyquist are
-// removed and the carrier is kept), and transformed back with the same
-// forward FFT applied to the conjugate.  Two real lines x_a, x_b share one
-// forward transform of z = x_a + i x_b: X_a[k] = (Z[k] + conj Z[n-k]) / 2 and
-// X_b[k] = (Z[k] - conj Z[n-k]) / 2i, so a pair costs three transforms
-// instead of four.  Twiddles come from per-pass tables of each length,
+// analytic_kernel: one block per pair of lines (256 threads for transforms up
+// to 2048 samples, 1024 above).  The pair is decoded to FP32 as z = x_a + i x_b,
+// run through a mixed-radix (4, 2, 3, 5, 7, 11, 13) Stockham FFT ping-ponged
+// between two LDS buffers, multiplied by -i sgn(k) (the one-sided mask H[0] =
+// 0, H[k] = 2 for 0 < 2k < n, 0 otherwise, applied to the imaginary part: DC
+// and Nyquist removed, carrier kept) and transformed back with the same
+// forward FFT applied to the conjugate; the real parts are the samples with
+// their DC and Nyquist components removed.  Two transforms per pair of lines.  Twiddles come from per-pass tables of each length,
 // contiguous in the butterfly index, computed in FP64 on the host and
 // rounded once; they are read through the caches (staging them in LDS cost
 // more in blocks per CU than it saved in latency).  A length with a prime factor above 13 takes each DFT
@@ -217,8 +215,20 @@ __device__ __forceinline__ float load_real(const void* base, int64_t idx, int el
 
 __device__ __forceinline__ float2 conjf2(float2 v) { return make_float2(v.x, -v.y); }
 
-// One block per work item of any job: a pair of lines (lines 2i, 2i+1) when
-// the transform is short enough for three LDS buffers, else one line.
+// One block per pair of lines (2i, 2i+1; a lone last line pairs with zeros).
+// With z = x_a + i x_b and Z = DFT(z), the analytic signal of each real line
+// is Gamma = IFFT(H X) (reading of Sec. 2 / Eq. 1: H[0] = 0, H[k] = 2 for
+// 0 < 2k < n, 0 above), whose two parts are
+//   Re Gamma = x - X[0]/n - X[n/2] (-1)^i / n      (DC and Nyquist removed)
+//   Im Gamma = IFFT(-i sgn(k) X[k])                (the Hilbert transform)
+// with sgn(k) = +1 for 0 < 2k < n, -1 for 2k > n, 0 at k = 0 and 2k = n.  The
+// Hilbert transform is real-linear, so one inverse DFT of -i sgn(k) Z[k]
+// gives h_a + i h_b, the imaginary parts of both lines, and X_a[0] + i X_b[0]
+// = Z[0] (and so at n/2).  A pair costs two transforms instead of the three
+// that splitting the spectra and inverting H X_a and H X_b take (four for two
+// lines alone), and needs two line buffers of LDS.  The real parts are the
+// samples themselves, read again at the end (from the cache: holding them in
+// registers instead took the 1024-thread kernel from two blocks per CU to one).
 template <int MAXR, int T>
 __global__ __launch_bounds__(T) void analytic_kernel(FftBatch B, int item0) {
     extern __shared__ float2 lds[];
@@ -228,53 +238,38 @@ __global__ __launch_bounds__(T) void analytic_kernel(FftBatch B, int item0) {
     const int item = w - B.prefix[j];
     const int n = J.n, m = J.plan.n;
     const int elem = J.elem;
-    const bool pairs = fft_pairs(m);
-    const int la = pairs ? 2 * item : item;
-    const bool two = pairs && la + 1 < J.nlines;
+    const int la = 2 * item;
+    const bool two = la + 1 < J.nlines;
     float2* a = lds;
     float2* b = lds + m;
-    float2* c = lds + 2 * m;            // pairs only
     const float2* tw = J.tw;
     const int64_t off = (int64_t)la * J.src_ls;
     for (int i = threadIdx.x; i < n; i += T)
         a[i] = make_float2(load_real(J.src, off + i, elem), two ? load_real(J.src, off + J.src_ls + i, elem) : 0.f);
     __syncthreads();
     float2* X = dft_line<MAXR, T>(a, b, J, tw);
-    float2* other = (X == a) ? b : a;
-    // one-sided mask and 1/n, then conjugate so that a forward DFT inverts
-    const float sc = 2.0f / (float)n;
-    if (!two) {
-        for (int k = threadIdx.x; k < n; k += T) {
-            const float2 v = X[k];
-            const bool keep = (k >= 1) && (2 * k < n);
-            X[k] = keep ? make_float2(v.x * sc, -v.y * sc) : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-        float2* Y = dft_line<MAXR, T>(X, other, J, tw);
-        float2* out = J.dst + (int64_t)la * n;
-        for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Y[i]);
-        return;
-    }
-    // split the spectra of the two real lines, masked and conjugated, into `other` (a) and `c` (b)
-    const float hs = 0.5f * sc;
+    float2* V = (X == a) ? b : a;
+    const float inv_n = 1.0f / (float)n;
+    const float2 z0 = X[0];
+    const float2 zh = (n & 1) ? make_float2(0.f, 0.f) : X[n >> 1];
+    // V = conj(-i sgn(k) Z[k]) / n = sgn(k) (Im Z, Re Z) / n, so that the forward DFT
+    // of V, conjugated, is IFFT(-i sgn Z)
     for (int k = threadIdx.x; k < n; k += T) {
-        float2 ma = make_float2(0.f, 0.f), mb = make_float2(0.f, 0.f);
-        if ((k >= 1) && (2 * k < n)) {
-            const float2 z = X[k], zn = X[n - k];
-            ma = make_float2(hs * (z.x + zn.x), -hs * (z.y - zn.y));      // conj(sc X_a[k])
-            mb = make_float2(hs * (z.y + zn.y), hs * (z.x - zn.x));       // conj(sc X_b[k])
-        }
-        other[k] = ma;
-        c[k] = mb;
+        const float2 v = X[k];
+        const float sg = (k == 0 || 2 * k == n) ? 0.f : (2 * k < n ? inv_n : -inv_n);
+        V[k] = make_float2(sg * v.y, sg * v.x);
     }
     __syncthreads();
-    float2* Ya = dft_line<MAXR, T>(other, X, J, tw);
-    float2* spare = (Ya == other) ? X : other;
+    float2* Y = dft_line<MAXR, T>(V, X, J, tw);
+    // h_a + i h_b = conj(Y): Im Gamma_a = Y.x, Im Gamma_b = -Y.y
+    const float dca = z0.x * inv_n, dcb = z0.y * inv_n, nqa = zh.x * inv_n, nqb = zh.y * inv_n;
     float2* out = J.dst + (int64_t)la * n;
-    for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Ya[i]);
-    float2* Yb = dft_line<MAXR, T>(c, spare, J, tw);
-    out += n;
-    for (int i = threadIdx.x; i < n; i += T) out[i] = conjf2(Yb[i]);
+    for (int i = threadIdx.x; i < n; i += T) {
+        const float sgn = (i & 1) ? -1.f : 1.f;
+        const float2 y = Y[i];
+        out[i] = make_float2(load_real(J.src, off + i, elem) - dca - sgn * nqa, y.x);
+        if (two) out[n + i] = make_float2(load_real(J.src, off + J.src_ls + i, elem) - dcb - sgn * nqb, -y.y);
+    }
 }
 
 // One block of 256 threads per tile of any job: 64 x 64 for real input

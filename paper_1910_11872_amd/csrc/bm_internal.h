@@ -9,7 +9,11 @@
 
 namespace bm {
 
-constexpr int kMaxL = 8;
+constexpr int kMaxL = 8;        // covariance size of line windows
+// Block windows (the paper's (2L+1) x (2L+1) window, Sec. 3) go up to 17 x 17, the
+// largest of the paper's window-size table; above kMaxL only odd sizes.
+constexpr int kMaxBlockL = 17;
+constexpr bool block_size_supported(int L) { return L >= 2 && (L <= kMaxL || (L <= kMaxBlockL && (L & 1))); }
 constexpr int kMaxN = 64;
 constexpr int kMaxFFT = 8192;
 constexpr int kMaxRadixPasses = 20;
@@ -32,8 +36,8 @@ enum class Elem : int { F16 = 1, F32 = 2, F64 = 3, C32 = 4, U8 = 5 };
 // double root at 1 split radially into (rho, 1/rho).  Rotated by the
 // frequency guess of each window at run time.
 struct RootTemplate {
-    float re[2 * kMaxL - 2];
-    float im[2 * kMaxL - 2];
+    float re[2 * kMaxBlockL - 2];
+    float im[2 * kMaxBlockL - 2];
 };
 
 // Window kinds of a root-MUSIC job.
@@ -64,6 +68,10 @@ struct RmJob {
     int bdirs;             // BM_DIR_X | BM_DIR_Y
     float* out_y;          // omega_y
     float* phase;          // wrapped block phase, or nullptr
+    // RM_LINE, optional temporal warm start: the previous frame's omega at
+    // prev[p * prev_es + line * prev_ls] (nullptr: none)
+    const float* prev;
+    int64_t prev_es, prev_ls;
 };
 
 // All root-MUSIC work of one L: jobs[j] owns work items prefix[j] .. prefix[j+1)-1.
@@ -96,25 +104,15 @@ struct FftJob {
     FftPlan plan;          // plan of n, or of m under Bluestein (chirp != nullptr)
 };
 
-// LDS of the analytic kernel's block, in complex elements (132 KiB): three
-// 5632-sample buffers, or two 8192-sample buffers.
+// LDS of the analytic kernel's block, in complex elements (132 KiB): two
+// buffers of up to 8192 samples (or of a Bluestein transform length).
 constexpr int kFftLdsElems = 16896;
 
-// Transform lengths up to this take two real lines per block (one complex
-// forward DFT of x_a + i x_b, split by symmetry): three line buffers in LDS.
-// Longer ones take one line per block: two buffers, so that two blocks fit
-// in a CU's LDS (pairs of 4096-sample lines, one block per CU, were 1.3x
-// slower than single lines).
-constexpr int kFftPairMax = 2048;
-
-// Transform lengths above this run 1024 threads per block (one radix-4
-// butterfly per thread and pass at 4096), shorter ones 256.
+// Transform lengths above this run 1024 threads per block, shorter ones 256.
 constexpr int kFftWideMin = 2049;
 
-__host__ __device__ inline bool fft_pairs(int m) { return m <= kFftPairMax; }
-
-// Work items (blocks) of one job: line pairs or lines.
-inline int fft_items(const FftJob& j) { return fft_pairs(j.plan.n) ? (j.nlines + 1) / 2 : j.nlines; }
+// Work items (blocks) of one job: pairs of lines.
+inline int fft_items(const FftJob& j) { return (j.nlines + 1) / 2; }
 
 // Entries of the per-pass twiddle tables of a plan: (R - 1)(Ns + 1) per pass,
 // at most plan.n + 64.
@@ -128,7 +126,7 @@ inline int fft_tw_len(const FftPlan& p) {
 }
 
 // LDS of one job's block, in complex elements.
-inline int fft_lds_elems(const FftJob& j) { return (fft_pairs(j.plan.n) ? 3 : 2) * j.plan.n; }
+inline int fft_lds_elems(const FftJob& j) { return 2 * j.plan.n; }
 
 // True when the job's plan has a radix above 5.
 inline bool fft_big_radix(const FftJob& j) {
@@ -180,14 +178,19 @@ struct TrBatch {
 // threads; `grid` is the number of blocks of the grid-stride loop (<= 0: one
 // block per work item).
 hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStream_t s);
+// Lanes per block of the block-window kernels: 256, or 128 above 8 x 8.
+constexpr int block_window_lanes(int L) { return L <= kMaxL ? 256 : 128; }
+// Block windows above 8 x 8 (odd sizes to kMaxBlockL), in their own translation unit.
+hipError_t launch_big_block_window(int L, const RmBatch& b, int grid, hipStream_t s);
 // Output pixels per work item of a line: the line-window root-MUSIC kernel
 // (line_kernel) covers two starts per lane, the block-window and surrogate
 // kernels one.
 int rootmusic_windows_per_block(int L, int block, bool line_kernel);
-// Plain root-MUSIC on the *count windows of `list` ({job, line << 16 | pixel}),
-// grid-stride over `grid` blocks of kGatherBlock lanes.
-hipError_t launch_rootmusic_gather(int L, const RmBatch& b, const int2* list, const int* count, int grid,
-                                   hipStream_t s);
+// Plain root-MUSIC on the *count windows of `list` ({job, line << 16 | pixel};
+// lines and pixels are below 65536 because frame sides are), grid-stride over
+// `grid` blocks of kGatherBlock lanes.
+hipError_t launch_rootmusic_gather(int L, const RmBatch& b, const int2* list, const unsigned long long* count,
+                                   int grid, hipStream_t s);
 
 // Surrogate MLP 32 -> 64 -> 64 -> 2 (GELU), bfloat16 weights stored
 // transposed (out x in) for the MFMA A operand, FP32 biases.
@@ -206,8 +209,8 @@ constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpH
 struct SurBatch {
     RmBatch rm;            // the windows (jobs of one L)
     MlpWeights w;
-    int2* rejects;         // windows sent to the plain fallback
-    int* reject_count;
+    int2* rejects;         // windows sent to the plain fallback (capacity: every window of rm)
+    unsigned long long* reject_count;
     int predictor;         // 0: MLP, 1: lag-1 phase of the covariance (no learning)
     float tau;             // acceptance bound on the null spectrum at the refined frequency
 };
@@ -217,7 +220,7 @@ struct SurBatch {
 hipError_t launch_surrogate(int L, const SurBatch& b, hipStream_t s);
 // Y[M x 2] = MLP(X[M x 32]) with the kernel's bfloat16 arithmetic.
 hipError_t launch_mlp_forward(const MlpWeights& w, const float* X, float* Y, int M, hipStream_t s);
-hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 
 // Surrogate training.  Lines of 128 samples drawn by counter (Philox4x32-10)
 // for ids first .. first+count-1; label windows {job = i >> 16, line = i & 0xFFFF,

@@ -28,6 +28,7 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void* blob = nullptr;  // device job tables referenced by the graph's kernels
+    void* rej = nullptr;   // BM_SURROGATE: reject counters and lists of the graph's sets, one region per set
     uint64_t last_use = 0;
 };
 
@@ -50,7 +51,7 @@ struct bosmusic_s {
     std::map<int, float2*> bluestein;   // line length -> chirp (n) then kernel (m) in one allocation
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
     uint64_t rm_launches = 0, rm_time_ns = 0;
-    bm::RootTemplate tmpl[bm::kMaxL + 1];
+    bm::RootTemplate tmpl[bm::kMaxBlockL + 1];
     Tune tune[bm::kMaxL + 1][bm::kMaxN + 1];
     std::string tune_path;
     // eager job-table upload
@@ -73,9 +74,9 @@ struct bosmusic_s {
     bool sur_loaded = false;
     float sur_tau = 0.25f;
     int sur_predictor = 0;
-    int2* rejects = nullptr;
+    int2* rejects = nullptr;       // eager calls: the sets of a group run one after another on one stream
     size_t rejects_cap = 0;
-    int* reject_count = nullptr;
+    unsigned long long* reject_count = nullptr;
     // surrogate training
     float* adam_m = nullptr;       // Adam moments (BOSMUSIC_MLP_PARAMS each)
     float* adam_v = nullptr;
@@ -238,7 +239,7 @@ void make_template(int L, bm::RootTemplate& t) {
         t.re[2 + i] = (float)z[i].real();
         t.im[2 + i] = (float)z[i].imag();
     }
-    for (int i = n; i < 2 * bm::kMaxL - 2; ++i) t.re[i] = t.im[i] = 0.f;
+    for (int i = n; i < 2 * bm::kMaxBlockL - 2; ++i) t.re[i] = t.im[i] = 0.f;
 }
 
 // Per-pass twiddle tables of the mixed-radix plan of n: for pass p with
@@ -333,7 +334,15 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
         return fail(h, BM_E_INVALID_ARG, "frame %d: size %dx%d outside 1..%dx%d", idx, f.width, f.height, h->max_w,
                     h->max_h);
     if (f.row_stride < f.width) return fail(h, BM_E_INVALID_ARG, "frame %d: row_stride < width", idx);
-    if (f.L < 2 || f.L > bm::kMaxL) return fail(h, BM_E_INVALID_ARG, "frame %d: L=%d outside 2..8", idx, f.L);
+    if (f.dirs & BM_BLOCK) {
+        if (!bm::block_size_supported(f.L))
+            return fail(h, BM_E_INVALID_ARG, "frame %d: block window %d x %d: 2..8, or odd up to %d", idx, f.L, f.L,
+                        bm::kMaxBlockL);
+        if (f.L > bm::kMaxL && f.width < f.L)
+            return fail(h, BM_E_INVALID_ARG, "frame %d: block window wider than the frame", idx);
+    } else if (f.L < 2 || f.L > bm::kMaxL) {
+        return fail(h, BM_E_INVALID_ARG, "frame %d: L=%d outside 2..8", idx, f.L);
+    }
     if (f.N < f.L || f.N > bm::kMaxN) return fail(h, BM_E_INVALID_ARG, "frame %d: N=%d outside L..64", idx, f.N);
     if ((f.dirs & 3u) == 0 || (f.dirs & ~(3u | BM_BLOCK)))
         return fail(h, BM_E_INVALID_ARG, "frame %d: dirs=%u", idx, f.dirs);
@@ -341,6 +350,8 @@ bm_status validate_frame(bosmusic_s* h, const bosmusic_frame& f, int idx) {
         return fail(h, BM_E_INVALID_ARG, "frame %d: block windows need N == L (got L=%d, N=%d)", idx, f.L, f.N);
     if (f.phase && ((f.dirs & (BM_BLOCK | 3u)) != (BM_BLOCK | 3u)))
         return fail(h, BM_E_INVALID_ARG, "frame %d: phase needs BM_BLOCK with both directions", idx);
+    if ((f.prev_omega_x || f.prev_omega_y) && (f.dirs & BM_BLOCK))
+        return fail(h, BM_E_UNSUPPORTED, "frame %d: the temporal warm start is for line windows", idx);
     if ((f.dirs & BM_DIR_X) && !f.omega_x) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_x is NULL", idx);
     if ((f.dirs & BM_DIR_Y) && !f.omega_y) return fail(h, BM_E_INVALID_ARG, "frame %d: omega_y is NULL", idx);
     if (f.dtype != BM_C32) {
@@ -379,6 +390,9 @@ struct RmSet {
     size_t jobs_off = 0, prefix_off = 0;
     bm::RmBatch batch{};
     Tune tune;
+    // BM_SURROGATE: where this set's rejected windows go (capacity set_windows)
+    int2* rej_list = nullptr;
+    unsigned long long* rej_count = nullptr;
 };
 
 struct GroupPlan {
@@ -485,6 +499,9 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             j.out = f.omega_x;
             j.out_es = 1;
             j.out_ls = W;
+            j.prev = f.prev_omega_x;
+            j.prev_es = 1;
+            j.prev_ls = W;
             j.flags = f.flags;
             j.flag_es = 1;
             j.flag_ls = W;
@@ -541,6 +558,9 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             j.out = oy;
             j.out_es = 1;
             j.out_ls = H;
+            j.prev = f.prev_omega_y;     // the caller's row-major map: along the line (y) W apart
+            j.prev_es = W;
+            j.prev_ls = 1;
             j.flags = f.flags;
             j.flag_es = W;
             j.flag_ls = 1;
@@ -578,9 +598,11 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         RmSet s = kv.second;
         int nmax = 0;
         for (auto& j : s.jobs) nmax = std::max(nmax, j.N);
-        s.tune = h->tune[s.L][nmax];
-        // the surrogate and block-window kernels run 256 lanes, one block per item
+        // the surrogate and block-window kernels run 256 lanes (128 for block windows
+        // above 8 x 8), one block per item; line windows take the tuned tile
         if (mode == BM_SURROGATE || s.block_win) s.tune = Tune{};
+        else s.tune = h->tune[s.L][nmax];
+        if (s.block_win) s.tune.block = bm::block_window_lanes(s.L);
         const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block, mode != BM_SURROGATE && !s.block_win);
         s.prefix.assign(1, 0);
         for (auto& j : s.jobs) {
@@ -656,14 +678,16 @@ size_t set_windows(const RmSet& s) {
     return n;
 }
 
-bm_status ensure_rejects(bosmusic_s* h, size_t n, hipStream_t st) {
+// The eager path's reject list (graphs own theirs).  Growing it waits for the
+// device: work enqueued by earlier eager calls, on any stream, may still use it.
+bm_status ensure_rejects(bosmusic_s* h, size_t n) {
     if (n <= h->rejects_cap && h->reject_count) return BM_OK;
     bm_status r;
-    if ((r = check(h, hipStreamSynchronize(st), "sync before growing the reject list"))) return r;
+    if ((r = check(h, hipDeviceSynchronize(), "sync before growing the reject list"))) return r;
     (void)hipFree(h->rejects);
     h->rejects = nullptr;
     h->rejects_cap = 0;
-    if (!h->reject_count && hipMalloc(&h->reject_count, sizeof(int)) != hipSuccess)
+    if (!h->reject_count && hipMalloc(&h->reject_count, sizeof(unsigned long long)) != hipSuccess)
         return fail(h, BM_E_NOMEM, "reject counter");
     if (hipMalloc(&h->rejects, std::max<size_t>(n, 1) * sizeof(int2)) != hipSuccess)
         return fail(h, BM_E_NOMEM, "reject list of %zu windows", n);
@@ -671,21 +695,23 @@ bm_status ensure_rejects(bosmusic_s* h, size_t n, hipStream_t st) {
     return BM_OK;
 }
 
-// Surrogate pass over a set, then the plain path on the windows it rejected.
+// Surrogate pass over a set, then the plain path on the windows it rejected,
+// through the set's own reject list.
 bm_status launch_sur(bosmusic_s* h, const RmSet& s, hipStream_t st) {
     bm_status r;
+    if (!s.rej_list || !s.rej_count) return fail(h, BM_E_DEVICE, "surrogate set without a reject list");
     bm::SurBatch sb;
     sb.rm = s.batch;
     sb.w = mlp_weights(h);
-    sb.rejects = h->rejects;
-    sb.reject_count = h->reject_count;
+    sb.rejects = s.rej_list;
+    sb.reject_count = s.rej_count;
     sb.predictor = h->sur_predictor;
     sb.tau = h->sur_tau;
-    if ((r = check(h, bm::launch_fill_int(h->reject_count, 1, 0, st), "reject counter"))) return r;
+    if ((r = check(h, bm::launch_fill_u64(s.rej_count, 1, 0ull, st), "reject counter"))) return r;
     if ((r = check(h, bm::launch_surrogate(s.L, sb, st), "surrogate"))) return r;
     const size_t cap = set_windows(s);
     const int grid = (int)std::min<size_t>((size_t)4 * h->cu_count, (cap + bm::kGatherBlock - 1) / bm::kGatherBlock);
-    return check(h, bm::launch_rootmusic_gather(s.L, s.batch, h->rejects, h->reject_count, std::max(grid, 1), st),
+    return check(h, bm::launch_rootmusic_gather(s.L, s.batch, s.rej_list, s.rej_count, std::max(grid, 1), st),
                  "fallback");
 }
 
@@ -753,9 +779,14 @@ bm_status run_group_eager(bosmusic_s* h, GroupPlan& gp, hipStream_t st) {
     bm_status r;
     if ((r = ensure_upload_buffers(h, gp.blob.size(), st))) return r;
     if (gp.mode == BM_SURROGATE) {
+        // the sets run one after another on `st`: they share one list
         size_t mx = 0;
         for (auto& s : gp.rm) mx = std::max(mx, set_windows(s));
-        if ((r = ensure_rejects(h, mx, st))) return r;
+        if ((r = ensure_rejects(h, mx))) return r;
+        for (auto& s : gp.rm) {
+            s.rej_list = h->rejects;
+            s.rej_count = h->reject_count;
+        }
     }
     if (h->pin_pending && (r = check(h, hipEventSynchronize(h->pin_ev), "upload wait"))) return r;
     std::memcpy(h->pin, gp.blob.data(), gp.blob.size());
@@ -781,7 +812,8 @@ std::string signature(const bosmusic_s* h, const bosmusic_frame* frames, int n, 
     }
     key.append((const char*)frames, (size_t)n * sizeof(bosmusic_frame));
     key.append((const char*)&h->options, sizeof(h->options));
-    for (int i = 0; i < n; ++i) key.append((const char*)&h->tune[frames[i].L][frames[i].N], sizeof(Tune));
+    for (int i = 0; i < n; ++i)
+        if (frames[i].L <= bm::kMaxL) key.append((const char*)&h->tune[frames[i].L][frames[i].N], sizeof(Tune));
     return key;
 }
 
@@ -789,6 +821,7 @@ void destroy_graph(GraphEntry& g) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
     (void)hipFree(g.blob);
+    (void)hipFree(g.rej);
     g = GraphEntry{};
 }
 
@@ -798,15 +831,31 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
     std::vector<GroupPlan> plans(groups.size());
     size_t total = 0;
     std::vector<size_t> offs;
+    size_t rej_total = 0;
+    std::vector<size_t> rej_offs;   // per set of every group: counter, then its list
     for (size_t g = 0; g < groups.size(); ++g) {
         if ((r = plan_group(h, frames, groups[g].first, groups[g].second, mode, plans[g]))) return r;
         if (mode == BM_SURROGATE)
-            for (auto& s : plans[g].rm)
-                if ((r = ensure_rejects(h, set_windows(s), st))) return r;
+            // sets of different L run concurrently on forked streams: each has its own list
+            for (auto& s : plans[g].rm) {
+                rej_offs.push_back(rej_total);
+                rej_total = align_up(rej_total + 256 + set_windows(s) * sizeof(int2), 256);
+            }
         offs.push_back(align_up(total, 256));
         total = offs.back() + plans[g].blob.size();
     }
     if (hipMalloc(&ge.blob, std::max<size_t>(total, 256)) != hipSuccess) return fail(h, BM_E_NOMEM, "graph tables");
+    if (mode == BM_SURROGATE) {
+        if (hipMalloc(&ge.rej, std::max<size_t>(rej_total, 256)) != hipSuccess)
+            return fail(h, BM_E_NOMEM, "graph reject lists (%zu bytes)", rej_total);
+        size_t k = 0;
+        for (auto& gp : plans)
+            for (auto& s : gp.rm) {
+                char* base = (char*)ge.rej + rej_offs[k++];
+                s.rej_count = (unsigned long long*)base;
+                s.rej_list = (int2*)(base + 256);
+            }
+    }
     for (size_t g = 0; g < groups.size(); ++g) {
         if ((r = check(h, hipMemcpy((char*)ge.blob + offs[g], plans[g].blob.data(), plans[g].blob.size(),
                                     hipMemcpyHostToDevice), "graph table upload")))
@@ -826,10 +875,12 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
         // fork: each distinct L on its own capture stream; a y pass stays on
         // the stream of the x pass of the same L, after it
         if ((lr = check(h, hipEventRecord(h->fork_ev, c0), "fork"))) break;
+        // (more distinct sizes than capture streams, possible with block windows,
+        // share streams and run one after another on them)
         std::map<int, int> lane_of_L;
         for (auto& s : gp.rm)
             if (!lane_of_L.count(s.L)) {
-                const int k = (int)lane_of_L.size();
+                const int k = (int)lane_of_L.size() % kMaxForks;
                 lane_of_L[s.L] = k;
             }
         for (auto& kv : lane_of_L)
@@ -1001,7 +1052,7 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
         const size_t o_gamma = carve((size_t)chunk * kLen * sizeof(float2));
         const size_t o_labels = carve((size_t)chunk * sizeof(float));
         const size_t o_list = carve((size_t)chunk * sizeof(int2));
-        const size_t o_count = carve(sizeof(int));
+        const size_t o_count = carve(sizeof(unsigned long long));
         const size_t o_fj = carve(sizeof(bm::FftJob));
         const size_t o_fp = carve(2 * sizeof(int));
         const size_t o_rj = carve(kMaxJobs * sizeof(bm::RmJob));
@@ -1069,12 +1120,12 @@ bm_status bosmusic_surrogate_dataset(bosmusic_t h, int64_t first_line, int64_t c
             rb.stats = nullptr;
             rb.tmpl = h->tmpl[kLabelL];
             int2* list = (int2*)(h->ds + o_list);
-            int* dcount = (int*)(h->ds + o_count);
+            unsigned long long* dcount = (unsigned long long*)(h->ds + o_count);
             const int grid = std::max(1, std::min(8 * h->cu_count, (n + bm::kGatherBlock - 1) / bm::kGatherBlock));
             if ((r = check(h, bm::launch_gen_lines(lines, first_line + c0, n, seed, st), "training lines")) ||
                 (r = check(h, bm::launch_analytic(fb, st), "analytic")) ||
                 (r = check(h, bm::launch_label_entries(list, n, st), "label windows")) ||
-                (r = check(h, bm::launch_fill_int(dcount, 1, n, st), "label count")) ||
+                (r = check(h, bm::launch_fill_u64(dcount, 1, (unsigned long long)n, st), "label count")) ||
                 (r = check(h, bm::launch_rootmusic_gather(kLabelL, rb, list, dcount, grid, st), "labels")) ||
                 (r = check(h, bm::launch_train_features(gamma, n, labels, X + c0 * bm::kMlpIn, T + c0 * bm::kMlpOut,
                                                         st),
@@ -1318,7 +1369,7 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
             release(h);
             return fail(nullptr, BM_E_NOMEM, "surrogate parameters");
         }
-        for (int L = 2; L <= bm::kMaxL; ++L) make_template(L, h->tmpl[L]);
+        for (int L = 2; L <= bm::kMaxBlockL; ++L) make_template(L, h->tmpl[L]);
         if (cfg->tune_cache) h->tune_path = cfg->tune_cache;
         load_tune_cache(h);
         *out = h;

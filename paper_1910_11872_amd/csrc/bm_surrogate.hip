@@ -36,6 +36,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
 constexpr int kPowerSteps = 6;
+constexpr float kEigVecTol = 1e-5f;   // bound on sin(angle) between the iterate and the top eigenvector
 constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps for the signal root
 constexpr int kPredictStride = 4;     // one network prediction per this many windows
 static_assert(kSurBlock / kPredictStride == 16 * (kSurBlock / 64), "one 16-window MLP tile per wave");
@@ -163,6 +164,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
 #pragma unroll
     for (int i = 0; i < L; ++i) v[i] = v0[i];
     float lam = 1.f;                        // |T v| of the last step: lambda_1 of the trace-1 T
+    float rho = 0.f, res2 = 1.f;            // Rayleigh quotient and squared residual before it
     for (int it = 0; it < kPowerSteps; ++it) {
         float y[L];
 #pragma unroll
@@ -172,6 +174,17 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
             for (int j = 0; j < L; ++j) acc = fmaf(T.at(i, j), v[j], acc);
             y[i] = acc;
         }
+        if (it == kPowerSteps - 1) {
+            rho = 0.f;
+#pragma unroll
+            for (int i = 0; i < L; ++i) rho = fmaf(v[i], y[i], rho);
+            res2 = 0.f;
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const float r = fmaf(-rho, v[i], y[i]);
+                res2 = fmaf(r, r, res2);
+            }
+        }
         float n2 = 0.f;
 #pragma unroll
         for (int i = 0; i < L; ++i) n2 = fmaf(y[i], y[i], n2);
@@ -180,6 +193,20 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
 #pragma unroll
         for (int i = 0; i < L; ++i) v[i] = y[i] * in;
     }
+    // lam = |T v| <= lambda_1 and lambda_2 <= tr T - lambda_1 = 1 - lambda_1, so
+    // lam (2 + d) > 1 + d proves lambda_2 < lambda_1 / (1 + d): the signal
+    // subspace is determined.  Windows it does not prove (low SNR, lambda_1
+    // near half the trace) go to the plain path, which decides exactly.
+    if (!(lam * (2.f + kDegenRel) > 1.f + kDegenRel)) return false;
+    // The power iteration must also have converged, or its polynomial is not the
+    // window's: with the Rayleigh quotient rho and residual r of the vector before
+    // the last step, the angle theta to the top eigenvector obeys sin theta <=
+    // |r| / (rho - lambda_2) <= |r| / (2 rho - 1) (lambda_2 <= 1 - lambda_1 <=
+    // 1 - rho), and the last step only shrinks it.  Accept sin theta <= 1e-5:
+    // windows whose two largest eigenvalues are close (two tones of nearly
+    // equal power) converge slowly and go to the plain path.
+    const float gap = 2.f * rho - 1.f;
+    if (!(gap > 0.f && res2 <= (kEigVecTol * gap) * (kEigVecTol * gap))) return false;
     // MUSIC null spectrum 1 - |u1^H a(w)|^2 / L at the prediction
     float dot = 0.f;
 #pragma unroll
@@ -196,7 +223,7 @@ __device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, i
     float c1w, s1w;
     guess_direction(ar[L], ai[L], c1w, s1w);
     double zr, zi, rr = 0.0, ri = 0.0;
-    pair_start(c1w, s1w, lam, K, zr, zi);
+    pair_start<L>(v, c1w, s1w, zr, zi);
     pair_newton32<n>(ar, ai, zr, zi, kCertIters32, nullptr);
     if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, nullptr)) return false;
     if (!certified_root<L>(ar, ai, zr, zi, rr, ri)) return false;
@@ -314,14 +341,14 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
     }
     // compact the rejected windows: one atomic per wave
     const unsigned long long mask = __ballot(reject);
-    int slot = 0;
+    unsigned long long slot = 0;
     if (mask) {
         const int lane = t & 63;
         const int leader = __ffsll((long long)mask) - 1;
-        int basei = 0;
-        if (lane == leader) basei = atomicAdd(S.reject_count, __popcll(mask));
+        unsigned long long basei = 0;
+        if (lane == leader) basei = atomicAdd(S.reject_count, (unsigned long long)__popcll(mask));
         basei = __shfl(basei, leader);
-        slot = basei + __popcll(mask & ((1ull << lane) - 1ull));
+        slot = basei + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
     }
     if (reject) S.rejects[slot] = make_int2(j, (int)(((unsigned)line << 16) | (unsigned)p));
     else if (inside_line) store_omega(J, line, p, omega, flag);
@@ -699,7 +726,7 @@ __global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(const float* part,
     } else if (kind == 3) wts[2048 + 4096 + o * 64 + i] = bv;             // W3^T
 }
 
-__global__ void fill_int_kernel(int* p, int n, int v) {
+__global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
@@ -764,9 +791,9 @@ hipError_t launch_mlp_reduce_adam(const float* part, int nblocks, float* master,
     return hipGetLastError();
 }
 
-hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s) {
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

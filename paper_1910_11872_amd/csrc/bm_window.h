@@ -53,6 +53,12 @@ constexpr double kPairMateTol = 1e-2;
 constexpr double kCertRemTol = 1e-5;
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
 constexpr int kInverseIters = BM_INVERSE_ITERS;
+// The one-dimensional signal subspace of Eq. 6-11 needs lambda_1 to stand
+// apart: a window with lambda_2 >= lambda_1 / (1 + kDegenRel) has no
+// determined signal eigenvector (two tones of equal power, say) and gets
+// NaN with BM_FLAG_DEGENERATE.  1e-5 is above the resolution of eigenvalues
+// computed in FP32 (a few 1e-7 of the trace).
+constexpr float kDegenRel = 1e-5f;
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -108,11 +114,28 @@ __device__ __forceinline__ void build_T(const Cov<L>& R, Sym<L>& T) {
     }
 }
 
+// Number of eigenvalues of the symmetric tridiagonal matrix (diagonal d,
+// squared off-diagonal e2) above p: the sign changes of the leading principal
+// minors of p I - T (Sturm).
+template <int L>
+__device__ __forceinline__ int sturm_above(const float (&d)[L], const float (&e2)[L], float p) {
+    float q0 = 1.f, q1 = p - d[0];
+    int changes = q1 < 0.f ? 1 : 0;
+#pragma unroll
+    for (int i = 1; i < L; ++i) {
+        const float q2 = fmaf(p - d[i], q1, -e2[i - 1] * q0);
+        changes += ((q2 < 0.f) != (q1 < 0.f)) ? 1 : 0;
+        q0 = q1;
+        q1 = q2;
+    }
+    return changes;
+}
+
 // Eigenvector of the largest eigenvalue of the trace-normalised symmetric T:
 // Householder tridiagonalisation, Newton from above on det(xI - T_tri),
 // shifted inverse iteration on the tridiagonal matrix, back-transformation.
 template <int L>
-__device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int& its, float& lam) {
+__device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int& its, float& lam, bool& degen) {
     float hv[L][L];   // reflector k lives in hv[k][k+1 .. L-1]
     float hb[L];
     float e[L];
@@ -184,6 +207,7 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
     for (int i = 0; i < L - 1; ++i) var = fmaf(2.f * e[i], e[i], var);
     const float ws = mu + fsqrt(var * ((float)(L - 1) / (float)L));
     float x = fminf(fminf(g, 1.f), ws) * 1.00001f + 1e-30f;
+    float last_step = x;                  // no step taken: lambda_1 >= 0 is all that is known
     for (int it = 0; it < kNewtonIters; ++it) {
         ++its;
         float q0 = 1.f, q1 = x - d[0], dq0 = 0.f, dq1 = 1.f;
@@ -197,10 +221,34 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
         const float step = q1 * frcp(dq1);
         if (!finitef(step)) break;
         x -= step;
+        last_step = step;
         // quadratic convergence: a step below 1e-5 x leaves an error of order 1e-10 x
         if (!(fabsf(step) > 1e-5f * x)) break;
     }
     lam = x;
+    // Degenerate signal subspace?  Every eigenvalue is below the Newton iterate,
+    // so its step at x was q/q' = 1 / sum_i 1/(x - lambda_i) >= (x - lambda_1)/L:
+    // lambda_1 >= lo = x_new - (L - 1) |last step|, a bound that also holds when
+    // the iteration stopped on its step limit short of a (nearly) double top
+    // eigenvalue; lambda_1 <= hi = x.  T has trace 1 and no negative
+    // eigenvalue, so lambda_2 <= 1 - lambda_1, and lo (2 + d) > 1 + d already
+    // proves lambda_2 < lambda_1 / (1 + d).  Otherwise Sturm counts decide: at
+    // most one eigenvalue above lo / (1 + d) proves the gap, two above
+    // hi / (1 + d) disprove it, and in between bisection narrows [lo, hi]
+    // around lambda_1 until one of the two holds.
+    degen = false;
+    float lo = x - (float)(L - 1) * fabsf(last_step), hi = x;
+    if (!(lo * (2.f + kDegenRel) > 1.f + kDegenRel)) {
+        constexpr float kInv = 1.f / (1.f + kDegenRel);
+        degen = true;                                 // if 24 halvings cannot decide
+        for (int b = 0; b < 24; ++b) {
+            if (sturm_above<L>(d, e2, lo * kInv) <= 1) { degen = false; break; }
+            if (sturm_above<L>(d, e2, hi * kInv) >= 2) break;
+            const float mid = 0.5f * (lo + hi);
+            if (sturm_above<L>(d, e2, mid) >= 1) lo = mid;
+            else hi = mid;
+        }
+    }
     // (sigma I - T_tri) y = y_prev, LDL^T without pivoting; sigma just above lambda_1
     const float sigma = x * 1.000002f + 1e-30f;
     float y[L];
@@ -247,7 +295,7 @@ __device__ __forceinline__ void top_eigvec_tridiag(Sym<L>& T, float (&v)[L], int
 
 // Same eigenvector by cyclic Jacobi rotations (selectable alternative).
 template <int L>
-__device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int& sweeps, float& lam) {
+__device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int& sweeps, float& lam, bool& degen) {
     float V[L][L];
 #pragma unroll
     for (int i = 0; i < L; ++i)
@@ -291,17 +339,19 @@ __device__ __forceinline__ void top_eigvec_jacobi(Sym<L>& T, float (&v)[L], int&
             }
         }
     }
-    float best = T.a[0][0];
+    float best = T.a[0][0], second = -INFINITY;
 #pragma unroll
     for (int i = 0; i < L; ++i) v[i] = V[i][0];
 #pragma unroll
     for (int k = 1; k < L; ++k) {
         const bool b = T.a[k][k] > best;
+        second = b ? best : fmaxf(second, T.a[k][k]);
         best = b ? T.a[k][k] : best;
 #pragma unroll
         for (int i = 0; i < L; ++i) v[i] = b ? V[i][k] : v[i];
     }
     lam = best;
+    degen = second * (1.f + kDegenRel) >= best;
 }
 
 
@@ -614,16 +664,23 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     // f and T f have equally many zeros inside the unit disk.
     constexpr int m = n - 2;
     const double rho = rin * (1.0 - kCertMargin);
-    double pw[2 * m + 1];
-    pw[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= 2 * m; ++k) pw[k] = pw[k - 1] * rho;
+    // rho^k - rho^{2m-k} = rho^k (1 - rho^{2(m-k)}): ascending powers first, then the
+    // factor descending, without a table of all 2m + 1 powers
     double gr[m], gi[m];
+    double pk = 1.0;
 #pragma unroll
     for (int k = 0; k < m; ++k) {
-        const double w = pw[k] - pw[2 * m - k];
+        gr[k] = pk;
+        pk *= rho;
+    }
+    const double rho2 = rho * rho;
+    double a = rho2;                                  // rho^{2(m-k)} at k = m - 1
+#pragma unroll
+    for (int k = m - 1; k >= 0; --k) {
+        const double w = gr[k] * (1.0 - a);
         gr[k] = fr[k] * w;
         gi[k] = fi[k] * w;
+        a *= rho2;
     }
     return zeros_inside_unit_disk<m - 1>(gr, gi) == L - 2;
     }
@@ -640,13 +697,79 @@ __device__ __forceinline__ void guess_direction(float c1r, float c1i, float& cw,
     sw = ok ? c1i * im : 0.f;
 }
 
-// Start of the pair iteration: the guessed direction (cw, sw) at the radius
-// the signal root typically has, 1 - r ~ 1.6 (1 - lambda_1) / K for K
-// snapshots and lambda_1 the trace-normalised top eigenvalue.
-__device__ __forceinline__ void pair_start(float cw, float sw, float lam, int K, double& zr, double& zi) {
-    const float r0 = fminf(0.9999f, fmaxf(0.9f, 1.f - 1.6f * (1.f - lam) / (float)K));
-    zr = (double)(r0 * cw);
-    zi = (double)(r0 * sw);
+// g(w) = e^{-j w (L-1)/2} B(e^{j w}) and its first two derivatives, where
+// B(z) = sum_i conj(u_i) z^i: on the unit circle the root-MUSIC polynomial is
+// z^{L-1} (L - g(w)^2) (with u = Q v conjugate-symmetric, u_{L-1-i} =
+// conj(u_i), P(z) = L z^{L-1} - B(z)^2), and g is real:
+// g(w) = sqrt2 sum_{i<m} (v_i cos(w s_i) + v_{o+i} sin(w s_i)) (+ v_m for odd L),
+// s_i = i - (L-1)/2, from the real eigenvector v of T.  (hc, hs) = e^{j w / 2}.
+template <int L>
+__device__ __forceinline__ void spectral_g(const float (&v)[L], float hc, float hs, float& g, float& g1, float& g2) {
+    constexpr int m = L / 2;
+    constexpr int o = L - m;
+    // e^{j w s_0}, s_0 = -(L-1)/2, then steps of e^{j w}
+    float er = 1.f, ei = 0.f;
+#pragma unroll
+    for (int k = 0; k < L - 1; ++k) {
+        const float t = er * hc + ei * hs;             // times e^{-j w/2}
+        ei = ei * hc - er * hs;
+        er = t;
+    }
+    const float sr = hc * hc - hs * hs, si = 2.f * hc * hs;   // e^{j w}
+    float a = 0.f, b = 0.f, c = 0.f;
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+        const float s = (float)i - 0.5f * (float)(L - 1);
+        const float x = fmaf(v[i], er, v[o + i] * ei);         // v_i cos + v_{o+i} sin
+        const float y = fmaf(v[o + i], er, -v[i] * ei);        // d/d(ws) of it
+        a += x;
+        b = fmaf(s, y, b);
+        c = fmaf(-s * s, x, c);
+        const float t = er * sr - ei * si;
+        ei = er * si + ei * sr;
+        er = t;
+    }
+    constexpr float kSqrt2 = 1.41421356237309515f;
+    g = kSqrt2 * a;
+    g1 = kSqrt2 * b;
+    g2 = kSqrt2 * c;
+    if (L & 1) g += v[m];
+}
+
+// Start of the signal-root iteration.  The signal root pair straddles the
+// unit circle where |g(w)|^2 nearly reaches L, i.e. at the peak of g^2: one
+// Newton step on (g^2)' = 0 from the guessed direction (cw, sw) moves w to
+// the peak, and there the quadratic model L - g^2 + (g'^2 + g g'') t^2 = 0 of
+// the polynomial at w + j t puts the root at radius e^{-t}.  From this start
+// the FP32 Newton stage of a window at 10 dB usually needs one step and the
+// FP64 stage one more (numpy trials, L = 6 and 8: FP32 steps of a wave's
+// slowest lane 2.9 -> 1.0, FP64 1.7 -> 1.0, against the lag-1 direction at a
+// radius fitted to lambda_1 and K).  Any start is safe: the certificate
+// judges the root found.
+template <int L>
+__device__ __forceinline__ void pair_start(const float (&v)[L], float cw, float sw, double& zr, double& zi) {
+    // e^{j w/2} from e^{j w} (cos(w/2) >= 0)
+    float hc = fsqrt(fmaxf(0.5f * (1.f + cw), 0.f));
+    float hs = hc > 1e-3f ? 0.5f * sw * frcp(hc) : 1.f;
+    if (!(hc > 1e-3f)) hc = 0.f;
+    float g, g1, g2;
+    spectral_g<L>(v, hc, hs, g, g1, g2);
+    // Newton step towards the peak of g^2: d = -(g g') / (g'^2 + g g'')
+    const float h2 = fmaf(g1, g1, g * g2);
+    float d = h2 < 0.f ? -g * g1 * frcp(h2) : 0.f;
+    d = fminf(0.25f, fmaxf(-0.25f, finitef(d) ? d : 0.f));
+    // rotate by e^{j d/2} (|d/2| <= 1/8: two Taylor terms each)
+    const float x = 0.5f * d, x2 = x * x;
+    const float rc = fmaf(x2, fmaf(x2, 1.f / 24.f, -0.5f), 1.f), rs = x * fmaf(x2, -1.f / 6.f, 1.f);
+    const float nc = hc * rc - hs * rs, ns = hs * rc + hc * rs;
+    spectral_g<L>(v, nc, ns, g, g1, g2);
+    const float hh = fmaf(g1, g1, g * g2);
+    const float dep = fmaxf((float)L - g * g, 0.f);
+    float t = hh < 0.f ? fsqrt(dep * frcp(-hh)) : 0.01f;
+    t = fminf(0.1f, fmaxf(1e-4f, finitef(t) ? t : 0.01f));
+    const float r0 = __expf(-t);
+    zr = (double)(r0 * (nc * nc - ns * ns));
+    zi = (double)(r0 * 2.f * nc * ns);
 }
 
 // Lag sums at start t: S_d = sum_{k<K} g[t+k] conj(g[t+k+d]), d < L, from the
@@ -713,11 +836,10 @@ __device__ __forceinline__ void lag_sums_pair(const float2* g, int q, int K, flo
     }
 }
 
-// Trace-normalised T = Q^H R_fb Q from the covariance; false when R is zero
-// or not finite (no signal subspace).
+// Divide T by its trace; false when the trace is zero or not finite (no
+// signal subspace).
 template <int L>
-__device__ __forceinline__ bool normalised_T(const Cov<L>& R, Sym<L>& T) {
-    build_T<L>(R, T);
+__device__ __forceinline__ bool trace_normalise(Sym<L>& T) {
     float tr = 0.f;
 #pragma unroll
     for (int i = 0; i < L; ++i) tr += T.a[i][i];
@@ -730,34 +852,106 @@ __device__ __forceinline__ bool normalised_T(const Cov<L>& R, Sym<L>& T) {
     return true;
 }
 
+// Trace-normalised T = Q^H R_fb Q from the covariance; false when R is zero
+// or not finite (no signal subspace).
+template <int L>
+__device__ __forceinline__ bool normalised_T(const Cov<L>& R, Sym<L>& T) {
+    build_T<L>(R, T);
+    return trace_normalise<L>(T);
+}
+
+// T = Q^H R_fb Q summed straight from the snapshots s_k (Eq. 4), without the
+// complex covariance.  Q satisfies J conj(Q) = Q, so Q^H J conj(R) J Q =
+// conj(Q^H R Q) and T = Re(Q^H R Q) = sum_k (a_k a_k^T + b_k b_k^T) with
+// a_k + j b_k = Q^H s_k: for i < m = L/2, (Q^H s)_i = (s_i + s_{L-1-i})/sqrt2,
+// (Q^H s)_{o+i} = -j (s_i - s_{L-1-i})/sqrt2, o = L - m, and for odd L
+// (Q^H s)_m = s_m.  The common factor sqrt2 is left in (y = sqrt2 Q^H s), which
+// scales T by 2; the trace normalisation removes it.  `snap(k, i)` returns
+// s_k[i].  About half the work of the complex upper triangle plus build_T,
+// and no complex L x L array in registers.
+template <int L, typename F>
+__device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T) {
+    constexpr int m = L / 2;
+    constexpr int o = L - m;
+    constexpr float kSqrt2 = 1.41421356237309515f;
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = i; j < L; ++j) T.a[i][j] = 0.f;
+    // one snapshot at a time: unrolled, the loads of all snapshots would be
+    // hoisted and held in registers
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+        float2 v[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = snap(k, i);
+        float a[L], b[L];
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            const float2 p = v[i], q = v[L - 1 - i];
+            a[i] = p.x + q.x;
+            b[i] = p.y + q.y;
+            a[o + i] = p.y - q.y;         // -j (p - q) = (p.y - q.y) - j (p.x - q.x)
+            b[o + i] = q.x - p.x;
+        }
+        if (L & 1) {
+            a[m] = kSqrt2 * v[m].x;
+            b[m] = kSqrt2 * v[m].y;
+        }
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int j = i; j < L; ++j) T.a[i][j] = fmaf(a[i], a[j], fmaf(b[i], b[j], T.a[i][j]));
+    }
+}
+
 // Plain root-MUSIC frequency of one window from its covariance (paper
-// Sec. 3, Eq. 6-15): eigen-split, polynomial, all roots, pair selection,
-// FP64 pair polish.  omega stays NaN and BM_FLAG_UNDEFINED is set when the
-// covariance is zero or not finite.
+// Sec. 3, Eq. 6-15): eigen-split, polynomial, the certified pair or all
+// roots, pair selection, FP64 pair polish.  omega stays NaN with
+// BM_FLAG_UNDEFINED when the covariance is zero or not finite, and with
+// BM_FLAG_DEGENERATE when its signal subspace is not determined.
+template <int L, bool JACOBI>
+__device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tmpl, bool full_roots, int K,
+                                               float wprev, float& omega, unsigned& flag, LaneStats& ls);
+
 template <int L, bool JACOBI>
 __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots, int K,
-                                             float& omega, unsigned& flag, LaneStats& ls) {
-    constexpr int n = 2 * L - 2;
+                                             float wprev, float& omega, unsigned& flag, LaneStats& ls) {
     Sym<L> T;
     if (!normalised_T<L>(R, T)) {
         flag |= BM_FLAG_UNDEFINED;
         return;
     }
+    window_omega_T<L, JACOBI>(T, tmpl, full_roots, K, wprev, omega, flag, ls);
+}
+
+// The same from the trace-normalised real symmetric T of the window.
+template <int L, bool JACOBI>
+__device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tmpl, bool full_roots, int K,
+                                               float wprev, float& omega, unsigned& flag, LaneStats& ls) {
+    constexpr int n = 2 * L - 2;
     ls.counted += 1;
     // ---- signal subspace (Eq. 6-11) ------------------------------------
     float v[L];
     float lam = 1.f;
-    if (JACOBI) top_eigvec_jacobi<L>(T, v, ls.eig_its, lam);
-    else top_eigvec_tridiag<L>(T, v, ls.eig_its, lam);
+    bool degen = false;
+    if (JACOBI) top_eigvec_jacobi<L>(T, v, ls.eig_its, lam, degen);
+    else top_eigvec_tridiag<L>(T, v, ls.eig_its, lam, degen);
+    if (degen) {
+        flag |= BM_FLAG_DEGENERATE;
+        return;
+    }
     float ur[L], ui[L];
     signal_vector<L>(v, ur, ui);
     // ---- polynomial coefficients (Eq. 12-14) -----------------------------
     float ar[n + 1], ai[n + 1];
     poly_coeffs<L>(ur, ui, ar, ai);
 
-    // frequency guess from the lag-1 coefficient c_1
+    // frequency guess from the lag-1 coefficient c_1, or, with the temporal
+    // warm start, the previous frame's frequency at this pixel
     float sw0, cw0;
-    guess_direction(ar[L], ai[L], cw0, sw0);
+    if (finitef(wprev)) __sincosf(wprev, &sw0, &cw0);
+    else guess_direction(ar[L], ai[L], cw0, sw0);
 
     // ---- certified pair ---------------------------------------------------
     // FP64 Newton (with the mate divided out) for the signal root from the
@@ -767,7 +961,7 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     bool cert = false;
     if (!full_roots) {
         double zr0, zi0, rr = 0.0, ri = 0.0;
-        pair_start(cw0, sw0, lam, K, zr0, zi0);
+        pair_start<L>(v, cw0, sw0, zr0, zi0);
         pair_newton32<n>(ar, ai, zr0, zi0, kCertIters32, &ls.pair_its32);
         cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, &ls.pair_its) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
         if (cert) omega = atan2f((float)ri, (float)rr);

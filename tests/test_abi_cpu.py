@@ -83,8 +83,8 @@ def test_struct_layout_matches_compiled_header(tmp_path):
 
 def test_struct_layout_matches_header():
     pkg, _ = _lib()
-    # bosmusic_frame: pointer, 3 x int32, int64, 2 x int32, uint32, 4 pointers
-    assert ctypes.sizeof(pkg.bosmusic_frame) == 80
+    # bosmusic_frame: pointer, 3 x int32, int64, 2 x int32, uint32, 6 pointers
+    assert ctypes.sizeof(pkg.bosmusic_frame) == 96
     assert pkg.bosmusic_frame.row_stride.offset == 24
     assert pkg.bosmusic_frame.omega_x.offset == 48
     assert ctypes.sizeof(pkg.bosmusic_config) == 32
@@ -138,3 +138,46 @@ def test_integrate_refuses_maps_not_row_major():
         pkg.bosmusic_integrate_many(None, [(wx, wy_t, 2, 2, 0.0, 0.0, phi)])
     with pytest.raises(ValueError):
         pkg.bosmusic_integrate(None, wx, None, 2, 0, 0.0, 0.0, torch.zeros(6, 5))   # phi must be FP64
+
+
+def test_frame_outputs_checked_for_dtype_shape_and_device():
+    """The kernels store 4-byte omega/phase values and flag bytes into caller buffers:
+    the binding refuses any other dtype (a float16 map would take out-of-bounds stores),
+    shape or layout, and host tensors (the C ABI takes device pointers), before any
+    library call."""
+    import torch
+    import paper_1910_11872_amd as pkg
+    H, W = 6, 40
+    fr = torch.zeros(H, W)
+    ok32 = torch.zeros(H, W)
+    bad = [dict(omega_x=torch.zeros(H, W, dtype=torch.float16)),
+           dict(omega_x=torch.zeros(H, W, dtype=torch.bfloat16)),
+           dict(omega_x=torch.zeros(H, W, dtype=torch.float64)),
+           dict(omega_y=torch.zeros(W, H).t()),
+           dict(omega_y=torch.zeros(H, W + 1)),
+           dict(flags=torch.zeros(H, W, dtype=torch.int32)),
+           dict(phase=torch.zeros(H, W, dtype=torch.float16))]
+    for kw in bad:
+        spec = pkg.FrameSpec(fr, 4, 16, pkg.BM_DIR_X | pkg.BM_DIR_Y, **{"omega_x": ok32, "omega_y": ok32, **kw})
+        with pytest.raises(ValueError):
+            pkg._marshal(spec)
+    # correct dtypes and shapes, but host memory: refused as well
+    spec = pkg.FrameSpec(fr, 4, 16, pkg.BM_DIR_X, omega_x=ok32, flags=torch.zeros(H, W, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="GPU"):
+        pkg._marshal(spec)
+    with pytest.raises(ValueError, match="GPU"):
+        pkg.bosmusic_integrate(None, ok32, None, 2, 0, 0.0, 0.0, torch.zeros(H, W, dtype=torch.float64))
+
+
+def test_surrogate_buffers_checked():
+    import torch
+    import paper_1910_11872_amd as pkg
+    X = torch.zeros(64, 32)
+    with pytest.raises(ValueError):
+        pkg.bosmusic_surrogate_forward(None, X, torch.zeros(64, 2, dtype=torch.float16))
+    with pytest.raises(ValueError):
+        pkg.bosmusic_surrogate_forward(None, X, torch.zeros(64, 3))
+    with pytest.raises(ValueError):
+        pkg.bosmusic_surrogate_grad(None, X, torch.zeros(64, 2), torch.zeros(100))
+    with pytest.raises(ValueError, match="GPU"):
+        pkg.bosmusic_surrogate_forward(None, X, torch.zeros(64, 2))

@@ -198,3 +198,35 @@ def test_every_analytic_kernel_variant_in_one_batch(bm, torch):
         rows = [0, H - 1]
         compare_omega(got[3 * k][rows], oracle_rows(imgs[k], rows, L, N), f"variant batch {W}")
     d.close()
+
+
+def test_cfg3_full_batch_one_graph_replay_sampled(bm, torch):
+    """The whole uneven batch (64 frames, 512x512 .. 2048x1536, L = 4, 6, 8, N = 2L + 8) in
+    one cached hipGraph, replayed: sampled rows and columns of every 21st frame against the
+    oracle, and the replay equal to the first launch bit for bit."""
+    from parity_util import compare_omega, oracle_cols, oracle_rows
+    frames = [wl.cfg3_frame(k) for k in range(64)]
+    px = sum(f.width * f.height for f in frames)
+    d = bm.Demodulator(0, max_width=2048, max_height=1536, graph=True, max_batch_pixels=px)
+    imgs = [torch.from_numpy(f.data).cuda() for f in frames]
+    outs = [(torch.empty(i.shape, device="cuda"), torch.empty(i.shape, device="cuda")) for i in imgs]
+    specs = [bm.FrameSpec(i, f.L, f.N, 3, o[0], o[1]) for i, f, o in zip(imgs, frames, outs)]
+    bm.bosmusic_demodulate(d.h, specs)             # capture and first launch
+    torch.cuda.synchronize()
+    first = [(a.clone(), b.clone()) for a, b in outs]
+    for a, b in outs:
+        a.fill_(3.0)
+        b.fill_(3.0)
+    bm.bosmusic_demodulate(d.h, specs)             # replay
+    torch.cuda.synchronize()
+    for (a, b), (fa, fb) in zip(outs, first):
+        assert torch.equal(torch.nan_to_num(a, 9.0), torch.nan_to_num(fa, 9.0))
+        assert torch.equal(torch.nan_to_num(b, 9.0), torch.nan_to_num(fb, 9.0))
+    for k in (0, 21, 42, 63):
+        f = frames[k]
+        gx, gy = outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()
+        rows = list(range(5, f.height, f.height // 3))
+        cols = list(range(9, f.width, f.width // 3))
+        compare_omega(gx[rows], oracle_rows(f.data, rows, f.L, f.N), f"cfg3 graph k{k} x")
+        compare_omega(gy[:, cols].T, oracle_cols(f.data, cols, f.L, f.N), f"cfg3 graph k{k} y")
+    d.close()

@@ -190,3 +190,97 @@ def test_block_phase_of_a_plane_wave(bm, torch):
     with pytest.raises(bm.BosmusicError):
         d.demodulate(dev(torch, g), 6, 6, "x", block=True, phase=True)     # phase needs both directions
     d.close()
+
+
+BIG_CASES = [
+    # (W, H, M, dtype, snr): the paper's odd windows above 8 x 8, to the 17 x 17 of its table
+    (220, 24, 9, np.float32, 5.0),
+    (240, 28, 11, np.float16, 0.0),
+    (200, 30, 13, np.float64, 8.0),
+    (256, 32, 15, np.uint8, 10.0),
+    (231, 34, 17, np.float32, 3.0),      # 231 = 3 * 7 * 11: the row DFT takes radix-7 and -11 passes
+]
+
+
+@pytest.mark.parametrize("W,H,M,dt,snr", BIG_CASES)
+def test_big_block_windows_match_oracle(bm, torch, W, H, M, dt, snr):
+    d = bm.Demodulator(0, max_width=1024, max_height=1024, stats=True)
+    img = wl.random_frame(W, H, seed=W + M, dtype=dt, snr_db=snr)
+    gx, gy = d.demodulate(dev(torch, img), M, M, "xy", block=True)
+    torch.cuda.synchronize()
+    st = d.stats()
+    ox, oy = oracle.demodulate_block(img, M)
+    print("x", compare_omega(gx.cpu().numpy(), ox, f"block x {W}x{H} M{M}"))
+    print("y", compare_omega(gy.cpu().numpy(), oy, f"block y {W}x{H} M{M}"))
+    print(f"M{M}: certified {st['sur_accepted']} of {st['windows']}")
+    assert st["windows"] == 2 * (W - M + 1) * (H - M + 1)
+    d.close()
+
+
+def test_block_paper_simulation_shape_11x11(bm, torch):
+    """The paper's simulation (Sec. 4): 512 x 512 at 0 dB with L = 5, i.e. an 11 x 11
+    window; sampled rows against the oracle on the rows around them."""
+    d = bm.Demodulator(0, max_width=512, max_height=512)
+    img = wl.random_frame(512, 512, seed=78, snr_db=0.0)
+    gx, gy = d.demodulate(dev(torch, img), 11, 11, "xy", block=True)
+    torch.cuda.synchronize()
+    gxn, gyn = gx.cpu().numpy(), gy.cpu().numpy()
+    assert np.isfinite(gxn).sum() == 502 * 502
+    for r in (5, 97, 256, 431, 506):
+        sub = img[r - 5:r + 6]
+        ox, oy = oracle.demodulate_block(sub, 11)
+        compare_omega(gxn[r], ox[5], f"11x11 x row {r}")
+        compare_omega(gyn[r], oy[5], f"11x11 y row {r}")
+    d.close()
+
+
+def test_big_block_plane_waves_exact_and_phase(bm, torch):
+    d = bm.Demodulator(0, max_width=512, max_height=512)
+    W, H = 200, 60
+    for M in (9, 15):
+        for (wx, wy, a) in [(0.7, -0.4, 0.3), (-2.5, 1.9, -1.2)]:
+            g = wl.complex_tone(W, H, wx, wy, alpha=a).astype(np.complex64)
+            gx, gy, ph = d.demodulate(dev(torch, g), M, M, "xy", block=True, phase=True)
+            torch.cuda.synchronize()
+            gx, gy, ph = gx.cpu().numpy(), gy.cpu().numpy(), ph.cpu().numpy()
+            assert np.isfinite(gx).sum() == (H - M + 1) * (W - M + 1)
+            assert np.nanmax(np.abs(wrap(gx - wx))) < 2e-5 and np.nanmax(np.abs(wrap(gy - wy))) < 2e-5
+            y, x = np.mgrid[0:H, 0:W]
+            v = np.isfinite(ph)
+            assert np.max(np.abs(wrap(ph[v] - (a + wx * x + wy * y)[v]))) < 1e-4
+    d.close()
+
+
+def test_big_block_certified_agrees_with_all_roots_and_phase(bm, torch):
+    img_np = wl.random_frame(220, 30, seed=9, snr_db=2.0)
+    img = dev(torch, img_np)
+    dc = bm.Demodulator(0, max_width=512, max_height=512, stats=True)
+    df = bm.Demodulator(0, max_width=512, max_height=512, full_roots=True)
+    a = dc.demodulate(img, 11, 11, "xy", block=True, phase=True)
+    b = df.demodulate(img, 11, 11, "xy", block=True)
+    torch.cuda.synchronize()
+    for u, v in zip(a[:2], b):
+        compare_omega(u.cpu().numpy(), v.cpu().numpy(), "11x11 certified vs all roots")
+    st = dc.stats()
+    assert st["sur_accepted"] + st["sur_rejected"] == st["windows"] > 0
+    ox, oy = oracle.demodulate_block(img_np, 11)
+    ref = oracle.block_phase(img_np, 11, ox, oy)
+    got = a[2].cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    v = np.isfinite(ref)
+    assert np.quantile(np.abs(wrap(got[v] - ref[v])), 0.999) <= 1e-4
+    dc.close()
+    df.close()
+
+
+def test_big_block_argument_checks(bm, torch):
+    d = bm.Demodulator(0, max_width=256, max_height=256)
+    img = dev(torch, wl.random_frame(128, 40, seed=1))
+    for M in (10, 16, 19):                 # above 8 x 8 only odd sizes up to 17
+        with pytest.raises(bm.BosmusicError) as ei:
+            d.demodulate(img, M, M, "xy", block=True)
+        assert ei.value.status == bm.BM_E_INVALID_ARG
+    with pytest.raises(bm.BosmusicError) as ei:
+        d.demodulate(img, 9, 9, "xy")     # line windows stay at L <= 8
+    assert ei.value.status == bm.BM_E_INVALID_ARG
+    d.close()

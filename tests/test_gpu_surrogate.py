@@ -43,9 +43,19 @@ def test_mlp_forward_matches_oracle(bm, torch):
     ref = S.forward(p, X, quantize=True, fp32_acc=True)["Y"]
     err = np.abs(Y - ref)
     scale = np.max(np.abs(ref))
-    # equal up to bfloat16 rounding decisions taken on FP32 sums in another order
-    assert np.quantile(err, 0.99) < 2e-3 * scale, np.quantile(err, 0.99)
-    assert err.max() < 3e-2 * scale, err.max()
+    # Equal up to FP32 rounding, except where an activation lies so near a bfloat16 rounding
+    # boundary that FP32 sums taken in another order (the matrix cores), or the kernel's erf
+    # (Abramowitz-Stegun 7.1.26, |error| < 1.5e-7), round it the other way: one bfloat16 unit
+    # (2^-8 relative) in one hidden value.  Emulating that on the CPU (FP32 sums in reverse
+    # order, erf perturbed by 1.5e-7) flips 2e-4 of the first layer's activations; the output
+    # error is then below 6e-8 of the output scale for 99% of the samples, 1e-4 of it for
+    # all but 0.1% and 5e-4 of it at most.  The bounds below leave a margin of 10 over that.
+    per_sample = err.max(axis=1)
+    print(f"mlp forward: p99 {np.quantile(err, 0.99) / scale:.2e} max {err.max() / scale:.2e} of scale, "
+          f"samples over 1e-4: {np.mean(per_sample > 1e-4 * scale):.4f}")
+    assert np.quantile(err, 0.99) < 1e-6 * scale, np.quantile(err, 0.99)
+    assert np.mean(per_sample > 1e-4 * scale) < 1e-2
+    assert err.max() < 5e-3 * scale, err.max()
     d.close()
 
 
@@ -96,6 +106,84 @@ def test_surrogate_graph_replays_match_eager(bm, torch):
     graph.close()
 
 
+def test_surrogate_graph_with_two_L_matches_eager(bm, torch):
+    """A surrogate batch with two covariance sizes: in a graph the two sets run on forked
+    capture streams at the same time, each with its own reject list; every replay equals
+    the eager call (the sets run one after another there) bit for bit."""
+    eager = bm.Demodulator(0, max_width=1024, max_height=1024)
+    graph = bm.Demodulator(0, max_width=1024, max_height=1024, graph=True)
+    p = S.init_params(4)               # untrained: many windows go to the fallback lists
+    for h in (eager.h, graph.h):
+        bm.bosmusic_surrogate_load(h, p)
+        bm.bosmusic_surrogate_config(h, 0.25, 0)
+    shapes = [(600, 64, 8, 32, 6.0), (520, 72, 6, 24, 4.0), (400, 48, 8, 32, 12.0)]
+    imgs, outs, specs = [], [], []
+    for k, (W, H, L, N, snr) in enumerate(shapes):
+        img = torch.from_numpy(wl.random_frame(W, H, seed=40 + k, snr_db=snr)).cuda()
+        wx = torch.empty((H, W), device="cuda")
+        wy = torch.empty((H, W), device="cuda")
+        imgs.append(img)
+        outs.append((wx, wy))
+        specs.append(bm.FrameSpec(img, L, N, 3, wx, wy))
+    bm.bosmusic_demodulate(eager.h, specs, bm.BM_SURROGATE)
+    torch.cuda.synchronize()
+    ref = [(a.clone(), b.clone()) for a, b in outs]
+    for k, (W, H, L, N, snr) in enumerate(shapes):
+        ox, oy = oracle.demodulate(imgs[k].cpu().numpy(), L, N, "xy")
+        for got, o in zip(ref[k], (ox, oy)):
+            assert rms_vs_oracle(got.cpu().numpy(), o)[0] <= 2e-3
+    for rep in range(3):
+        for a, b in outs:
+            a.fill_(5.0)
+            b.fill_(5.0)
+        bm.bosmusic_demodulate(graph.h, specs, bm.BM_SURROGATE)
+        torch.cuda.synchronize()
+        x = torch.zeros(1, device="cuda") + 1.0       # eager work between replays
+        torch.cuda.synchronize()
+        for (a, b), (ra, rb) in zip(outs, ref):
+            assert torch.equal(torch.nan_to_num(a, 9.0), torch.nan_to_num(ra, 9.0)), rep
+            assert torch.equal(torch.nan_to_num(b, 9.0), torch.nan_to_num(rb, 9.0)), rep
+    eager.close()
+    graph.close()
+
+
+def test_surrogate_graph_replay_after_larger_eager_call(bm, torch):
+    """A graph captured on a small frame keeps its own reject list: capturing a second graph
+    for a larger frame on the same handle, and eager calls between the replays, change
+    nothing in the first graph's replays."""
+    d = bm.Demodulator(0, max_width=2048, max_height=1024, graph=True)
+    e = bm.Demodulator(0, max_width=2048, max_height=1024)
+    p = S.init_params(6)
+    for h in (d.h, e.h):
+        bm.bosmusic_surrogate_load(h, p)
+        bm.bosmusic_surrogate_config(h, 0.25, 0)
+    small = torch.from_numpy(wl.random_frame(300, 40, seed=61, snr_db=5.0)).cuda()
+    wx = torch.empty((40, 300), device="cuda")
+    wy = torch.empty((40, 300), device="cuda")
+    spec = [bm.FrameSpec(small, 8, 32, 3, wx, wy)]
+    bm.bosmusic_demodulate(e.h, spec, bm.BM_SURROGATE)
+    torch.cuda.synchronize()
+    ref = (wx.clone(), wy.clone())
+    bm.bosmusic_demodulate(d.h, spec, bm.BM_SURROGATE)          # capture
+    torch.cuda.synchronize()
+    big = torch.from_numpy(wl.random_frame(2048, 512, seed=62, snr_db=3.0)).cuda()
+    bx = torch.empty((512, 2048), device="cuda")
+    by = torch.empty((512, 2048), device="cuda")
+    for rep in range(2):
+        # a second graph on the same handle, for a batch with more windows
+        bm.bosmusic_demodulate(d.h, [bm.FrameSpec(big, 8, 32, 3, bx, by)], bm.BM_SURROGATE)
+        # and an eager call on another handle in between
+        bm.bosmusic_demodulate(e.h, [bm.FrameSpec(big, 8, 32, 3, bx, by)], bm.BM_SURROGATE)
+        wx.fill_(5.0)
+        wy.fill_(5.0)
+        bm.bosmusic_demodulate(d.h, spec, bm.BM_SURROGATE)      # replay
+        torch.cuda.synchronize()
+        assert torch.equal(torch.nan_to_num(wx, 9.0), torch.nan_to_num(ref[0], 9.0)), rep
+        assert torch.equal(torch.nan_to_num(wy, 9.0), torch.nan_to_num(ref[1], 9.0)), rep
+    d.close()
+    e.close()
+
+
 def test_surrogate_requires_parameters_and_long_windows(bm, torch):
     d = bm.Demodulator(0, max_width=256, max_height=256)
     img = torch.from_numpy(wl.random_frame(128, 32, seed=1)).cuda()
@@ -106,4 +194,33 @@ def test_surrogate_requires_parameters_and_long_windows(bm, torch):
     with pytest.raises(bm.BosmusicError) as ei:
         d.demodulate(img, 4, 12, "x", mode=bm.BM_SURROGATE)
     assert ei.value.status == bm.BM_E_UNSUPPORTED
+    d.close()
+
+
+def test_surrogate_on_a_full_4096_fp16_frame(bm, torch):
+    """The surrogate workload's inference shape: one 4096 x 4096 FP16 frame, x and y, L = 8,
+    N = 32, with a network trained on the GPU for a few seconds; sampled rows and columns
+    within RMS 2e-3 of the oracle (accepted windows reproduce the plain selection)."""
+    from parity_util import oracle_cols, oracle_rows
+    d = bm.Demodulator(0, max_width=4096, max_height=4096, stats=True)
+    bm.bosmusic_surrogate_load(d.h, S.init_params(8))
+    n = 1 << 18
+    X = torch.empty((n, 32), device="cuda")
+    T = torch.empty((n, 2), device="cuda")
+    bm.bosmusic_surrogate_dataset(d.h, 0, X, T, None, seed=44)
+    bm.bosmusic_surrogate_train(d.h, X, T, batch=4096, steps=1500, lr=2e-3)
+    bm.bosmusic_surrogate_config(d.h, 0.25, 0)
+    f = wl.cfg4_frame(7)
+    wx, wy = d.demodulate(torch.from_numpy(f.data).cuda(), 8, 32, "xy", mode=bm.BM_SURROGATE)
+    torch.cuda.synchronize()
+    st = d.stats()
+    gx, gy = wx.cpu().numpy(), wy.cpu().numpy()
+    rows = [11, 1024, 2047, 3100, 4090]
+    cols = [13, 2049, 4001]
+    rx, _ = rms_vs_oracle(gx[rows], oracle_rows(f.data, rows, 8, 32))
+    ry, _ = rms_vs_oracle(gy[:, cols].T, oracle_cols(f.data, cols, 8, 32))
+    acc = st["sur_accepted"] / max(1, st["sur_accepted"] + st["sur_rejected"])
+    print(f"4096^2 surrogate: rms x {rx:.2e} y {ry:.2e}, accepted {acc:.5f}")
+    assert rx <= 2e-3 and ry <= 2e-3
+    assert acc > 0.9
     d.close()

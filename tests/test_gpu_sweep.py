@@ -1,6 +1,6 @@
 """Window-size sweep on the GPU (the paper's window-size study, Sec. 4, Table 1): the paper's
 simulation shape (512 x 512 at 0 dB), a field whose frequency varies smoothly, line windows
-N = 4 .. 64 and block windows 2 .. 8.  The frequency and the integrated phase are compared with
+N = 4 .. 64 and block windows 2 .. 8, then the paper's odd sizes to 17 x 17.  The frequency and the integrated phase are compared with
 the field's own; the frequency error must be U-shaped in N (noise-limited small windows, model-
 limited large ones).  The table is printed for the record."""
 import numpy as np
@@ -47,7 +47,7 @@ def test_window_size_sweep_is_u_shaped(bm, torch):
         ep = p - (true - true[a])
         ep = ep[np.isfinite(ep)]
         rows.append((N, L, ex, ey, float(np.sqrt(np.mean((ep - ep.mean()) ** 2)))))
-    for M in range(2, 9):
+    for M in list(range(2, 9)) + [9, 11, 13, 15, 17]:
         bx, by = d.demodulate(img, M, M, "xy", block=True)
         torch.cuda.synchronize()
         c = -(M // 2) + (M - 1) / 2
@@ -58,8 +58,10 @@ def test_window_size_sweep_is_u_shaped(bm, torch):
     for r in rows:
         print(f"  {str(r[0]):9s} {r[1]:3d}   {r[2]:.4f}          {r[3]:.4f}          {r[4]:.4f}")
     line = [r for r in rows if isinstance(r[0], int)]
-    for k in (2, 3):
-        e = [r[k] for r in line]
-        i = int(np.argmin(e))
-        assert 0 < i < len(e) - 1, e
-        assert e[0] > 1.3 * e[i] and e[-1] > 1.3 * e[i], e
+    block = [r for r in rows if not isinstance(r[0], int)]
+    for group in (line, block):
+        for k in (2, 3):
+            e = [r[k] for r in group]
+            i = int(np.argmin(e))
+            assert 0 < i < len(e) - 1, e
+            assert e[0] > 1.3 * e[i] and e[-1] > 1.3 * e[i], e

@@ -150,10 +150,12 @@ def cfg3(frames=range(64)) -> list:
     return [cfg3_frame(k) for k in frames]
 
 
-def cfg4_frame(t: int, size: int = 4096) -> Frame:
+def cfg4_frame(t: int, size: int = 4096, dtype=np.float16) -> Frame:
+    """Frame t of the FP16 series; dtype=np.float64 gives the same frame before its
+    FP16 storage rounding (same seed, same noise draws)."""
     W = H = size
     w_t = 16.0 * 16.0 ** (t / 15.0)
-    img, twx, twy = erf_fringe(W, H, 1.0 / 8.0, 45.0, 6.0, H / 2.0, w_t, 10.0, 4000 + t, np.float16)
+    img, twx, twy = erf_fringe(W, H, 1.0 / 8.0, 45.0, 6.0, H / 2.0, w_t, 10.0, 4000 + t, dtype)
     return Frame(img, L=8, N=32, dirs="xy", truth_wx=twx, truth_wy=twy,
                  meta={"cfg": 4, "t": t, "w": w_t})
 
