@@ -297,6 +297,25 @@ bm_status bosmusic_surrogate_step(bosmusic_t h, const float* grad, float lr, voi
 bm_status bosmusic_surrogate_train(bosmusic_t h, const float* X, const float* T, int64_t M, int32_t batch,
                                    int32_t steps, float lr, float* losses, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * integration of bosmusic_integrate, with the same arguments and results
+ * (the same kernels), but without a handle and without allocating anything.
+ * It runs on the current HIP device; the anchor column it needs lives in a
+ * fixed device array of BOSMUSIC_NOALLOC_MAX_HEIGHT doubles (512 KiB) that the
+ * library keeps on every device it runs on until the process ends, looked up
+ * on the first call on each device.  height > BOSMUSIC_NOALLOC_MAX_HEIGHT, or
+ * any other argument bosmusic_integrate would refuse, returns
+ * BM_E_INVALID_ARG before anything is enqueued; the detail is in
+ * bosmusic_last_error(NULL).  Every call on one device uses that device's one
+ * array (each call writes the rows it reads, nothing carries over): calls that
+ * overlap on one device, on different streams or threads, race on it and
+ * must be ordered by the caller. */
+#define BOSMUSIC_NOALLOC_MAX_HEIGHT 65536
+bm_status bosmusic_integrate_noalloc(const float* omega_x, const float* omega_y, int32_t width, int32_t height,
+                                     int32_t Nx, int32_t Ny, double carrier_x, double carrier_y, double* phi,
+                                     void* stream);
+
 /* One map of a batched integration: the arguments of bosmusic_integrate. */
 typedef struct {
     const float* omega_x;   /* width*height, required */

@@ -33,7 +33,7 @@ ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "
                  "bosmusic_version", "bosmusic_surrogate_load", "bosmusic_surrogate_save",
                  "bosmusic_surrogate_config", "bosmusic_surrogate_forward", "bosmusic_surrogate_dataset",
                  "bosmusic_surrogate_grad", "bosmusic_surrogate_step", "bosmusic_surrogate_train",
-                 "bosmusic_integrate_many")
+                 "bosmusic_integrate_many", "bosmusic_integrate_noalloc")
 MLP_PARAMS = 6402
 
 
@@ -99,6 +99,9 @@ def lib():
         L.bosmusic_surrogate_config.restype = c_int32
         L.bosmusic_surrogate_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
         L.bosmusic_surrogate_forward.restype = c_int32
+        L.bosmusic_integrate_noalloc.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                                 c_double, c_double, c_void_p, c_void_p]
+        L.bosmusic_integrate_noalloc.restype = c_int32
         L.bosmusic_integrate_many.argtypes = [c_void_p, POINTER(bosmusic_integrate_job), c_int32, c_void_p]
         L.bosmusic_integrate_many.restype = c_int32
         L.bosmusic_surrogate_dataset.argtypes = [c_void_p, c_int64, c_int64, ctypes.c_uint64, c_void_p, c_void_p,
@@ -254,6 +257,17 @@ def bosmusic_integrate(h, omega_x, omega_y, Nx: int, Ny: int, carrier_x: float, 
     wy = c_void_p(omega_y.data_ptr()) if omega_y is not None else c_void_p()
     _check(lib().bosmusic_integrate(h, c_void_p(omega_x.data_ptr()), wy, W, H, Nx, Ny, carrier_x, carrier_y,
                                     c_void_p(phi.data_ptr()), _stream_ptr(stream)), h)
+
+
+def bosmusic_integrate_noalloc(omega_x, omega_y, Nx: int, Ny: int, carrier_x: float, carrier_y: float, phi,
+                               stream=None) -> None:
+    """bosmusic_integrate without a handle and without any allocation, on the current device
+    (the maps' device must be current); height <= BOSMUSIC_NOALLOC_MAX_HEIGHT."""
+    _map_check(omega_x, omega_y, phi)
+    H, W = omega_x.shape
+    wy = c_void_p(omega_y.data_ptr()) if omega_y is not None else c_void_p()
+    _check(lib().bosmusic_integrate_noalloc(c_void_p(omega_x.data_ptr()), wy, W, H, Nx, Ny, carrier_x, carrier_y,
+                                            c_void_p(phi.data_ptr()), _stream_ptr(stream)), None)
 
 
 def bosmusic_autotune(h, L: int, N: int, width: int = 1024, lines: int = 512, stream=None) -> float:

@@ -211,6 +211,23 @@ hipError_t launch_integrate(const float* wx, const float* wy, int W, int H, int 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free entry point: the anchor column of one
+// integration, kNoAllocMaxHeight doubles, held on every device the library
+// runs on until the process ends.  In host code `noalloc_anchor` names a
+// host-side stand-in, not device memory: host code uses only the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double noalloc_anchor[kNoAllocMaxHeight];
+
+hipError_t noalloc_anchor_address(double** ptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_anchor));
+    if (e != hipSuccess) return e;
+    *ptr = static_cast<double*>(p);
+    return hipSuccess;
+}
+
 hipError_t integrate_set_attributes() {
     hipError_t e = hipFuncSetAttribute((const void*)rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kMaxFFT * (int)(sizeof(double) + sizeof(float)));

@@ -263,6 +263,11 @@ struct IntJob {
 hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njobs, int total_rows, int max_w,
                                  double* anchors, hipStream_t s);
 
+// Allocation-free integration: the anchor column lives in a fixed device array
+// of kNoAllocMaxHeight doubles (512 KiB); its address on the current device.
+constexpr int kNoAllocMaxHeight = BOSMUSIC_NOALLOC_MAX_HEIGHT;
+hipError_t noalloc_anchor_address(double** ptr);
+
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KiB; call
 // once per device with that device current.
 hipError_t analytic_set_attributes();

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,7 +101,9 @@ struct bosmusic_s {
 
 namespace {
 
-thread_local std::string g_create_error;
+// Detail of the last failed handle-less call on this thread (create, the
+// allocation-free integration): a fixed buffer, so that reporting allocates nothing.
+thread_local char g_create_error[512];
 
 bm_status fail(bosmusic_s* h, bm_status st, const char* fmt, ...) {
     char buf[512];
@@ -109,7 +112,7 @@ bm_status fail(bosmusic_s* h, bm_status st, const char* fmt, ...) {
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
     if (h) h->err = buf;
-    else g_create_error = buf;
+    else std::memcpy(g_create_error, buf, sizeof(buf));
     return st;
 }
 
@@ -1300,7 +1303,7 @@ const char* bosmusic_status_string(bm_status s) {
     }
 }
 
-const char* bosmusic_last_error(bosmusic_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+const char* bosmusic_last_error(bosmusic_t h) { return h ? h->err.c_str() : g_create_error; }
 
 bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
     try {
@@ -1461,6 +1464,57 @@ bm_status bosmusic_integrate(bosmusic_t h, const float* omega_x, const float* om
     } catch (...) {
         return fail(h, BM_E_NOMEM, "host exception in integrate");
     }
+}
+
+}  // extern "C"
+
+namespace {
+
+// Per device: the address of the fixed anchor scratch, looked up once with that
+// device current (each device holds its own copy of the array at its own address).
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_anchor[kNoAllocDevices] = {};
+
+}  // namespace
+
+extern "C" {
+
+bm_status bosmusic_integrate_noalloc(const float* omega_x, const float* omega_y, int32_t width, int32_t height,
+                                     int32_t Nx, int32_t Ny, double carrier_x, double carrier_y, double* phi,
+                                     void* stream) {
+    g_create_error[0] = 0;
+    if (!omega_x || !phi) return fail(nullptr, BM_E_INVALID_ARG, "omega_x/phi is NULL");
+    if (width < 1 || height < 1 || width > bm::kMaxFFT)
+        return fail(nullptr, BM_E_INVALID_ARG, "size %dx%d (1 <= width <= %d)", width, height, bm::kMaxFFT);
+    if (height > bm::kNoAllocMaxHeight)
+        return fail(nullptr, BM_E_INVALID_ARG, "height %d exceeds the fixed scratch of %d rows", height,
+                    bm::kNoAllocMaxHeight);
+    if (Nx < 1 || Nx > bm::kMaxN || (omega_y && (Ny < 1 || Ny > bm::kMaxN)))
+        return fail(nullptr, BM_E_INVALID_ARG, "Nx/Ny");
+    if (!std::isfinite(carrier_x) || !std::isfinite(carrier_y)) return fail(nullptr, BM_E_INVALID_ARG, "carrier");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, BM_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(nullptr, BM_E_UNSUPPORTED, "device %d", dev);
+    double* anchor = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_anchor[dev]) {
+            // set-up on the first call on this device (the current one)
+            double* p = nullptr;
+            if ((e = bm::noalloc_anchor_address(&p)) != hipSuccess || !p)
+                return fail(nullptr, BM_E_DEVICE, "hipGetSymbolAddress of the scratch: %s", hipGetErrorString(e));
+            if ((e = bm::integrate_set_attributes()) != hipSuccess)
+                return fail(nullptr, BM_E_DEVICE, "kernel attributes: %s", hipGetErrorString(e));
+            g_noalloc_anchor[dev] = p;
+        }
+        anchor = g_noalloc_anchor[dev];
+    }
+    e = bm::launch_integrate(omega_x, omega_y, width, height, Nx, Ny, carrier_x, carrier_y, anchor, phi,
+                             (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, BM_E_DEVICE, "integrate: %s", hipGetErrorString(e));
+    return BM_OK;
 }
 
 bm_status bosmusic_integrate_many(bosmusic_t h, const bosmusic_integrate_job* jobs, int32_t n, void* stream) {
