@@ -9,8 +9,10 @@ integration of both maps to phase.  One step = one bosmusic_demodulate call
 over all frames plus the integration of every frame, inputs resident in HBM.
 The same frames are timed twice: with the plain root-MUSIC path (the line's
 `value`) and with the learned surrogate (an MLP trained on the GPU on 10M
-method-generated windows first) plus its pseudospectrum check, certificate
-and plain fallback (the `surrogate` object).
+method-generated windows first), whose prediction seeds a power iteration for
+the signal eigenvector that is accepted once proven converged and within the
+MUSIC main lobe of the prediction, the plain eigen-split otherwise (the
+`surrogate` object).
 
 Prints one JSON line: Mpixel/s (frames*W*H / step time) of each mode, the
 roofline of each mode's dominant kernel (algorithmic flops per launch / its
@@ -110,29 +112,27 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     select = 11 * n
     fp32 = common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(n)
     fp64 = pair_iters * pair_newton_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
-    return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
+    return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64, "eigen": house + newton_f + inverse}
 
 
-def surrogate_flops_per_window(L: int, N: int) -> dict:
-    """Algorithmic flops of one window of the surrogate kernel, counted up to
-    the first point where a window can be rejected (so a lower bound for the
-    accepted ones): features and the MLP of one window in four (matrix-core
-    flops kept apart, GELU as its A&S erf: 16 flops), lag sums, the real transform, the power
-    iteration, the polynomial, three FP64 Newton steps for the signal root
-    and the certificate.  Transcendentals count as one flop."""
-    K = N - L + 1
-    n = 2 * L - 2
-    stride = 4                                        # one network prediction per 4 windows
+def surrogate_flops_per_window(L: int, N: int, power_steps: float) -> dict:
+    """Algorithmic flops of the surrogate kernel's own work on one window: the features
+    and the MLP of one window in 32 (matrix-core flops kept apart, GELU as its A&S
+    erf: 16 flops), and for a window the prediction serves the steering vector of the
+    prediction, tr T^2, `power_steps` power steps (T v; the Rayleigh quotient, residual
+    and bounds from the second step on), the normalisation and the null spectrum.
+    Transcendentals count as one flop."""
+    stride = 32                                       # one network prediction per 32 windows
     feat = (4 * N + 16 * 6 + 10) / stride
     mlp_mfma = 2 * (32 * 64 + 64 * 64 + 64 * 2) / stride
-    mlp_valu = (2 * 64 * (16 + 1) + 2) / stride
-    lag = K * L * 8
-    build_t = 3 * L * L + L + L * (L + 1) // 2
-    power = 6 * (2 * L * L + 3 * L + 1) + 2 * L
-    coef = 2 * L + 8 * L * (L + 1) // 2
-    fp32 = feat + mlp_valu + lag + build_t + power + coef + 20
-    fp64 = 3 * pair_newton_flops(n) + certificate_flops(L)
-    return {"fp32": fp32, "fp64": fp64, "mfma": mlp_mfma, "valu": fp32 + fp64}
+    mlp_valu = (2 * 64 * (16 + 1) + 2) / stride + 1   # + the half-angle sincos of the prediction
+    steer = 6 * (L - 1) + 6 * (L // 2) + 6
+    trace2 = L + 3 * (L * (L - 1) // 2)
+    step = 2 * L * L
+    test = 8 * L + 20
+    power = power_steps * step + max(0.0, power_steps - 1) * test
+    null = 5 * L + 3
+    return {"predict": feat + mlp_valu, "mfma": mlp_mfma, "served": steer + trace2 + power + null}
 
 
 TRAIN_MFMA_FLOPS = 2 * (32 * 64 + 64 * 64 + 64 * 2) * 2 + 2 * 64 * 64   # forward, weight gradients, dH1
@@ -287,8 +287,8 @@ def workload(name, nframes):
                 f"diffusion phase, SNR 10 dB; x and y windows N=32, L=8; FP32 covariance/eigen/rooting, FP64 "
                 f"root polish and phase prefix sums. Plain root-MUSIC (value) vs surrogate MLP 32-64-64-2 "
                 f"(GELU, BF16 MFMA, FP32 accumulate) trained on the GPU on 10M method-generated windows "
-                f"(carrier 1/16-1/4 cyc/px, SNR 0-30 dB, root-MUSIC L=8 N=32 labels) + pseudospectrum check + "
-                f"certificate + root-MUSIC fallback (surrogate)")
+                f"(carrier 1/16-1/4 cyc/px, SNR 0-30 dB, root-MUSIC L=8 N=32 labels) seeding a verified power "
+                f"iteration for the signal eigenvector, plain eigen-split where it does not serve (surrogate)")
     elif name == "exp":
         fr = [wl.exp_frame(i) for i in range(nframes or 19)]
         desc = (f"{len(fr)} time-lapsed 1850x700 8-bit frames (stand-in for the paper's experimental diffusion "
@@ -485,9 +485,16 @@ def main():
             newton = ss["eig_iters"] / nwin
             pair_its32 = ss.get("pair_iters32", 0) / nwin
             if surrogate:
-                # the fallback windows (the surrogate kernel's own work is modelled below)
-                iters = ss["root_iters"] / nwin
-                pair_its, cert = ss["pair_iters"] / nwin, 0.0
+                # served and fallback windows share everything but the eigenvector; the
+                # certified fraction and the Aberth iterations come from a plain counting pass
+                pdem = make(bm.BM_PLAIN, stats=True)
+                bm.bosmusic_demodulate(pdem.h, sub, bm.BM_PLAIN, stream)
+                ps = pdem.stats(reset=True)
+                pdem.close()
+                pn = max(1, ps["windows"])
+                newton = ps["eig_iters"] / pn
+                iters = ps["root_iters"] / max(1, ps["sur_rejected"])
+                pair_its, cert = ss["pair_iters"] / nwin, ps["sur_accepted"] / pn
             elif args.full_roots:
                 iters = ss["root_iters"] / nwin
                 pair_its, cert = 0.0, 0.0
@@ -508,21 +515,25 @@ def main():
                      "root_iters": round(iters, 2), "windows_per_step": wins}
             if surrogate:
                 acc, rej = ss["sur_accepted"], ss["sur_rejected"]
-                frac_rej = rej / max(1, acc + rej)
-                sfl = surrogate_flops_per_window(L, fr[idx[0]].N)
-                flops_step += wins * (sfl["valu"] + frac_rej * fl["total"])
+                frac_acc = acc / max(1, acc + rej)
+                # power steps of the served windows (the counter also holds the fallback
+                # windows' eigenvalue Newton steps: at most `newton` each)
+                psteps = max(0.0, ss["eig_iters"] - rej * newton) / max(1, acc)
+                sfl = surrogate_flops_per_window(L, fr[idx[0]].N, psteps)
+                per_win = fl["total"] - frac_acc * fl["eigen"] + sfl["predict"] + frac_acc * sfl["served"]
+                flops_step += wins * per_win
                 mfma_step += wins * sfl["mfma"]
-                entry.update({"surrogate_valu_flop_per_window": sfl["valu"],
+                entry.update({"flop_per_window": round(per_win), "power_steps": round(psteps, 2),
                               "surrogate_mfma_flop_per_window": sfl["mfma"],
-                              "accepted_fraction": round(1 - frac_rej, 5)})
+                              "accepted_fraction": round(frac_acc, 5), "certified_fraction": round(cert, 5)})
             else:
                 entry.update({"pair_iters32": round(pair_its32, 2), "pair_iters": round(pair_its, 2),
                               "certified_fraction": round(cert, 5)})
                 flops_step += fl["total"] * wins
             per_L[L] = entry
-        rm_s = st["rm_time_ns"] / 1e9 / args.steps      # root-MUSIC (or surrogate + fallback) time per step
+        rm_s = st["rm_time_ns"] / 1e9 / args.steps      # root-MUSIC (or surrogate) launch time per step
         achieved = flops_step / rm_s
-        kname = "surrogate_kernel + rootmusic_gather_kernel fallback" if surrogate else "rootmusic_kernel"
+        kname = "surrogate_kernel" if surrogate else "rootmusic_kernel"
         traffic = None
         if (args.workload == "cfg2" and not (args.block or args.full_roots or surrogate)):
             traffic = TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 * 2 * total_px / max(1, st["rm_launches"] // args.steps)

@@ -151,13 +151,18 @@ typedef struct {
 
 typedef struct {
     uint64_t windows;       /* windows demodulated since the last reset (in BM_PLAIN:
-                               sur_accepted + sur_rejected + the BM_FLAG_DEGENERATE ones) */
-    uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI) */
+                               sur_accepted + sur_rejected + the BM_FLAG_DEGENERATE ones;
+                               in BM_SURROGATE: sur_accepted + sur_rejected) */
+    uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI);
+                               BM_SURROGATE: power steps of the accepted windows plus
+                               Newton steps of the rest */
     uint64_t root_iters;    /* sum over windows of simultaneous root iterations (all-roots windows) */
     uint64_t polish_fail;   /* windows whose FP64 pair polish did not converge */
-    uint64_t sur_accepted;  /* BM_SURROGATE: windows whose surrogate estimate was accepted;
+    uint64_t sur_accepted;  /* BM_SURROGATE: windows whose signal eigenvector came from the
+                               prediction (proven converged, null spectrum at the
+                               prediction <= tau);
                                BM_PLAIN: windows finished by the certified pair */
-    uint64_t sur_rejected;  /* BM_SURROGATE: windows sent to the plain fallback;
+    uint64_t sur_rejected;  /* BM_SURROGATE: windows finished by the plain eigen-split;
                                BM_PLAIN: windows whose roots were all found */
     uint64_t pair_iters;    /* sum over windows of FP64 Newton steps for the signal root
                                (its mate divided out) before the certificate */
@@ -219,19 +224,16 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
  * An MLP 32 -> 64 -> 64 -> 2 (exact-erf GELU) maps the normalised window (16
  * central samples de-rotated by the central sample's phase, divided by the
  * window's RMS magnitude, [Re(16), Im(16)]) to (cos w, sin w); it runs on
- * every fourth window of a line and its estimate w_hat serves that window
- * and its three neighbours.  w_hat seeds a power iteration for the signal
- * eigenvector u1; the window is
- * rejected when the MUSIC null spectrum 1 - |u1^H a(w_hat)|^2 / L at the
- * prediction exceeds tau.  Newton iterations (FP64) for the signal root of
- * the root-MUSIC polynomial (paper Eq. 12), its conjugate-reciprocal mate
- * divided out, start just inside the unit circle at the eigenvector's
- * lag-1 phase; the window is accepted only when the polynomial divides by
- * the pair's factor (z - z_in)(z - 1/conj z_in) and a Schur-Cohn count on
- * the quotient shows that no other root lies as near the unit circle: the
- * accepted pair is then the pair the plain path selects (Sec. 3, Eq. 15),
- * and w = arg(z1 + z2) as there.  Every other window is finished by the
- * plain path, so the output equals the plain output up to rounding.
+ * one window in 16 of a line and its estimate w_hat serves those 16.  w_hat
+ * seeds a power iteration on the window's FB-averaged covariance (in its
+ * real form, paper Eq. 6-11) for the signal eigenvector u1, accepted once an
+ * a-posteriori bound proves it within 1e-5 rad of the top eigenvector and
+ * the MUSIC null spectrum 1 - |u1^H a(w_hat)|^2 / L at the prediction is at
+ * most tau.  Any other window takes the plain eigen-split.  From u1 on every
+ * window follows the plain path (polynomial, Eq. 12-14; certified pair or
+ * all roots; w = arg(z1 + z2), Eq. 15), so the output equals the plain
+ * output up to the eigenvector bound and rounding.  Line windows with
+ * L <= 8 and N >= 16 only.
  * Parameters are FP32, in this order, row-major: W1[32][64], b1[64],
  * W2[64][64], b2[64], W3[64][2], b3[2] (6402 floats); the kernels use
  * bfloat16 copies (round to nearest even) and FP32 accumulation. */

@@ -209,14 +209,13 @@ constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpH
 struct SurBatch {
     RmBatch rm;            // the windows (jobs of one L)
     MlpWeights w;
-    int2* rejects;         // windows sent to the plain fallback (capacity: every window of rm)
-    unsigned long long* reject_count;
     int predictor;         // 0: MLP, 1: lag-1 phase of the covariance (no learning)
-    float tau;             // acceptance bound on the null spectrum at the refined frequency
+    float tau;             // acceptance bound on the MUSIC null spectrum at the prediction
 };
 
-// Surrogate pass over every window of b.rm (256 lanes per block, one block
-// per work item); windows it cannot accept are appended to b.rejects.
+// Surrogate pass over every window of b.rm: the line kernel's blocks (256
+// lanes, line_windows_per_block windows, one block per work item); windows
+// the prediction does not serve are finished by the plain eigen-split.
 hipError_t launch_surrogate(int L, const SurBatch& b, hipStream_t s);
 // Y[M x 2] = MLP(X[M x 32]) with the kernel's bfloat16 arithmetic.
 hipError_t launch_mlp_forward(const MlpWeights& w, const float* X, float* Y, int M, hipStream_t s);

@@ -29,7 +29,6 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void* blob = nullptr;  // device job tables referenced by the graph's kernels
-    void* rej = nullptr;   // BM_SURROGATE: reject counters and lists of the graph's sets, one region per set
     uint64_t last_use = 0;
 };
 
@@ -75,9 +74,6 @@ struct bosmusic_s {
     bool sur_loaded = false;
     float sur_tau = 0.25f;
     int sur_predictor = 0;
-    int2* rejects = nullptr;       // eager calls: the sets of a group run one after another on one stream
-    size_t rejects_cap = 0;
-    unsigned long long* reject_count = nullptr;
     // surrogate training
     float* adam_m = nullptr;       // Adam moments (BOSMUSIC_MLP_PARAMS each)
     float* adam_v = nullptr;
@@ -393,9 +389,6 @@ struct RmSet {
     size_t jobs_off = 0, prefix_off = 0;
     bm::RmBatch batch{};
     Tune tune;
-    // BM_SURROGATE: where this set's rejected windows go (capacity set_windows)
-    int2* rej_list = nullptr;
-    unsigned long long* rej_count = nullptr;
 };
 
 struct GroupPlan {
@@ -602,11 +595,11 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
         int nmax = 0;
         for (auto& j : s.jobs) nmax = std::max(nmax, j.N);
         // the surrogate and block-window kernels run 256 lanes (128 for block windows
-        // above 8 x 8), one block per item; line windows take the tuned tile
+        // above 8 x 8), one block per item; plain line windows take the tuned tile
         if (mode == BM_SURROGATE || s.block_win) s.tune = Tune{};
         else s.tune = h->tune[s.L][nmax];
         if (s.block_win) s.tune.block = bm::block_window_lanes(s.L);
-        const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block, mode != BM_SURROGATE && !s.block_win);
+        const int wpb = bm::rootmusic_windows_per_block(s.L, s.tune.block, !s.block_win);
         s.prefix.assign(1, 0);
         for (auto& j : s.jobs) {
             j.bpl = (j.len + wpb - 1) / wpb;
@@ -674,48 +667,15 @@ bm::MlpWeights mlp_weights(const bosmusic_s* h) {
     return w;
 }
 
-// Windows of a set (upper bound on the reject list it can produce).
-size_t set_windows(const RmSet& s) {
-    size_t n = 0;
-    for (auto& j : s.jobs) n += (size_t)j.nlines * (size_t)j.len;
-    return n;
-}
-
-// The eager path's reject list (graphs own theirs).  Growing it waits for the
-// device: work enqueued by earlier eager calls, on any stream, may still use it.
-bm_status ensure_rejects(bosmusic_s* h, size_t n) {
-    if (n <= h->rejects_cap && h->reject_count) return BM_OK;
-    bm_status r;
-    if ((r = check(h, hipDeviceSynchronize(), "sync before growing the reject list"))) return r;
-    (void)hipFree(h->rejects);
-    h->rejects = nullptr;
-    h->rejects_cap = 0;
-    if (!h->reject_count && hipMalloc(&h->reject_count, sizeof(unsigned long long)) != hipSuccess)
-        return fail(h, BM_E_NOMEM, "reject counter");
-    if (hipMalloc(&h->rejects, std::max<size_t>(n, 1) * sizeof(int2)) != hipSuccess)
-        return fail(h, BM_E_NOMEM, "reject list of %zu windows", n);
-    h->rejects_cap = n;
-    return BM_OK;
-}
-
-// Surrogate pass over a set, then the plain path on the windows it rejected,
-// through the set's own reject list.
+// Surrogate pass over a set: every window is finished in the surrogate
+// kernel, by the plain eigen-split where the prediction does not serve.
 bm_status launch_sur(bosmusic_s* h, const RmSet& s, hipStream_t st) {
-    bm_status r;
-    if (!s.rej_list || !s.rej_count) return fail(h, BM_E_DEVICE, "surrogate set without a reject list");
     bm::SurBatch sb;
     sb.rm = s.batch;
     sb.w = mlp_weights(h);
-    sb.rejects = s.rej_list;
-    sb.reject_count = s.rej_count;
     sb.predictor = h->sur_predictor;
     sb.tau = h->sur_tau;
-    if ((r = check(h, bm::launch_fill_u64(s.rej_count, 1, 0ull, st), "reject counter"))) return r;
-    if ((r = check(h, bm::launch_surrogate(s.L, sb, st), "surrogate"))) return r;
-    const size_t cap = set_windows(s);
-    const int grid = (int)std::min<size_t>((size_t)4 * h->cu_count, (cap + bm::kGatherBlock - 1) / bm::kGatherBlock);
-    return check(h, bm::launch_rootmusic_gather(s.L, s.batch, s.rej_list, s.rej_count, std::max(grid, 1), st),
-                 "fallback");
+    return check(h, bm::launch_surrogate(s.L, sb, st), "surrogate");
 }
 
 // Root-MUSIC launch, bracketed by HIP events on the same stream when timing.
@@ -781,16 +741,6 @@ bm_status ensure_upload_buffers(bosmusic_s* h, size_t bytes, hipStream_t st) {
 bm_status run_group_eager(bosmusic_s* h, GroupPlan& gp, hipStream_t st) {
     bm_status r;
     if ((r = ensure_upload_buffers(h, gp.blob.size(), st))) return r;
-    if (gp.mode == BM_SURROGATE) {
-        // the sets run one after another on `st`: they share one list
-        size_t mx = 0;
-        for (auto& s : gp.rm) mx = std::max(mx, set_windows(s));
-        if ((r = ensure_rejects(h, mx))) return r;
-        for (auto& s : gp.rm) {
-            s.rej_list = h->rejects;
-            s.rej_count = h->reject_count;
-        }
-    }
     if (h->pin_pending && (r = check(h, hipEventSynchronize(h->pin_ev), "upload wait"))) return r;
     std::memcpy(h->pin, gp.blob.data(), gp.blob.size());
     if ((r = check(h, hipMemcpyAsync(h->djobs, h->pin, gp.blob.size(), hipMemcpyHostToDevice, st), "job upload")))
@@ -824,7 +774,6 @@ void destroy_graph(GraphEntry& g) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
     (void)hipFree(g.blob);
-    (void)hipFree(g.rej);
     g = GraphEntry{};
 }
 
@@ -834,31 +783,12 @@ bm_status build_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
     std::vector<GroupPlan> plans(groups.size());
     size_t total = 0;
     std::vector<size_t> offs;
-    size_t rej_total = 0;
-    std::vector<size_t> rej_offs;   // per set of every group: counter, then its list
     for (size_t g = 0; g < groups.size(); ++g) {
         if ((r = plan_group(h, frames, groups[g].first, groups[g].second, mode, plans[g]))) return r;
-        if (mode == BM_SURROGATE)
-            // sets of different L run concurrently on forked streams: each has its own list
-            for (auto& s : plans[g].rm) {
-                rej_offs.push_back(rej_total);
-                rej_total = align_up(rej_total + 256 + set_windows(s) * sizeof(int2), 256);
-            }
         offs.push_back(align_up(total, 256));
         total = offs.back() + plans[g].blob.size();
     }
     if (hipMalloc(&ge.blob, std::max<size_t>(total, 256)) != hipSuccess) return fail(h, BM_E_NOMEM, "graph tables");
-    if (mode == BM_SURROGATE) {
-        if (hipMalloc(&ge.rej, std::max<size_t>(rej_total, 256)) != hipSuccess)
-            return fail(h, BM_E_NOMEM, "graph reject lists (%zu bytes)", rej_total);
-        size_t k = 0;
-        for (auto& gp : plans)
-            for (auto& s : gp.rm) {
-                char* base = (char*)ge.rej + rej_offs[k++];
-                s.rej_count = (unsigned long long*)base;
-                s.rej_list = (int2*)(base + 256);
-            }
-    }
     for (size_t g = 0; g < groups.size(); ++g) {
         if ((r = check(h, hipMemcpy((char*)ge.blob + offs[g], plans[g].blob.data(), plans[g].blob.size(),
                                     hipMemcpyHostToDevice), "graph table upload")))
@@ -1258,8 +1188,6 @@ void release(bosmusic_s* h) {
     (void)hipFree(h->djobs);
     (void)hipFree(h->sur_master);
     (void)hipFree(h->sur_w);
-    (void)hipFree(h->rejects);
-    (void)hipFree(h->reject_count);
     (void)hipFree(h->adam_m);
     (void)hipFree(h->adam_v);
     (void)hipFree(h->part);

@@ -1,29 +1,29 @@
 // Learned surrogate of the per-window frequency estimate (an addition to the
 // paper's method), with the paper's root-MUSIC as the check and the fallback.
 //
-// surrogate_kernel: one block per work item of the plain kernel's grid.
-//   1. stage the analytic signal of BLOCK + N - 1 samples in LDS;
-//   2. features of every window: 16 central samples, de-rotated by the phase
-//      of the central sample, divided by the window's RMS magnitude, as
+// surrogate_kernel: the plain line kernel's blocks (two window starts per
+// lane, lag sums shared through LDS), with a cheaper route to the signal
+// subspace where the network's estimate allows it:
+//   1. stage the analytic signal of the block in LDS;
+//   2. features of every 8th window: 16 central samples, de-rotated by the
+//      phase of the central sample, divided by the window's RMS magnitude, as
 //      bfloat16 [Re(16), Im(16)];
 //   3. MLP 32 -> GELU 64 -> GELU 64 -> 2 on the matrix cores: every GEMM is
 //      a set of v_mfma_f32_16x16x32_bf16 tiles with FP32 accumulation, in
 //      transposed form (W^T X^T) so that the bfloat16 weights are the A
 //      operand and each layer's output tile is the next layer's B operand
 //      after one LDS round trip; omega_hat = atan2 of the two outputs;
-//   4. lag sums and covariance as in the plain kernel, the real symmetric
-//      T = Q^H R_fb Q, its top eigenvector by power iteration seeded with the
-//      steering vector of omega_hat, and the MUSIC null spectrum at
-//      omega_hat (reject above tau);
-//   5. Newton iterations in FP64 for the signal root of the root-MUSIC
-//      polynomial (paper Eq. 12), its mate divided out, started at the
-//      frequency of the eigenvector's lag-1 coefficient; accept when the
-//      root's pair divides the polynomial and a Schur-Cohn count on the
-//      quotient shows no other root as near the unit circle, so that the
-//      pair is the one the plain path selects: omega = arg(z1 + z2) as in the
-//      plain path; otherwise the window goes to the reject list, which the
-//      plain gather kernel finishes.
-#include "bm_window.h"
+//   4. lag sums, covariance and the real symmetric T = Q^H R_fb Q as in the
+//      plain kernel; the top eigenvector by power iteration from the steering
+//      vector of omega_hat, accepted once an a-posteriori bound proves it
+//      within 1e-5 of the eigenvector and the MUSIC null spectrum at
+//      omega_hat is below tau; otherwise the plain eigen-split (Householder,
+//      Newton, inverse iteration);
+//   5. the plain path's polynomial, certified root pair (or all roots) and
+//      omega = arg(z1 + z2) either way.
+// A better prediction needs fewer power steps; a window the prediction does
+// not serve is computed by the plain path in the same lane.
+#include "bm_rootmusic_kernels.h"
 
 #include <algorithm>
 
@@ -35,11 +35,16 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
-constexpr int kPowerSteps = 6;
+constexpr int kSurMinSteps = 2;       // power steps before the first convergence test
+constexpr int kSurMaxSteps = 8;       // then at most this many in all
 constexpr float kEigVecTol = 1e-5f;   // bound on sin(angle) between the iterate and the top eigenvector
-constexpr int kRefineIters = 8;       // at most this many FP64 Newton steps for the signal root
-constexpr int kPredictStride = 4;     // one network prediction per this many windows
-static_assert(kSurBlock / kPredictStride == 16 * (kSurBlock / 64), "one 16-window MLP tile per wave");
+constexpr int kPredictStride = 32;    // one network prediction per this many windows
+// predictions per block, in 16-window MLP tiles
+constexpr int kPredictions = (2 * kSurBlock / kPredictStride + 15) / 16 * 16;
+constexpr int kPredictTiles = kPredictions / 16;
+static_assert(kPredictions <= 16 * (kSurBlock / 64), "at most one output tile per wave");
+static_assert(kSurBlock % kPredictions == 0 && 16 % (kSurBlock / kPredictions) == 0,
+              "lanes per prediction: a power of two that divides the 16 feature samples");
 
 // C(16 x 16) += A(16 x 32) B(32 x 16) on one wave.  A(i, k) = a[i*lda + k],
 // B(k, j) = b[j*ldb + k]; both 16-byte aligned with k contiguous.  Lane l
@@ -82,10 +87,21 @@ struct alignas(16) MlpSmem {
     float b1[kMlpHidden], b2[kMlpHidden], b3[4];
 };
 
+// 16-byte copies (n16 of them); both pointers 16-byte aligned.
+__device__ __forceinline__ void copy16(const __bf16* src, __bf16* dst, int n16, int nthreads) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    for (int i = threadIdx.x; i < n16; i += nthreads) d4[i] = s4[i];
+}
+
+// The weights into LDS (the bfloat16 matrices 16-byte aligned in device memory).
 __device__ void load_weights(const MlpWeights& w, MlpSmem& s, int nthreads) {
-    for (int i = threadIdx.x; i < kMlpHidden * kMlpIn; i += nthreads) s.w1t[i] = w.w1t[i];
-    for (int i = threadIdx.x; i < kMlpHidden * kMlpHidden; i += nthreads) s.w2t[i] = w.w2t[i];
-    for (int i = threadIdx.x; i < 16 * kMlpHidden; i += nthreads) s.w3t[i] = w.w3t[i];
+    copy16(w.w1t, s.w1t, kMlpHidden * kMlpIn / 8, nthreads);
+    copy16(w.w2t, s.w2t, kMlpHidden * kMlpHidden / 8, nthreads);
+    // W3^T: its two rows, and zeros for the padding rows of the 16-row tile
+    copy16(w.w3t, s.w3t, kMlpOut * kMlpHidden / 8, nthreads);
+    for (int i = threadIdx.x; i < (16 - kMlpOut) * kMlpHidden / 8; i += nthreads)
+        reinterpret_cast<uint4*>(s.w3t + kMlpOut * kMlpHidden)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = threadIdx.x; i < kMlpHidden; i += nthreads) {
         s.b1[i] = w.b1[i];
         s.b2[i] = w.b2[i];
@@ -93,8 +109,17 @@ __device__ void load_weights(const MlpWeights& w, MlpSmem& s, int nthreads) {
     if (threadIdx.x < 2) s.b3[threadIdx.x] = w.b3[threadIdx.x];
 }
 
-// MLP on one tile of 16 rows of x ([row][32] bf16); h1, h2 are this wave's
-// [16][64] bf16 scratch tiles.  Lanes 0..15 return (y0, y1) of row l.
+// LDS written by this wave is visible to all its lanes: the workgroup-scope
+// fence waits for the wave's own LDS stores; no other wave is waited for.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// MLP on one tile of 16 rows of x ([row][32] bf16, written by this wave or
+// before a block barrier); h1, h2 are this wave's [16][64] bf16 scratch
+// tiles.  Wave-local: no block barrier.  Lanes 0..15 return (y0, y1) of row l.
 __device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __bf16* h1, __bf16* h2) {
     const int l = threadIdx.x & 63;
     const int col = l & 15, rq = (l >> 4) * 4;
@@ -109,7 +134,7 @@ __device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __
         for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b1[hid + q]);
         *reinterpret_cast<bf16x4*>(h1 + col * kMlpHidden + hid) = hv;
     }
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
         floatx4 c = {0.f, 0.f, 0.f, 0.f};
@@ -122,136 +147,99 @@ __device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __
         for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b2[hid + q]);
         *reinterpret_cast<bf16x4*>(h2 + col * kMlpHidden + hid) = hv;
     }
-    __syncthreads();
+    wave_lds_sync();
     floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) c = mfma_tile(s.w3t + 32 * kb, kMlpHidden, h2 + 32 * kb, kMlpHidden, c);
     return make_float2(c[0] + s.b3[0], c[1] + s.b3[1]);
 }
 
-// Real form of the unit steering vector of frequency w under the unitary
-// transform of build_T: v0 = Q^H a(w) e^{-j w (L-1)/2} / sqrt(L).
-template <int L>
-__device__ __forceinline__ void steering_real(float w, float (&v0)[L]) {
-    constexpr int m = L / 2;
-    constexpr int o = L - m;
-    const float sc = 1.41421356237309515f * rsqrtf((float)L);
+// MLP on T tiles of 16 rows of x ([row][32] bf16) by the block's four waves
+// together: wave w computes hidden units 16w .. 16w+15 of every tile in both
+// hidden layers, so each wave takes a quarter of the GELUs; the output layer
+// runs on the first T waves.  h1, h2: [T][16][64] bf16.  Lanes 0..15 of
+// wave j < T write what[16 j + l] = atan2(y1, y0) of row 16 j + l.
+template <int T>
+__device__ __forceinline__ void mlp_block(const MlpSmem& s, const __bf16* x, __bf16* h1, __bf16* h2, float* what) {
+    static_assert(kSurBlock / 64 * 16 == kMlpHidden, "one 16-unit slice of each hidden layer per wave");
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = l & 15, hid = 16 * wv + (l >> 4) * 4;
 #pragma unroll
-    for (int a = 0; a < m; ++a) {
-        float sn, cs;
-        sincosf(w * ((float)a - 0.5f * (float)(L - 1)), &sn, &cs);
-        v0[a] = sc * cs;
-        v0[o + a] = sc * sn;
+    for (int j = 0; j < T; ++j) {
+        floatx4 c = {0.f, 0.f, 0.f, 0.f};
+        c = mfma_tile(s.w1t + 16 * wv * kMlpIn, kMlpIn, x + 16 * j * kMlpIn, kMlpIn, c);
+        bf16x4 hv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b1[hid + q]);
+        *reinterpret_cast<bf16x4*>(h1 + (16 * j + col) * kMlpHidden + hid) = hv;
     }
-    if (L & 1) v0[m] = rsqrtf((float)L);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            c = mfma_tile(s.w2t + 16 * wv * kMlpHidden + 32 * kb, kMlpHidden, h1 + 16 * j * kMlpHidden + 32 * kb,
+                          kMlpHidden, c);
+        bf16x4 hv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b2[hid + q]);
+        *reinterpret_cast<bf16x4*>(h2 + (16 * j + col) * kMlpHidden + hid) = hv;
+    }
+    __syncthreads();
+    if (wv < T) {
+        floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            c = mfma_tile(s.w3t + 32 * kb, kMlpHidden, h2 + 16 * wv * kMlpHidden + 32 * kb, kMlpHidden, c);
+        if (l < 16) what[16 * wv + l] = atan2f(c[1] + s.b3[1], c[0] + s.b3[0]);
+    }
 }
 
-// Refinement of a predicted frequency; true when the estimate is accepted.
-// The estimate is judged by the MUSIC null spectrum at the prediction, then
-// the signal root of the root-MUSIC polynomial (paper Eq. 12) is found by
-// Newton's method in FP64 with its conjugate-reciprocal mate divided out,
-// and the window is accepted only when that pair (z, 1/conj z) is the pair
-// of roots nearest the unit circle, which is the pair the plain path
-// selects (Sec. 3): the polynomial divides by the pair's factor and the
-// quotient has all its inner roots strictly inside |z| < |z_in|.
+// e^{j w / 2} of the lag-1 direction of the covariance (the non-learned
+// predictor): w = arg sum_i R[i][i+1]^*, the phase of the mean lag-1 product.
 template <int L>
-__device__ __forceinline__ bool refine(const Cov<L>& R, float what, float tau, int K, float& omega) {
-    constexpr int n = 2 * L - 2;
-    Sym<L> T;
-    if (!normalised_T<L>(R, T)) return false;
-    float v0[L], v[L];
-    steering_real<L>(what, v0);
+__device__ __forceinline__ void lag1_half_angle(const Cov<L>& R, float& hc, float& hs) {
+    float sr = 0.f, si = 0.f;
 #pragma unroll
-    for (int i = 0; i < L; ++i) v[i] = v0[i];
-    float lam = 1.f;                        // |T v| of the last step: lambda_1 of the trace-1 T
-    float rho = 0.f, res2 = 1.f;            // Rayleigh quotient and squared residual before it
-    for (int it = 0; it < kPowerSteps; ++it) {
-        float y[L];
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            float acc = 0.f;
-#pragma unroll
-            for (int j = 0; j < L; ++j) acc = fmaf(T.at(i, j), v[j], acc);
-            y[i] = acc;
-        }
-        if (it == kPowerSteps - 1) {
-            rho = 0.f;
-#pragma unroll
-            for (int i = 0; i < L; ++i) rho = fmaf(v[i], y[i], rho);
-            res2 = 0.f;
-#pragma unroll
-            for (int i = 0; i < L; ++i) {
-                const float r = fmaf(-rho, v[i], y[i]);
-                res2 = fmaf(r, r, res2);
-            }
-        }
-        float n2 = 0.f;
-#pragma unroll
-        for (int i = 0; i < L; ++i) n2 = fmaf(y[i], y[i], n2);
-        const float in = frsq(n2);
-        lam = n2 * in;
-#pragma unroll
-        for (int i = 0; i < L; ++i) v[i] = y[i] * in;
+    for (int i = 0; i + 1 < L; ++i) {
+        sr += R.re[i][i + 1];
+        si -= R.im[i][i + 1];
     }
-    // lam = |T v| <= lambda_1 and lambda_2 <= tr T - lambda_1 = 1 - lambda_1, so
-    // lam (2 + d) > 1 + d proves lambda_2 < lambda_1 / (1 + d): the signal
-    // subspace is determined.  Windows it does not prove (low SNR, lambda_1
-    // near half the trace) go to the plain path, which decides exactly.
-    if (!(lam * (2.f + kDegenRel) > 1.f + kDegenRel)) return false;
-    // The power iteration must also have converged, or its polynomial is not the
-    // window's: with the Rayleigh quotient rho and residual r of the vector before
-    // the last step, the angle theta to the top eigenvector obeys sin theta <=
-    // |r| / (rho - lambda_2) <= |r| / (2 rho - 1) (lambda_2 <= 1 - lambda_1 <=
-    // 1 - rho), and the last step only shrinks it.  Accept sin theta <= 1e-5:
-    // windows whose two largest eigenvalues are close (two tones of nearly
-    // equal power) converge slowly and go to the plain path.
-    const float gap = 2.f * rho - 1.f;
-    if (!(gap > 0.f && res2 <= (kEigVecTol * gap) * (kEigVecTol * gap))) return false;
-    // MUSIC null spectrum 1 - |u1^H a(w)|^2 / L at the prediction
-    float dot = 0.f;
-#pragma unroll
-    for (int i = 0; i < L; ++i) dot = fmaf(v[i], v0[i], dot);
-    if (!(1.f - dot * dot <= tau)) return false;
-    float ur[L], ui[L];
-    signal_vector<L>(v, ur, ui);
-    float ar[n + 1], ai[n + 1];
-    poly_coeffs<L>(ur, ui, ar, ai);
-    // The signal eigenvector seeded by the prediction now gives a sharper
-    // frequency than the prediction itself: u1[i+1]/u1[i] ~ e^{j w}, so the
-    // lag-1 coefficient c_1 ~ -((L-1)/L) e^{-j w}.  Newton for the signal
-    // root (its mate divided out) starts there.
-    float c1w, s1w;
-    guess_direction(ar[L], ai[L], c1w, s1w);
-    double zr, zi, rr = 0.0, ri = 0.0;
-    pair_start<L>(v, c1w, s1w, zr, zi);
-    pair_newton32<n>(ar, ai, zr, zi, kCertIters32, nullptr);
-    if (!pair_newton<n>(ar, ai, zr, zi, kRefineIters, nullptr)) return false;
-    if (!certified_root<L>(ar, ai, zr, zi, rr, ri)) return false;
-    const float w = atan2f((float)ri, (float)rr);
-    omega = w;
-    return finitef(w);
+    const float m2 = sr * sr + si * si;
+    const bool ok = m2 > 0.f && finitef(m2);
+    const float im = ok ? frsq(m2) : 0.f;
+    const float cw = ok ? sr * im : 1.f, sw = ok ? si * im : 0.f;
+    hc = fsqrt(fmaxf(0.5f * (1.f + cw), 0.f));
+    hs = hc > 1e-3f ? 0.5f * sw * frcp(hc) : 1.f;
+    if (!(hc > 1e-3f)) hc = 0.f;
 }
 
-template <int L>
-__global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
+template <int L, bool STATS>
+__global__ __launch_bounds__(kSurBlock)
+__attribute__((amdgpu_waves_per_eu(STATS ? 1 : 4)))
+void surrogate_kernel(SurBatch S) {
     constexpr int BLOCK = kSurBlock;
-    constexpr int WPB = BLOCK - (L - 1);
-    __shared__ MlpSmem sm;
-    __shared__ float2 sg[BLOCK + kMaxN];
-    constexpr int NP = BLOCK / kPredictStride;     // predictions per block (one MLP tile per wave)
+    constexpr int SPAN = LineSpan<L, BLOCK>::span;
+    constexpr int WPB = LineSpan<L, BLOCK>::wpb;
+    constexpr int ROW = LineSpan<L, BLOCK>::row;
+    constexpr int NP = kPredictions;
+    static_assert(NP * kPredictStride >= SPAN, "the predictions cover the block's windows");
+    __shared__ float2 sg[SPAN + kMaxN];
     __shared__ float what[NP];
-    // x [NP][32] + per-wave h1, h2 [16][64]; later reused for the lag sums
-    constexpr int kXBytes = NP * kMlpIn * 2, kHBytes = 4 * 2 * 16 * kMlpHidden * 2;
-    constexpr int kSBytes = L * BLOCK * 8;
-    constexpr int kUBytes = (kXBytes + kHBytes) > kSBytes ? (kXBytes + kHBytes) : kSBytes;
-    __shared__ alignas(16) unsigned char ubuf[kUBytes];
-    __bf16* xs = reinterpret_cast<__bf16*>(ubuf);
-    float2 (*sS)[BLOCK] = reinterpret_cast<float2 (*)[BLOCK]>(ubuf);
-    const int t = threadIdx.x, wv = t >> 6;
-    __bf16* h1 = reinterpret_cast<__bf16*>(ubuf + kXBytes) + wv * 2 * 16 * kMlpHidden;
-    __bf16* h2 = h1 + 16 * kMlpHidden;
+    // the MLP's weights, features and hidden tiles, later the lag sums
+    constexpr int kWBytes = (int)sizeof(MlpSmem), kXBytes = NP * kMlpIn * 2, kHBytes = 2 * NP * kMlpHidden * 2;
+    constexpr int kSBytes = L * ROW * 8;
+    constexpr int kMBytes = kWBytes + kXBytes + kHBytes;
+    static_assert(kWBytes % 16 == 0, "bfloat16 tiles stay 16-byte aligned");
+    __shared__ alignas(16) unsigned char ubuf[kMBytes > kSBytes ? kMBytes : kSBytes];
+    MlpSmem& sm = *reinterpret_cast<MlpSmem*>(ubuf);
+    __bf16* xs = reinterpret_cast<__bf16*>(ubuf + kWBytes);
+    float2 (*sS)[ROW] = reinterpret_cast<float2 (*)[ROW]>(ubuf);
+    const int t = threadIdx.x;
+    __bf16* h1 = reinterpret_cast<__bf16*>(ubuf + kWBytes + kXBytes);
+    __bf16* h2 = h1 + NP * kMlpHidden;
 
-    load_weights(S.w, sm, BLOCK);
     const RmBatch& B = S.rm;
     const int j = find_job(B.prefix, B.njobs, blockIdx.x);
     const RmJob J = B.jobs[j];
@@ -261,110 +249,101 @@ __global__ __launch_bounds__(kSurBlock) void surrogate_kernel(SurBatch S) {
     const int N = J.N, half = N >> 1, K = N - L + 1, len = J.len;
     const float2* g = J.gamma + (int64_t)line * J.gamma_ls;
     const int base = p0 - half;
-    for (int i = t; i < BLOCK + N - 1; i += BLOCK) {
+    if (S.predictor == 0) load_weights(S.w, sm, BLOCK);
+    for (int i = t; i < SPAN + N - 1; i += BLOCK) {
         const int q = base + i;
         sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    const int p = p0 + t;
-    const bool inside_line = (t < WPB) && (p < len);
-    const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
 
     // ---- features and the MLP ------------------------------------------
-    // The local frequency varies slowly along a line, and the prediction only
-    // seeds the refinement that the certificate then judges, so the network
-    // runs on every kPredictStride-th window: prediction k is made at window
+    // The local frequency varies slowly along a line and the prediction only
+    // seeds the power iteration, so the network runs on every
+    // kPredictStride-th window: prediction k is made at window
     // kPredictStride k + kPredictStride/2 (moved inside the block's valid
-    // windows) and serves the windows kPredictStride k .. kPredictStride k +
-    // kPredictStride - 1.
+    // windows) and serves windows kPredictStride k .. kPredictStride (k+1) - 1.
+    // LPW lanes make the features of one prediction (a share of the energy
+    // sum and 16/LPW of the 16 samples each); the whole block runs the MLP.
     if (S.predictor == 0) {
-        // valid windows of this block: lanes lo .. hi
+        constexpr int LPW = BLOCK / NP, SPL = 16 / LPW;
         const int lo = max(0, half - p0);
         const int hi = min(min(WPB - 1, len - 1 - p0), len - N + half - p0);
-        if (t < NP) {
-            const int pos = min(max(kPredictStride * t + kPredictStride / 2, lo), max(hi, lo));
-            const bool ok0 = hi >= lo;
-            const float2* w = sg + pos;
-            float e = 0.f;
-            for (int k = 0; k < N; ++k) e = fmaf(w[k].x, w[k].x, fmaf(w[k].y, w[k].y, e));
-            const float2 gc = w[half];
-            const float mc = fsqrt(gc.x * gc.x + gc.y * gc.y);
-            const bool ok = ok0 && mc > 0.f && e > 0.f;
-            const float sc = ok ? frcp(mc) * rsqrtf(e / (float)N) : 0.f;
-            const float rc = gc.x * sc, rs = -gc.y * sc;           // conj(gc)/|gc|/rms
+        const int k = t / LPW, q = t % LPW;
+        const int pos = min(max(kPredictStride * k + kPredictStride / 2, lo), max(hi, lo));
+        const float2* w = sg + pos;
+        float e = 0.f;
+        for (int i = q; i < N; i += LPW) e = fmaf(w[i].x, w[i].x, fmaf(w[i].y, w[i].y, e));
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const float2 v = w[half - 8 + k];
-                xs[t * kMlpIn + k] = (__bf16)(v.x * rc - v.y * rs);
-                xs[t * kMlpIn + 16 + k] = (__bf16)(v.x * rs + v.y * rc);
-            }
+        for (int off = 1; off < LPW; off <<= 1) e += __shfl_xor(e, off);
+        const float2 gc = w[half];
+        const float mc = fsqrt(gc.x * gc.x + gc.y * gc.y);
+        const bool ok = hi >= lo && mc > 0.f && e > 0.f;
+        const float sc = ok ? frcp(mc) * frsq(e / (float)N) : 0.f;
+        const float rc = gc.x * sc, rs = -gc.y * sc;               // conj(gc)/|gc|/rms
+#pragma unroll
+        for (int m = 0; m < SPL; ++m) {
+            const int i = q * SPL + m;
+            const float2 v = w[half - 8 + i];
+            xs[k * kMlpIn + i] = (__bf16)(v.x * rc - v.y * rs);
+            xs[k * kMlpIn + 16 + i] = (__bf16)(v.x * rs + v.y * rc);
         }
         __syncthreads();
-        {
-            const int tile = wv;                                   // NP / 16 == number of waves
-            const float2 y = mlp_tile(sm, xs + tile * 16 * kMlpIn, h1, h2);
-            if ((t & 63) < 16) what[tile * 16 + (t & 15)] = atan2f(y.y, y.x);
-        }
+        mlp_block<kPredictTiles>(sm, xs, h1, h2, what);
     }
     __syncthreads();
-    // ---- lag sums (the MLP scratch is dead now: every wave passed the barrier above) ---
-    lag_sums<L, BLOCK>(sg, t, K, sS);
+    // ---- lag sums (the MLP scratch is dead: every wave passed the barrier) ---
+    lag_sums_pair<L, ROW>(sg, 2 * t, K, sS);
     __syncthreads();
 
-    float omega = __builtin_nanf("");
-    unsigned flag = 0;
-    bool reject = false;
-    int acc = 0;
-    if (valid) {
-        Cov<L> R;
+    LaneStats ls;
+#pragma unroll 1
+    for (int r = 0; r < 2; ++r) {
+        const int s = r * BLOCK + t;
+        const int p = p0 + s;
+        const bool inside_line = (s < WPB) && (p < len);
+        const bool valid = inside_line && (p - half >= 0) && (p - half + N <= len);
+        float omega = __builtin_nanf("");
+        unsigned flag = 0;
+        if (valid) {
+            Cov<L> R;
 #pragma unroll
-        for (int i = 0; i < L; ++i)
+            for (int i = 0; i < L; ++i)
 #pragma unroll
-            for (int jj = i; jj < L; ++jj) {
-                const float2 v = sS[jj - i][t + i];
-                R.re[i][jj] = v.x;
-                R.im[i][jj] = (i == jj) ? 0.f : v.y;
+                for (int jj = i; jj < L; ++jj) {
+                    const float2 v = sS[jj - i][s + i];
+                    R.re[i][jj] = v.x;
+                    R.im[i][jj] = (i == jj) ? 0.f : v.y;
+                }
+            Sym<L> T;
+            if (!normalised_T<L>(R, T)) {
+                flag |= BM_FLAG_UNDEFINED;
+            } else {
+                float hc, hs;
+                if (S.predictor == 0) __sincosf(0.5f * what[min(NP - 1, s / kPredictStride)], &hs, &hc);
+                else lag1_half_angle<L>(R, hc, hs);
+                float v[L], nu = 1.f;
+                int steps = 0;
+                const bool good =
+                    power_top_eigvec<L>(T, hc, hs, kSurMinSteps, kSurMaxSteps, kEigVecTol, v, steps, nu) &&
+                    nu <= S.tau;
+                const int a0 = ls.accepted, r0 = ls.rejected;
+                if (good) {
+                    ls.counted += 1;
+                    ls.eig_its += steps;
+                    window_omega_v<L>(v, B.tmpl, B.full_roots != 0, __builtin_nanf(""), omega, flag, ls);
+                } else {
+                    window_omega_T<L, false>(T, B.tmpl, B.full_roots != 0, K, __builtin_nanf(""), omega, flag, ls);
+                }
+                // the surrogate's own counters: windows the prediction served, and the rest
+                ls.accepted = a0 + (good ? 1 : 0);
+                ls.rejected = r0 + (good ? 0 : 1);
             }
-        float wh;
-        if (S.predictor == 0) {
-            wh = what[min(NP - 1, t / kPredictStride)];
         } else {
-            float sr = 0.f, si = 0.f;
-#pragma unroll
-            for (int i = 0; i + 1 < L; ++i) { sr += R.re[i][i + 1]; si -= R.im[i][i + 1]; }
-            wh = atan2f(si, sr);
+            flag |= BM_FLAG_UNDEFINED;
         }
-        if (refine<L>(R, wh, S.tau, K, omega)) acc = 1;
-        else reject = true;
-    } else {
-        flag |= BM_FLAG_UNDEFINED;
+        if (inside_line) store_omega(J, line, p, omega, flag);
     }
-    // compact the rejected windows: one atomic per wave
-    const unsigned long long mask = __ballot(reject);
-    unsigned long long slot = 0;
-    if (mask) {
-        const int lane = t & 63;
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned long long basei = 0;
-        if (lane == leader) basei = atomicAdd(S.reject_count, (unsigned long long)__popcll(mask));
-        basei = __shfl(basei, leader);
-        slot = basei + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-    }
-    if (reject) S.rejects[slot] = make_int2(j, (int)(((unsigned)line << 16) | (unsigned)p));
-    else if (inside_line) store_omega(J, line, p, omega, flag);
-    if (B.stats) {
-        unsigned long long a0 = acc, a1 = reject ? 1 : 0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            a0 += __shfl_xor(a0, off);
-            a1 += __shfl_xor(a1, off);
-        }
-        if ((t & 63) == 0) {
-            unsigned long long* sl = B.stats + kStatFields * ((blockIdx.x * 4 + wv) % kStatSlots);
-            if (a0) atomicAdd(sl + 4, a0);
-            if (a1) atomicAdd(sl + 5, a1);
-        }
-    }
+    if (STATS) flush_stats<BLOCK>(ls, B.stats);
 }
 
 __global__ __launch_bounds__(256) void mlp_forward_kernel(MlpWeights w, const float* X, float* Y, int M) {
@@ -733,20 +712,26 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
 
 }  // namespace
 
+template <int L>
+hipError_t launch_sur_L(const SurBatch& b, hipStream_t s) {
+    const dim3 grid(b.rm.total), block(kSurBlock);
+    if (b.rm.stats) hipLaunchKernelGGL((surrogate_kernel<L, true>), grid, block, 0, s, b);
+    else hipLaunchKernelGGL((surrogate_kernel<L, false>), grid, block, 0, s, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_surrogate(int L, const SurBatch& b, hipStream_t s) {
     if (b.rm.total <= 0) return hipSuccess;
-    const dim3 grid(b.rm.total), block(kSurBlock);
     switch (L) {
-        case 2: hipLaunchKernelGGL(surrogate_kernel<2>, grid, block, 0, s, b); break;
-        case 3: hipLaunchKernelGGL(surrogate_kernel<3>, grid, block, 0, s, b); break;
-        case 4: hipLaunchKernelGGL(surrogate_kernel<4>, grid, block, 0, s, b); break;
-        case 5: hipLaunchKernelGGL(surrogate_kernel<5>, grid, block, 0, s, b); break;
-        case 6: hipLaunchKernelGGL(surrogate_kernel<6>, grid, block, 0, s, b); break;
-        case 7: hipLaunchKernelGGL(surrogate_kernel<7>, grid, block, 0, s, b); break;
-        case 8: hipLaunchKernelGGL(surrogate_kernel<8>, grid, block, 0, s, b); break;
+        case 2: return launch_sur_L<2>(b, s);
+        case 3: return launch_sur_L<3>(b, s);
+        case 4: return launch_sur_L<4>(b, s);
+        case 5: return launch_sur_L<5>(b, s);
+        case 6: return launch_sur_L<6>(b, s);
+        case 7: return launch_sur_L<7>(b, s);
+        case 8: return launch_sur_L<8>(b, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_mlp_forward(const MlpWeights& w, const float* X, float* Y, int M, hipStream_t s) {

@@ -70,6 +70,7 @@ template <int L>
 struct Sym {
     float a[L][L];
     __device__ __forceinline__ float& at(int i, int j) { return i <= j ? a[i][j] : a[j][i]; }
+    __device__ __forceinline__ float at(int i, int j) const { return i <= j ? a[i][j] : a[j][i]; }
 };
 
 // Hermitian covariance, upper triangle stored.
@@ -905,6 +906,118 @@ __device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T) {
     }
 }
 
+// Top eigenvector of the trace-normalised T by power iteration from the real
+// form of the steering vector of a predicted frequency w, (hc, hs) = e^{j w/2}
+// (v0 = Q^H a(w) e^{-j w (L-1)/2} / sqrt L: sqrt(2/L) (cos w s_i, sin w s_i)
+// with s_i = i - (L-1)/2, and 1/sqrt L for the middle of odd L).  The iterate
+// is accepted once an a-posteriori bound proves it within `tol` of the top
+// eigenvector.  With the Rayleigh quotient rho and residual r of the vector
+// v a step is taken from: lambda_1 >= rho; every other eigenvalue has
+// |lambda_i| <= l2 = sqrt(tr T^2 - rho^2), since their squares sum to
+// tr T^2 - lambda_1^2; so sin(angle of v) <= sb = |r| / (|v| (rho - l2))
+// (the residual bound for symmetric matrices), and the step multiplies
+// tan(angle) by at most l2 / rho.  The result of the step is accepted when
+// (l2 / rho) tan <= tol, with tan <= sb / sqrt(1 - sb^2) <= sb sqrt(4/3) for
+// sb <= 1/2.  Such a bound also proves lambda_2 < lambda_1, so an accepted
+// window is never degenerate.  Returns false (v undefined) when no step
+// within max_steps is accepted; *steps counts the steps taken.  *nu receives
+// the MUSIC null spectrum 1 - (v^T v0)^2 at the prediction.
+template <int L>
+__device__ __forceinline__ bool power_top_eigvec(const Sym<L>& T, float hc, float hs, int min_steps, int max_steps,
+                                                 float tol, float (&v)[L], int& steps, float& nu) {
+    constexpr int m = L / 2;
+    constexpr int o = L - m;
+    float v0[L];
+    {
+        float er = 1.f, ei = 0.f;
+#pragma unroll
+        for (int k = 0; k < L - 1; ++k) {                  // e^{j w s_0}
+            const float t = er * hc + ei * hs;
+            ei = ei * hc - er * hs;
+            er = t;
+        }
+        const float sr = hc * hc - hs * hs, si = 2.f * hc * hs;
+        const float sc = 1.41421356237309515f * frsq((float)L);
+#pragma unroll
+        for (int a = 0; a < m; ++a) {
+            v0[a] = sc * er;
+            v0[o + a] = sc * ei;
+            const float t = er * sr - ei * si;
+            ei = er * si + ei * sr;
+            er = t;
+        }
+        if (L & 1) v0[m] = frsq((float)L);
+    }
+    float t2 = 0.f;                                         // tr T^2
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        t2 = fmaf(T.a[i][i], T.a[i][i], t2);
+#pragma unroll
+        for (int j = i + 1; j < L; ++j) t2 = fmaf(2.f * T.a[i][j], T.a[i][j], t2);
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) v[i] = v0[i];
+    // Unnormalised steps: the trace is 1, so lambda_1 >= 1/L and max_steps
+    // steps shrink the iterate by at most L^-max_steps, far inside FP32's range.
+    bool ok = false;
+    for (int it = 0; it < max_steps; ++it) {
+        ++steps;
+        float y[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < L; ++j) acc = fmaf(T.at(i, j), v[j], acc);
+            y[i] = acc;
+        }
+        if (it + 1 >= min_steps) {
+            float vy = 0.f, vv = 0.f;
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                vy = fmaf(v[i], y[i], vy);
+                vv = fmaf(v[i], v[i], vv);
+            }
+            const float ivv = frcp(vv);
+            const float rho = vy * ivv;                     // Rayleigh quotient of v
+            float r2 = 0.f;                                 // |T v - rho v|^2, summed from its terms
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const float r = fmaf(-rho, v[i], y[i]);
+                r2 = fmaf(r, r, r2);
+            }
+            // |lambda_i| <= l2 for every i >= 2 (Frobenius), sin(theta) of v <= sb,
+            // and the step contracts tan(theta) by at least l2 / rho
+            const float l2 = fsqrt(fmaxf(fmaf(-rho, rho, t2), 0.f));
+            const float gap = rho - l2;
+            const float sb2 = r2 * ivv * frcp(gap * gap);
+            const float c2 = l2 * l2 * frcp(rho * rho);
+            ok = gap > 0.f && sb2 <= 0.25f && sb2 * c2 * (4.f / 3.f) <= tol * tol && finitef(ivv);
+            // give up early where even the remaining steps at the proven
+            // contraction cannot reach tol (low SNR: the plain solver is cheaper)
+            const float left = (float)(max_steps - it);
+            const bool hopeless = !(gap > 0.f) || !finitef(ivv) ||
+                                  fminf(sb2, 0.25f) * (4.f / 3.f) *
+                                          __builtin_amdgcn_exp2f(left * __builtin_amdgcn_logf(c2)) > tol * tol;
+            if (!ok && hopeless) break;
+        }
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = y[i];
+        if (ok) break;
+    }
+    float n2 = 0.f, dot = 0.f;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        n2 = fmaf(v[i], v[i], n2);
+        dot = fmaf(v[i], v0[i], dot);
+    }
+    const float in = frsq(n2);
+#pragma unroll
+    for (int i = 0; i < L; ++i) v[i] *= in;
+    dot *= in;
+    nu = 1.f - dot * dot;
+    return ok;
+}
+
 // Plain root-MUSIC frequency of one window from its covariance (paper
 // Sec. 3, Eq. 6-15): eigen-split, polynomial, the certified pair or all
 // roots, pair selection, FP64 pair polish.  omega stays NaN with
@@ -925,11 +1038,14 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     window_omega_T<L, JACOBI>(T, tmpl, full_roots, K, wprev, omega, flag, ls);
 }
 
+template <int L>
+__device__ __forceinline__ void window_omega_v(const float (&v)[L], const RootTemplate& tmpl, bool full_roots,
+                                               float wprev, float& omega, unsigned& flag, LaneStats& ls);
+
 // The same from the trace-normalised real symmetric T of the window.
 template <int L, bool JACOBI>
 __device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tmpl, bool full_roots, int K,
                                                float wprev, float& omega, unsigned& flag, LaneStats& ls) {
-    constexpr int n = 2 * L - 2;
     ls.counted += 1;
     // ---- signal subspace (Eq. 6-11) ------------------------------------
     float v[L];
@@ -941,6 +1057,15 @@ __device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tm
         flag |= BM_FLAG_DEGENERATE;
         return;
     }
+    window_omega_v<L>(v, tmpl, full_roots, wprev, omega, flag, ls);
+}
+
+// The rest of the window from the top eigenvector v of T (unit, real form of
+// u1 = Q v): polynomial, the certified pair or all roots, omega.
+template <int L>
+__device__ __forceinline__ void window_omega_v(const float (&v)[L], const RootTemplate& tmpl, bool full_roots,
+                                               float wprev, float& omega, unsigned& flag, LaneStats& ls) {
+    constexpr int n = 2 * L - 2;
     float ur[L], ui[L];
     signal_vector<L>(v, ur, ui);
     // ---- polynomial coefficients (Eq. 12-14) -----------------------------

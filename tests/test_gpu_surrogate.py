@@ -77,7 +77,10 @@ def test_surrogate_maps_match_oracle(bm, torch, predictor):
             print(f"pred={predictor} L{L} {name}: rms {r:.2e} p99.9 {np.quantile(dd, 0.999):.2e} "
                   f"accepted {st['sur_accepted']} rejected {st['sur_rejected']}")
             assert r <= 2e-3
-        assert st["sur_accepted"] + st["sur_rejected"] > 0
+            # served windows carry an eigenvector proven within 1e-5 of the plain one: the
+            # maps also meet the plain path's bar
+            assert np.quantile(dd, 0.999) <= 1e-4
+        assert st["sur_accepted"] + st["sur_rejected"] == st["windows"] > 0
         if predictor == 1:
             assert st["sur_accepted"] > 0.5 * (st["sur_accepted"] + st["sur_rejected"])
     d.close()
@@ -108,11 +111,11 @@ def test_surrogate_graph_replays_match_eager(bm, torch):
 
 def test_surrogate_graph_with_two_L_matches_eager(bm, torch):
     """A surrogate batch with two covariance sizes: in a graph the two sets run on forked
-    capture streams at the same time, each with its own reject list; every replay equals
-    the eager call (the sets run one after another there) bit for bit."""
+    capture streams at the same time; every replay equals the eager call (the sets run one
+    after another there) bit for bit."""
     eager = bm.Demodulator(0, max_width=1024, max_height=1024)
     graph = bm.Demodulator(0, max_width=1024, max_height=1024, graph=True)
-    p = S.init_params(4)               # untrained: many windows go to the fallback lists
+    p = S.init_params(4)               # untrained: many windows take the fallback
     for h in (eager.h, graph.h):
         bm.bosmusic_surrogate_load(h, p)
         bm.bosmusic_surrogate_config(h, 0.25, 0)
@@ -148,9 +151,8 @@ def test_surrogate_graph_with_two_L_matches_eager(bm, torch):
 
 
 def test_surrogate_graph_replay_after_larger_eager_call(bm, torch):
-    """A graph captured on a small frame keeps its own reject list: capturing a second graph
-    for a larger frame on the same handle, and eager calls between the replays, change
-    nothing in the first graph's replays."""
+    """Capturing a second graph for a larger frame on the same handle, and eager calls
+    between the replays, change nothing in the first graph's replays."""
     d = bm.Demodulator(0, max_width=2048, max_height=1024, graph=True)
     e = bm.Demodulator(0, max_width=2048, max_height=1024)
     p = S.init_params(6)
@@ -217,8 +219,9 @@ def test_surrogate_on_a_full_4096_fp16_frame(bm, torch):
     gx, gy = wx.cpu().numpy(), wy.cpu().numpy()
     rows = [11, 1024, 2047, 3100, 4090]
     cols = [13, 2049, 4001]
-    rx, _ = rms_vs_oracle(gx[rows], oracle_rows(f.data, rows, 8, 32))
-    ry, _ = rms_vs_oracle(gy[:, cols].T, oracle_cols(f.data, cols, 8, 32))
+    rx, dx = rms_vs_oracle(gx[rows], oracle_rows(f.data, rows, 8, 32))
+    ry, dy = rms_vs_oracle(gy[:, cols].T, oracle_cols(f.data, cols, 8, 32))
+    assert np.quantile(np.concatenate([dx, dy]), 0.999) <= 1e-4
     acc = st["sur_accepted"] / max(1, st["sur_accepted"] + st["sur_rejected"])
     print(f"4096^2 surrogate: rms x {rx:.2e} y {ry:.2e}, accepted {acc:.5f}")
     assert rx <= 2e-3 and ry <= 2e-3
