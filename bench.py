@@ -39,6 +39,10 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed), FLOP/s
+# mean eigenvalue Newton steps of the tridiagonal solver per window (L = 6, 8 at 10 dB, counted
+# before the power route took most windows): the flop model's figure for the windows that fall
+# back to it when the two routes are mixed in one counter
+NEWTON_STEPS_TRIDIAG = 2.11
 PEAK_HBM = 8.0e12
 # HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
 # certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
@@ -71,8 +75,20 @@ def certificate_flops(L: int) -> int:
     return 40 + 18 * (n + 1) + 5 * m + schur
 
 
+def power_route_flops(L: int, steps: float) -> float:
+    """The verified power iteration for the signal eigenvector: the start's half-angle
+    (from the lag-1 sums, or the prediction's sincos), the real steering vector, tr T^2,
+    `steps` products T v, the Rayleigh quotient / residual / bound test from the second
+    step on, and the final normalisation."""
+    half = 2 * (L - 1) + 12
+    steer = 6 * (L - 1) + 6 * (L // 2) + 6
+    trace2 = L + 3 * (L * (L - 1) // 2)
+    return half + steer + trace2 + steps * 2 * L * L + max(0.0, steps - 1) * (8 * L + 20) + 3 * L + 2
+
+
 def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,
-                     cert_frac: float = 0.0, block: bool = False, pair_iters32: float = 0.0) -> dict:
+                     cert_frac: float = 0.0, block: bool = False, pair_iters32: float = 0.0,
+                     power_frac: float = 0.0, power_steps: float = 0.0) -> dict:
     """Algorithmic flop count of one window of the root-MUSIC kernel.
 
     FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` is the
@@ -84,7 +100,9 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     of a window that fails it is not counted.  `block`: the L x L block
     window, whose covariance is summed directly from its L snapshots.
     The eigenvalue Newton steps cost 8L flops each (the characteristic
-    polynomial and its derivative), after a 7L + 2 flop start bound.
+    polynomial and its derivative), after a 7L + 2 flop start bound.  `power_frac` of
+    the windows take the verified power iteration (`power_steps` steps each) instead of
+    that solver.
     """
     K = N - L + 1
     n = 2 * L - 2
@@ -101,38 +119,32 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     house = sum(2 * l * l + 2 * l * (l + 1) + 9 * l for l in range(2, L))
     newton_f = newton * 8 * L + 7 * L + 2
     inverse = 6 * L + 2 * 8 * L + sum(4 * l for l in range(2, L))
+    eigen = (1.0 - power_frac) * (house + newton_f + inverse) + power_frac * power_route_flops(L, power_steps)
     coef = 2 * L + 8 * L * (L + 1) // 2
     # start of the signal-root Newton: two evaluations of the real spectral function g, g', g''
     # (half-angle powers and the L/2 terms), the peak step, the half-angle and the radius
     spectral_start = 2 * (6 * (L - 1) + 9 * L + 5) + 25
-    common32 = lag + build_t + house + newton_f + inverse + coef + 20 + spectral_start
+    common32 = lag + build_t + eigen + coef + 20 + spectral_start
     full = 1.0 - cert_frac
     start = 4 * n + 40
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
     fp32 = common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(n)
     fp64 = pair_iters * pair_newton_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
-    return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64, "eigen": house + newton_f + inverse}
+    return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
 
-def surrogate_flops_per_window(L: int, N: int, power_steps: float) -> dict:
-    """Algorithmic flops of the surrogate kernel's own work on one window: the features
+def surrogate_flops_per_window(L: int, N: int) -> dict:
+    """The surrogate kernel's own work per window beyond the plain path's: the features
     and the MLP of one window in 32 (matrix-core flops kept apart, GELU as its A&S
-    erf: 16 flops), and for a window the prediction serves the steering vector of the
-    prediction, tr T^2, `power_steps` power steps (T v; the Rayleigh quotient, residual
-    and bounds from the second step on), the normalisation and the null spectrum.
-    Transcendentals count as one flop."""
+    erf: 16 flops) and the null spectrum at the prediction (its power route is counted
+    with the plain path's).  Transcendentals count as one flop."""
     stride = 32                                       # one network prediction per 32 windows
     feat = (4 * N + 16 * 6 + 10) / stride
     mlp_mfma = 2 * (32 * 64 + 64 * 64 + 64 * 2) / stride
-    mlp_valu = (2 * 64 * (16 + 1) + 2) / stride + 1   # + the half-angle sincos of the prediction
-    steer = 6 * (L - 1) + 6 * (L // 2) + 6
-    trace2 = L + 3 * (L * (L - 1) // 2)
-    step = 2 * L * L
-    test = 8 * L + 20
-    power = power_steps * step + max(0.0, power_steps - 1) * test
-    null = 5 * L + 3
-    return {"predict": feat + mlp_valu, "mfma": mlp_mfma, "served": steer + trace2 + power + null}
+    mlp_valu = (2 * 64 * (16 + 1) + 2) / stride
+    null = 2 * L + 2
+    return {"predict": feat + mlp_valu + null, "mfma": mlp_mfma}
 
 
 TRAIN_MFMA_FLOPS = 2 * (32 * 64 + 64 * 64 + 64 * 2) * 2 + 2 * 64 * 64   # forward, weight gradients, dH1
@@ -482,17 +494,25 @@ def main():
             ss = sdem.stats(reset=True)
             sdem.close()
             nwin = max(1, ss["windows"])
-            newton = ss["eig_iters"] / nwin
+            # eig_iters holds the power steps of the power-route windows and the eigenvalue
+            # Newton steps of the rest; the latter are taken at the tridiagonal solver's
+            # measured mean when both routes are mixed
+            pw = ss.get("power_windows", 0)
+            if pw:
+                newton = NEWTON_STEPS_TRIDIAG
+                psteps = max(0.0, ss["eig_iters"] - (nwin - pw) * newton) / pw
+            else:
+                newton, psteps = ss["eig_iters"] / nwin, 0.0
+            power_frac = pw / nwin
             pair_its32 = ss.get("pair_iters32", 0) / nwin
             if surrogate:
-                # served and fallback windows share everything but the eigenvector; the
-                # certified fraction and the Aberth iterations come from a plain counting pass
+                # the certified fraction and the Aberth iterations come from a plain counting
+                # pass (the surrogate's accepted/rejected counters are its own)
                 pdem = make(bm.BM_PLAIN, stats=True)
                 bm.bosmusic_demodulate(pdem.h, sub, bm.BM_PLAIN, stream)
                 ps = pdem.stats(reset=True)
                 pdem.close()
                 pn = max(1, ps["windows"])
-                newton = ps["eig_iters"] / pn
                 iters = ps["root_iters"] / max(1, ps["sur_rejected"])
                 pair_its, cert = ss["pair_iters"] / nwin, ps["sur_accepted"] / pn
             elif args.full_roots:
@@ -510,26 +530,21 @@ def main():
                 else:
                     wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
             fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert, block=bool(args.block),
-                                  pair_iters32=pair_its32)
-            entry = {"flop_per_window": round(fl["total"]), "newton": round(newton, 2),
-                     "root_iters": round(iters, 2), "windows_per_step": wins}
+                                  pair_iters32=pair_its32, power_frac=power_frac, power_steps=psteps)
+            per_win = fl["total"]
+            entry = {"newton": round(newton, 2), "power_fraction": round(power_frac, 5),
+                     "power_steps": round(psteps, 2), "root_iters": round(iters, 2), "windows_per_step": wins,
+                     "pair_iters32": round(pair_its32, 2), "pair_iters": round(pair_its, 2),
+                     "certified_fraction": round(cert, 5)}
             if surrogate:
                 acc, rej = ss["sur_accepted"], ss["sur_rejected"]
-                frac_acc = acc / max(1, acc + rej)
-                # power steps of the served windows (the counter also holds the fallback
-                # windows' eigenvalue Newton steps: at most `newton` each)
-                psteps = max(0.0, ss["eig_iters"] - rej * newton) / max(1, acc)
-                sfl = surrogate_flops_per_window(L, fr[idx[0]].N, psteps)
-                per_win = fl["total"] - frac_acc * fl["eigen"] + sfl["predict"] + frac_acc * sfl["served"]
-                flops_step += wins * per_win
+                sfl = surrogate_flops_per_window(L, fr[idx[0]].N)
+                per_win += sfl["predict"]
                 mfma_step += wins * sfl["mfma"]
-                entry.update({"flop_per_window": round(per_win), "power_steps": round(psteps, 2),
-                              "surrogate_mfma_flop_per_window": sfl["mfma"],
-                              "accepted_fraction": round(frac_acc, 5), "certified_fraction": round(cert, 5)})
-            else:
-                entry.update({"pair_iters32": round(pair_its32, 2), "pair_iters": round(pair_its, 2),
-                              "certified_fraction": round(cert, 5)})
-                flops_step += fl["total"] * wins
+                entry.update({"surrogate_mfma_flop_per_window": sfl["mfma"],
+                              "accepted_fraction": round(acc / max(1, acc + rej), 5)})
+            entry["flop_per_window"] = round(per_win)
+            flops_step += per_win * wins
             per_L[L] = entry
         rm_s = st["rm_time_ns"] / 1e9 / args.steps      # root-MUSIC (or surrogate) launch time per step
         achieved = flops_step / rm_s

@@ -18,7 +18,10 @@
  *   - L x L sample autocorrelation of the K = N-L+1 length-L sub-snapshots
  *     (Eq. 4), forward-backward averaged;
  *   - signal/noise eigen-split with a one-dimensional signal subspace
- *     (Eq. 6-11);
+ *     (Eq. 6-11): the top eigenvector of the real form of the covariance,
+ *     by power iteration where an a-posteriori bound proves it within
+ *     1e-5 rad, else by a tridiagonal solver (line windows; block windows
+ *     always take the solver);
  *   - root-MUSIC polynomial a(z)^H Un Un^H a(z) (Eq. 12) from the diagonal
  *     sums of the noise projector, degree 2L-2;
  *   - the root pair nearest the unit circle (Sec. 3, selection rule): found
@@ -93,7 +96,8 @@ enum { BM_PLAIN = 0, BM_SURROGATE = 1 };
 enum {
     BM_OPT_STATS = 1u,  /* count Jacobi sweeps and root iterations per call */
     BM_OPT_TIMING = 2u, /* time every root-MUSIC kernel launch with HIP events on its stream */
-    BM_OPT_JACOBI = 4u, /* signal subspace by cyclic Jacobi instead of the tridiagonal solver */
+    BM_OPT_JACOBI = 4u, /* signal subspace by cyclic Jacobi for every window (no power
+                           iteration, no tridiagonal solver) */
     BM_OPT_GRAPH = 8u,  /* capture each distinct batch once into a hipGraph and replay it;
                            ignored when BM_OPT_TIMING is set */
     BM_OPT_FULL_ROOTS = 16u, /* always find every root of the polynomial, never the
@@ -153,9 +157,9 @@ typedef struct {
     uint64_t windows;       /* windows demodulated since the last reset (in BM_PLAIN:
                                sur_accepted + sur_rejected + the BM_FLAG_DEGENERATE ones;
                                in BM_SURROGATE: sur_accepted + sur_rejected) */
-    uint64_t eig_iters;     /* sum over windows of Newton steps (Jacobi sweeps with BM_OPT_JACOBI);
-                               BM_SURROGATE: power steps of the accepted windows plus
-                               Newton steps of the rest */
+    uint64_t eig_iters;     /* sum over windows of eigen-split iterations: power steps of the
+                               power_windows, Newton steps of the tridiagonal solver for the
+                               rest (Jacobi sweeps with BM_OPT_JACOBI) */
     uint64_t root_iters;    /* sum over windows of simultaneous root iterations (all-roots windows) */
     uint64_t polish_fail;   /* windows whose FP64 pair polish did not converge */
     uint64_t sur_accepted;  /* BM_SURROGATE: windows whose signal eigenvector came from the
@@ -170,6 +174,9 @@ typedef struct {
     uint64_t rm_time_ns;    /* their summed duration between HIP events, ns */
     uint64_t pair_iters32;  /* sum over windows of FP32 Newton steps for the signal root,
                                taken before the FP64 ones */
+    uint64_t power_windows; /* windows whose signal eigenvector came from the verified power
+                               iteration (the rest took the tridiagonal solver); eig_iters
+                               holds their power steps */
 } bosmusic_stats;
 
 /* Create a handle on cfg->device, allocating the workspace for frames up to

@@ -59,7 +59,7 @@ class bosmusic_stats(ctypes.Structure):
     _fields_ = [("windows", c_uint64), ("eig_iters", c_uint64), ("root_iters", c_uint64),
                 ("polish_fail", c_uint64), ("sur_accepted", c_uint64), ("sur_rejected", c_uint64),
                 ("pair_iters", c_uint64), ("rm_launches", c_uint64), ("rm_time_ns", c_uint64),
-                ("pair_iters32", c_uint64)]
+                ("pair_iters32", c_uint64), ("power_windows", c_uint64)]
 
 
 class BosmusicError(RuntimeError):

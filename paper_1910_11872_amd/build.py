@@ -20,8 +20,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbosmusic.so")
 ARCH = os.environ.get("BOSMUSIC_ARCH", "gfx950")
 
-SOURCES = ["bm_runtime.cpp", "bm_analytic.hip", "bm_rootmusic.hip", "bm_bigblock.hip", "bm_surrogate.hip",
-           "bm_integrate.hip"]
+SOURCES = ["bm_runtime.cpp", "bm_analytic.hip", "bm_rootmusic.hip", "bm_rootmusic_jacobi.hip", "bm_bigblock.hip",
+           "bm_bigblock_large.hip", "bm_surrogate.hip", "bm_integrate.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

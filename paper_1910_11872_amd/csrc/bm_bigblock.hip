@@ -2,7 +2,8 @@
 // its window-size table reaching 17 x 17): odd sizes 9 .. 17, 128 lanes per
 // block, one wave per SIMD.  Their own translation unit: these instantiations
 // are large (fully unrolled L x L eigen-split, degree 2L-2 polynomial, FP64
-// certificate) and compile alongside the rest.
+// certificate) and compile alongside the rest; 15 x 15 and 17 x 17 in
+// bm_bigblock_large.hip.
 #include "bm_rootmusic_kernels.h"
 
 namespace bm {
@@ -14,8 +15,8 @@ hipError_t launch_big_block_window(int L, const RmBatch& b, int grid, hipStream_
         case 9: return launch_big_block<9>(b, grid, s);
         case 11: return launch_big_block<11>(b, grid, s);
         case 13: return launch_big_block<13>(b, grid, s);
-        case 15: return launch_big_block<15>(b, grid, s);
-        case 17: return launch_big_block<17>(b, grid, s);
+        case 15:
+        case 17: return launch_big_block_window_15_17(L, b, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

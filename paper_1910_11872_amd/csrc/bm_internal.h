@@ -18,7 +18,7 @@ constexpr int kMaxN = 64;
 constexpr int kMaxFFT = 8192;
 constexpr int kMaxRadixPasses = 20;
 constexpr int kStatSlots = 64;   // counter slots of the statistics buffer
-constexpr int kStatFields = 8;   // counters per slot
+constexpr int kStatFields = 9;   // counters per slot
 constexpr int kGatherBlock = 256;
 
 // Mixed-radix plan of one DFT length (radices 4, 2, 3, 5, 7, 11, 13 in pass order).
@@ -83,6 +83,7 @@ struct RmBatch {
     int jacobi;            // 1: cyclic Jacobi eigen-split instead of the tridiagonal solver
     int full_roots;        // 1: always find every root (no certified-pair shortcut)
     int block_windows;     // 1: every job is RM_BLOCK (256-lane blocks); 0: every job is RM_LINE
+    int warm;              // 1: some job has a previous-frame map (line windows: the warm-start kernels)
     unsigned long long* stats;  // kStatSlots x kStatFields counters, or nullptr
     RootTemplate tmpl;
 };
@@ -182,6 +183,9 @@ hipError_t launch_rootmusic(int L, const RmBatch& b, int block, int grid, hipStr
 constexpr int block_window_lanes(int L) { return L <= kMaxL ? 256 : 128; }
 // Block windows above 8 x 8 (odd sizes to kMaxBlockL), in their own translation unit.
 hipError_t launch_big_block_window(int L, const RmBatch& b, int grid, hipStream_t s);
+hipError_t launch_big_block_window_15_17(int L, const RmBatch& b, int grid, hipStream_t s);
+// The same launch with the cyclic Jacobi eigen-split (L <= 8).
+hipError_t launch_rootmusic_jacobi(int L, const RmBatch& b, int block, int grid, hipStream_t s);
 // Output pixels per work item of a line: the line-window root-MUSIC kernel
 // (line_kernel) covers two starts per lane, the block-window and surrogate
 // kernels one.

@@ -13,12 +13,16 @@
 //               closed form from R without forming R_fb
 //   eigen-split the eigenvector v of the largest eigenvalue of T gives the
 //               signal subspace u1 = Q v (paper Eq. 6-11, one-dimensional
-//               signal subspace).  Default solver: Householder reduction to
-//               tridiagonal form, Newton's method from above on the
-//               characteristic polynomial (monotone for real-rooted
-//               polynomials) for the largest eigenvalue, one shifted inverse
-//               iteration for its eigenvector, back-transformation.  The
-//               cyclic Jacobi solver is kept as a selectable alternative.
+//               signal subspace).  Line windows: power iteration on T from
+//               the steering vector of the window's lag-1 phase, kept when
+//               an a-posteriori bound proves it within 1e-5 rad of the top
+//               eigenvector (2-3 steps at 10 dB).  Otherwise, and for block
+//               windows: Householder reduction to tridiagonal form, Newton's
+//               method from above on the characteristic polynomial
+//               (monotone for real-rooted polynomials) for the largest
+//               eigenvalue, one shifted inverse iteration for its
+//               eigenvector, back-transformation.  The cyclic Jacobi solver
+//               is kept as a selectable alternative.
 //   polynomial  c_k = sum_i C[i,i+k] with C = I - u1 u1^H = Un Un^H
 //               (paper Eq. 12-14)
 //   certified pair  FP64 Newton for the signal root with its mate
@@ -66,7 +70,7 @@ struct LineSpan {
 };
 
 // One block of windows: SPAN-(L-1) consecutive pixels p0.. of one line of job J.
-template <int L, int BLOCK, bool JACOBI>
+template <int L, int BLOCK, bool JACOBI, bool WARM>
 __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0, float2* sg,
                                                 float2 (*sS)[LineSpan<L, BLOCK>::row], const RootTemplate& tmpl,
                                                 bool full_roots, LaneStats& ls) {
@@ -109,8 +113,8 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
                     R.re[i][j] = v.x;
                     R.im[i][j] = (i == j) ? 0.f : v.y;
                 }
-            const float wprev = J.prev ? J.prev[(int64_t)p * J.prev_es + (int64_t)line * J.prev_ls]
-                                       : __builtin_nanf("");
+            const float wprev = (WARM && J.prev) ? J.prev[(int64_t)p * J.prev_es + (int64_t)line * J.prev_ls]
+                                                 : __builtin_nanf("");
             window_omega<L, JACOBI>(R, tmpl, full_roots, K, wprev, omega, flag, ls);
         } else {
             flag |= BM_FLAG_UNDEFINED;
@@ -213,20 +217,21 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
 
 template <int BLOCK>
 __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long long* stats) {
-    unsigned long long a[8] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
-                               (unsigned long long)ls.iters, (unsigned long long)ls.pfail,
-                               (unsigned long long)ls.accepted, (unsigned long long)ls.rejected,
-                               (unsigned long long)ls.pair_its, (unsigned long long)ls.pair_its32};
+    unsigned long long a[kStatFields] = {(unsigned long long)ls.counted, (unsigned long long)ls.eig_its,
+                                         (unsigned long long)ls.iters, (unsigned long long)ls.pfail,
+                                         (unsigned long long)ls.accepted, (unsigned long long)ls.rejected,
+                                         (unsigned long long)ls.pair_its, (unsigned long long)ls.pair_its32,
+                                         (unsigned long long)ls.power};
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) a[c] += __shfl_xor(a[c], off);
+        for (int c = 0; c < kStatFields; ++c) a[c] += __shfl_xor(a[c], off);
     if ((threadIdx.x & 63) == 0) {
         // spread the counters over kStatSlots slots to avoid one hot address
         unsigned long long* sl =
             stats + kStatFields * ((blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) % kStatSlots);
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
+        for (int c = 0; c < kStatFields; ++c)
             if (a[c]) atomicAdd(sl + c, a[c]);
     }
 }
@@ -244,7 +249,9 @@ __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long l
 // Block windows above 8 x 8 (odd sizes to 17 x 17) run 128 lanes per block at
 // one wave per SIMD: the per-lane T, the degree 2L-2 polynomial and the FP64
 // certificate need up to 512 VGPRs.
-template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN>
+// WARM: line windows may read a previous-frame map (the other build folds the
+// warm-start branch away: four fewer spilled registers at L = 8).
+template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN, bool WARM = false>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu((!STATS && L <= kMaxL) ? (BLOCKWIN ? 4 : (L <= 6 ? 5 : 4)) : 1)))
 void rootmusic_kernel(RmBatch B) {
@@ -265,7 +272,7 @@ void rootmusic_kernel(RmBatch B) {
         if constexpr (BLOCKWIN)
             rootmusic_block2d<L, BLOCK, JACOBI>(J, line, bx * WPB, sS, B.tmpl, B.full_roots != 0, ls);
         else
-            rootmusic_block<L, BLOCK, JACOBI>(J, line, bx * WPB, sg, sS, B.tmpl, B.full_roots != 0, ls);
+            rootmusic_block<L, BLOCK, JACOBI, WARM>(J, line, bx * WPB, sg, sS, B.tmpl, B.full_roots != 0, ls);
         __syncthreads();
     }
     if (STATS) flush_stats<BLOCK>(ls, B.stats);
@@ -311,19 +318,22 @@ __global__ __launch_bounds__(kGatherBlock) void rootmusic_gather_kernel(RmBatch 
         window_omega<L, JACOBI>(R, B.tmpl, B.full_roots != 0, K, __builtin_nanf(""), omega, flag, ls);
         store_omega(J, line, p, omega, flag);
     }
-    // the surrogate kernel owns the accepted/rejected counters of its windows
-    ls.accepted = 0;
-    ls.rejected = 0;
     if (STATS) flush_stats<kGatherBlock>(ls, B.stats);
+}
+
+template <int L, int BLOCK, bool JACOBI, bool WARM>
+hipError_t launch_LBJW(const RmBatch& b, int grid, hipStream_t s) {
+    if (b.stats)
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, true, JACOBI, false, WARM>), dim3(grid), dim3(BLOCK), 0, s, b);
+    else
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI, false, WARM>), dim3(grid), dim3(BLOCK), 0, s,
+                           b);
+    return hipGetLastError();
 }
 
 template <int L, int BLOCK, bool JACOBI>
 hipError_t launch_LBJ(const RmBatch& b, int grid, hipStream_t s) {
-    if (b.stats)
-        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, true, JACOBI, false>), dim3(grid), dim3(BLOCK), 0, s, b);
-    else
-        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI, false>), dim3(grid), dim3(BLOCK), 0, s, b);
-    return hipGetLastError();
+    return b.warm ? launch_LBJW<L, BLOCK, JACOBI, true>(b, grid, s) : launch_LBJW<L, BLOCK, JACOBI, false>(b, grid, s);
 }
 
 // Block windows: 256 lanes per block (128 above 8 x 8).
@@ -344,12 +354,27 @@ hipError_t launch_big_block(const RmBatch& b, int grid, hipStream_t s) {
     return launch_block_LJ<L, false>(b, grid, s);
 }
 
-template <int L>
-hipError_t launch_L(const RmBatch& b, int block, int grid, hipStream_t s) {
-    if (b.block_windows) return b.jacobi ? launch_block_LJ<L, true>(b, grid, s) : launch_block_LJ<L, false>(b, grid, s);
-    if (block == 128)
-        return b.jacobi ? launch_LBJ<L, 128, true>(b, grid, s) : launch_LBJ<L, 128, false>(b, grid, s);
-    return b.jacobi ? launch_LBJ<L, 256, true>(b, grid, s) : launch_LBJ<L, 256, false>(b, grid, s);
+// Line and block windows up to 8 x 8 of one eigen solver (JACOBI or the
+// default route), one translation unit each.
+template <int L, bool JACOBI>
+hipError_t launch_LJ(const RmBatch& b, int block, int grid, hipStream_t s) {
+    if (b.block_windows) return launch_block_LJ<L, JACOBI>(b, grid, s);
+    if (block == 128) return launch_LBJ<L, 128, JACOBI>(b, grid, s);
+    return launch_LBJ<L, 256, JACOBI>(b, grid, s);
+}
+
+template <bool JACOBI>
+hipError_t launch_rootmusic_J(int L, const RmBatch& b, int block, int grid, hipStream_t s) {
+    switch (L) {
+        case 2: return launch_LJ<2, JACOBI>(b, block, grid, s);
+        case 3: return launch_LJ<3, JACOBI>(b, block, grid, s);
+        case 4: return launch_LJ<4, JACOBI>(b, block, grid, s);
+        case 5: return launch_LJ<5, JACOBI>(b, block, grid, s);
+        case 6: return launch_LJ<6, JACOBI>(b, block, grid, s);
+        case 7: return launch_LJ<7, JACOBI>(b, block, grid, s);
+        case 8: return launch_LJ<8, JACOBI>(b, block, grid, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int L, bool JACOBI>
@@ -363,11 +388,7 @@ hipError_t launch_gather_LJ(const RmBatch& b, const int2* list, const unsigned l
     return hipGetLastError();
 }
 
-template <int L>
-hipError_t launch_gather_L(const RmBatch& b, const int2* list, const unsigned long long* count, int grid, hipStream_t s) {
-    return b.jacobi ? launch_gather_LJ<L, true>(b, list, count, grid, s)
-                    : launch_gather_LJ<L, false>(b, list, count, grid, s);
-}
+
 
 }  // namespace
 }  // namespace bm

@@ -646,6 +646,8 @@ void bind_group(bosmusic_s* h, GroupPlan& gp, const char* dev) {
         s.batch.jacobi = (h->options & BM_OPT_JACOBI) ? 1 : 0;
         s.batch.full_roots = (h->options & BM_OPT_FULL_ROOTS) ? 1 : 0;
         s.batch.block_windows = s.block_win ? 1 : 0;
+        s.batch.warm = 0;
+        for (auto& jb : s.jobs) s.batch.warm |= jb.prev ? 1 : 0;
         s.batch.stats = (h->options & BM_OPT_STATS) ? h->stats : nullptr;
         s.batch.tmpl = h->tmpl[s.L];
     }
@@ -1664,6 +1666,7 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
         out->sur_rejected = v[5];
         out->pair_iters = v[6];
         out->pair_iters32 = v[7];
+        out->power_windows = v[8];
         out->rm_launches = h->rm_launches;
         out->rm_time_ns = h->rm_time_ns;
         if (reset) h->rm_launches = h->rm_time_ns = 0;

@@ -35,9 +35,6 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSurBlock = 256;
-constexpr int kSurMinSteps = 2;       // power steps before the first convergence test
-constexpr int kSurMaxSteps = 8;       // then at most this many in all
-constexpr float kEigVecTol = 1e-5f;   // bound on sin(angle) between the iterate and the top eigenvector
 constexpr int kPredictStride = 32;    // one network prediction per this many windows
 // predictions per block, in 16-window MLP tiles
 constexpr int kPredictions = (2 * kSurBlock / kPredictStride + 15) / 16 * 16;
@@ -154,23 +151,29 @@ __device__ __forceinline__ float2 mlp_tile(const MlpSmem& s, const __bf16* x, __
     return make_float2(c[0] + s.b3[0], c[1] + s.b3[1]);
 }
 
-// MLP on T tiles of 16 rows of x ([row][32] bf16) by the block's four waves
-// together: wave w computes hidden units 16w .. 16w+15 of every tile in both
-// hidden layers, so each wave takes a quarter of the GELUs; the output layer
-// runs on the first T waves.  h1, h2: [T][16][64] bf16.  Lanes 0..15 of
-// wave j < T write what[16 j + l] = atan2(y1, y0) of row 16 j + l.
+// MLP on T tiles of 16 rows of x ([row][32] bf16, LDS) by the block's four
+// waves together: wave w computes hidden units 16w .. 16w+15 of every tile in
+// both hidden layers, so each wave takes a quarter of the GELUs and needs only
+// its own 16 rows of W1^T and W2^T, read as MFMA A operands straight from
+// device memory (the 14 KiB of weights stay in the caches); the output layer
+// runs on the first T waves.  h1, h2: [T][16][64] bf16 in LDS.  Lanes 0..15
+// of wave j < T write what[16 j + l] = atan2(y1, y0) of row 16 j + l.
 template <int T>
-__device__ __forceinline__ void mlp_block(const MlpSmem& s, const __bf16* x, __bf16* h1, __bf16* h2, float* what) {
+__device__ __forceinline__ void mlp_block(const MlpWeights& w, const __bf16* x, __bf16* h1, __bf16* h2, float* what) {
     static_assert(kSurBlock / 64 * 16 == kMlpHidden, "one 16-unit slice of each hidden layer per wave");
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = l & 15, hid = 16 * wv + (l >> 4) * 4;
+    const float4 b1 = *reinterpret_cast<const float4*>(w.b1 + hid);
+    const float4 b2 = *reinterpret_cast<const float4*>(w.b2 + hid);
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         floatx4 c = {0.f, 0.f, 0.f, 0.f};
-        c = mfma_tile(s.w1t + 16 * wv * kMlpIn, kMlpIn, x + 16 * j * kMlpIn, kMlpIn, c);
+        c = mfma_tile(w.w1t + 16 * wv * kMlpIn, kMlpIn, x + 16 * j * kMlpIn, kMlpIn, c);
         bf16x4 hv;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b1[hid + q]);
+        hv[0] = (__bf16)gelu(c[0] + b1.x);
+        hv[1] = (__bf16)gelu(c[1] + b1.y);
+        hv[2] = (__bf16)gelu(c[2] + b1.z);
+        hv[3] = (__bf16)gelu(c[3] + b1.w);
         *reinterpret_cast<bf16x4*>(h1 + (16 * j + col) * kMlpHidden + hid) = hv;
     }
     __syncthreads();
@@ -179,11 +182,13 @@ __device__ __forceinline__ void mlp_block(const MlpSmem& s, const __bf16* x, __b
         floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
-            c = mfma_tile(s.w2t + 16 * wv * kMlpHidden + 32 * kb, kMlpHidden, h1 + 16 * j * kMlpHidden + 32 * kb,
+            c = mfma_tile(w.w2t + 16 * wv * kMlpHidden + 32 * kb, kMlpHidden, h1 + 16 * j * kMlpHidden + 32 * kb,
                           kMlpHidden, c);
         bf16x4 hv;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)gelu(c[q] + s.b2[hid + q]);
+        hv[0] = (__bf16)gelu(c[0] + b2.x);
+        hv[1] = (__bf16)gelu(c[1] + b2.y);
+        hv[2] = (__bf16)gelu(c[2] + b2.z);
+        hv[3] = (__bf16)gelu(c[3] + b2.w);
         *reinterpret_cast<bf16x4*>(h2 + (16 * j + col) * kMlpHidden + hid) = hv;
     }
     __syncthreads();
@@ -191,28 +196,9 @@ __device__ __forceinline__ void mlp_block(const MlpSmem& s, const __bf16* x, __b
         floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
-            c = mfma_tile(s.w3t + 32 * kb, kMlpHidden, h2 + 16 * wv * kMlpHidden + 32 * kb, kMlpHidden, c);
-        if (l < 16) what[16 * wv + l] = atan2f(c[1] + s.b3[1], c[0] + s.b3[0]);
+            c = mfma_tile(w.w3t + 32 * kb, kMlpHidden, h2 + 16 * wv * kMlpHidden + 32 * kb, kMlpHidden, c);
+        if (l < 16) what[16 * wv + l] = atan2f(c[1] + w.b3[1], c[0] + w.b3[0]);
     }
-}
-
-// e^{j w / 2} of the lag-1 direction of the covariance (the non-learned
-// predictor): w = arg sum_i R[i][i+1]^*, the phase of the mean lag-1 product.
-template <int L>
-__device__ __forceinline__ void lag1_half_angle(const Cov<L>& R, float& hc, float& hs) {
-    float sr = 0.f, si = 0.f;
-#pragma unroll
-    for (int i = 0; i + 1 < L; ++i) {
-        sr += R.re[i][i + 1];
-        si -= R.im[i][i + 1];
-    }
-    const float m2 = sr * sr + si * si;
-    const bool ok = m2 > 0.f && finitef(m2);
-    const float im = ok ? frsq(m2) : 0.f;
-    const float cw = ok ? sr * im : 1.f, sw = ok ? si * im : 0.f;
-    hc = fsqrt(fmaxf(0.5f * (1.f + cw), 0.f));
-    hs = hc > 1e-3f ? 0.5f * sw * frcp(hc) : 1.f;
-    if (!(hc > 1e-3f)) hc = 0.f;
 }
 
 template <int L, bool STATS>
@@ -227,17 +213,15 @@ void surrogate_kernel(SurBatch S) {
     static_assert(NP * kPredictStride >= SPAN, "the predictions cover the block's windows");
     __shared__ float2 sg[SPAN + kMaxN];
     __shared__ float what[NP];
-    // the MLP's weights, features and hidden tiles, later the lag sums
-    constexpr int kWBytes = (int)sizeof(MlpSmem), kXBytes = NP * kMlpIn * 2, kHBytes = 2 * NP * kMlpHidden * 2;
+    // the MLP's features and hidden tiles, later the lag sums
+    constexpr int kXBytes = NP * kMlpIn * 2, kHBytes = 2 * NP * kMlpHidden * 2;
     constexpr int kSBytes = L * ROW * 8;
-    constexpr int kMBytes = kWBytes + kXBytes + kHBytes;
-    static_assert(kWBytes % 16 == 0, "bfloat16 tiles stay 16-byte aligned");
+    constexpr int kMBytes = kXBytes + kHBytes;
     __shared__ alignas(16) unsigned char ubuf[kMBytes > kSBytes ? kMBytes : kSBytes];
-    MlpSmem& sm = *reinterpret_cast<MlpSmem*>(ubuf);
-    __bf16* xs = reinterpret_cast<__bf16*>(ubuf + kWBytes);
+    __bf16* xs = reinterpret_cast<__bf16*>(ubuf);
     float2 (*sS)[ROW] = reinterpret_cast<float2 (*)[ROW]>(ubuf);
     const int t = threadIdx.x;
-    __bf16* h1 = reinterpret_cast<__bf16*>(ubuf + kWBytes + kXBytes);
+    __bf16* h1 = reinterpret_cast<__bf16*>(ubuf + kXBytes);
     __bf16* h2 = h1 + NP * kMlpHidden;
 
     const RmBatch& B = S.rm;
@@ -249,7 +233,6 @@ void surrogate_kernel(SurBatch S) {
     const int N = J.N, half = N >> 1, K = N - L + 1, len = J.len;
     const float2* g = J.gamma + (int64_t)line * J.gamma_ls;
     const int base = p0 - half;
-    if (S.predictor == 0) load_weights(S.w, sm, BLOCK);
     for (int i = t; i < SPAN + N - 1; i += BLOCK) {
         const int q = base + i;
         sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
@@ -288,7 +271,7 @@ void surrogate_kernel(SurBatch S) {
             xs[k * kMlpIn + 16 + i] = (__bf16)(v.x * rs + v.y * rc);
         }
         __syncthreads();
-        mlp_block<kPredictTiles>(sm, xs, h1, h2, what);
+        mlp_block<kPredictTiles>(S.w, xs, h1, h2, what);
     }
     __syncthreads();
     // ---- lag sums (the MLP scratch is dead: every wave passed the barrier) ---
@@ -314,27 +297,28 @@ void surrogate_kernel(SurBatch S) {
                     R.re[i][jj] = v.x;
                     R.im[i][jj] = (i == jj) ? 0.f : v.y;
                 }
+            // the prediction's e^{j w_hat / 2}
+            float hc, hs;
+            if (S.predictor == 0) __sincosf(0.5f * what[min(NP - 1, s / kPredictStride)], &hs, &hc);
+            else lag1_half_angle<L>(R, hc, hs);
             Sym<L> T;
             if (!normalised_T<L>(R, T)) {
                 flag |= BM_FLAG_UNDEFINED;
             } else {
-                float hc, hs;
-                if (S.predictor == 0) __sincosf(0.5f * what[min(NP - 1, s / kPredictStride)], &hs, &hc);
-                else lag1_half_angle<L>(R, hc, hs);
+                ls.counted += 1;
                 float v[L], nu = 1.f;
                 int steps = 0;
                 const bool good =
-                    power_top_eigvec<L>(T, hc, hs, kSurMinSteps, kSurMaxSteps, kEigVecTol, v, steps, nu) &&
+                    power_top_eigvec<L>(T, hc, hs, kPowerMinSteps, kPowerMaxSteps, kPowerTol, v, steps, nu) &&
                     nu <= S.tau;
-                const int a0 = ls.accepted, r0 = ls.rejected;
                 if (good) {
-                    ls.counted += 1;
+                    ls.power += 1;
                     ls.eig_its += steps;
-                    window_omega_v<L>(v, B.tmpl, B.full_roots != 0, __builtin_nanf(""), omega, flag, ls);
-                } else {
-                    window_omega_T<L, false>(T, B.tmpl, B.full_roots != 0, K, __builtin_nanf(""), omega, flag, ls);
                 }
                 // the surrogate's own counters: windows the prediction served, and the rest
+                const int a0 = ls.accepted, r0 = ls.rejected;
+                if (good || signal_eigvec_T<L, false>(T, v, flag, ls))
+                    window_omega_v<L>(v, B.tmpl, B.full_roots != 0, __builtin_nanf(""), omega, flag, ls);
                 ls.accepted = a0 + (good ? 1 : 0);
                 ls.rejected = r0 + (good ? 0 : 1);
             }

@@ -380,7 +380,8 @@ __device__ __forceinline__ void store_omega(const RmJob& J, int line, int p, flo
 
 // Counters a lane accumulates over the windows it owns.
 struct LaneStats {
-    int counted = 0, eig_its = 0, iters = 0, pfail = 0, accepted = 0, rejected = 0, pair_its = 0, pair_its32 = 0;
+    int counted = 0, eig_its = 0, iters = 0, pfail = 0, accepted = 0, rejected = 0, pair_its = 0, pair_its32 = 0,
+        power = 0;
 };
 
 // u1 = Q v for the unitary transform used by build_T.
@@ -918,8 +919,8 @@ __device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T) {
 // (the residual bound for symmetric matrices), and the step multiplies
 // tan(angle) by at most l2 / rho.  The result of the step is accepted when
 // (l2 / rho) tan <= tol, with tan <= sb / sqrt(1 - sb^2) <= sb sqrt(4/3) for
-// sb <= 1/2.  Such a bound also proves lambda_2 < lambda_1, so an accepted
-// window is never degenerate.  Returns false (v undefined) when no step
+// sb <= 1/2, and rho - l2 > 1e-5 rho is required too: that proves
+// lambda_1 > lambda_2 (1 + 1e-5), so an accepted window is never degenerate.  Returns false (v undefined) when no step
 // within max_steps is accepted; *steps counts the steps taken.  *nu receives
 // the MUSIC null spectrum 1 - (v^T v0)^2 at the prediction.
 template <int L>
@@ -991,7 +992,7 @@ __device__ __forceinline__ bool power_top_eigvec(const Sym<L>& T, float hc, floa
             const float gap = rho - l2;
             const float sb2 = r2 * ivv * frcp(gap * gap);
             const float c2 = l2 * l2 * frcp(rho * rho);
-            ok = gap > 0.f && sb2 <= 0.25f && sb2 * c2 * (4.f / 3.f) <= tol * tol && finitef(ivv);
+            ok = gap > kDegenRel * rho && sb2 <= 0.25f && sb2 * c2 * (4.f / 3.f) <= tol * tol && finitef(ivv);
             // give up early where even the remaining steps at the proven
             // contraction cannot reach tol (low SNR: the plain solver is cheaper)
             const float left = (float)(max_steps - it);
@@ -1027,20 +1028,76 @@ template <int L, bool JACOBI>
 __device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tmpl, bool full_roots, int K,
                                                float wprev, float& omega, unsigned& flag, LaneStats& ls);
 
+template <int L>
+__device__ __forceinline__ void window_omega_v(const float (&v)[L], const RootTemplate& tmpl, bool full_roots,
+                                               float wprev, float& omega, unsigned& flag, LaneStats& ls);
+
+// e^{j w / 2} of the lag-1 direction of the covariance, w = arg sum_i
+// R[i][i+1]^* (the phase of the mean lag-1 product), for a power-iteration start.
+template <int L>
+__device__ __forceinline__ void lag1_half_angle(const Cov<L>& R, float& hc, float& hs) {
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int i = 0; i + 1 < L; ++i) {
+        sr += R.re[i][i + 1];
+        si -= R.im[i][i + 1];
+    }
+    const float m2 = sr * sr + si * si;
+    const bool ok = m2 > 0.f && finitef(m2);
+    const float im = ok ? frsq(m2) : 0.f;
+    const float cw = ok ? sr * im : 1.f, sw = ok ? si * im : 0.f;
+    hc = fsqrt(fmaxf(0.5f * (1.f + cw), 0.f));
+    hs = hc > 1e-3f ? 0.5f * sw * frcp(hc) : 1.f;
+    if (!(hc > 1e-3f)) hc = 0.f;
+}
+
+// Power iteration of the line windows: a start at the lag-1 direction, the
+// first test after two steps, at most eight, and a proven angle below 1e-5.
+constexpr int kPowerMinSteps = 2;
+constexpr int kPowerMaxSteps = 8;
+constexpr float kPowerTol = 1e-5f;
+
+// The signal eigenvector first by power iteration from the lag-1 direction
+// (power_top_eigvec: accepted only with a proven angle below 1e-5 rad and a
+// proven gap), else by the tridiagonal solver (or Jacobi with JACOBI).
+// The signal eigenvector of T by the tridiagonal solver (Jacobi with
+// JACOBI); false, with BM_FLAG_DEGENERATE, when the subspace is not determined.
+template <int L, bool JACOBI>
+__device__ __forceinline__ bool signal_eigvec_T(Sym<L>& T, float (&v)[L], unsigned& flag, LaneStats& ls) {
+    float lam = 1.f;
+    bool degen = false;
+    if (JACOBI) top_eigvec_jacobi<L>(T, v, ls.eig_its, lam, degen);
+    else top_eigvec_tridiag<L>(T, v, ls.eig_its, lam, degen);
+    if (degen) flag |= BM_FLAG_DEGENERATE;
+    return !degen;
+}
+
 template <int L, bool JACOBI>
 __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots, int K,
                                              float wprev, float& omega, unsigned& flag, LaneStats& ls) {
+    float hc = 1.f, hs = 0.f;
+    if (!JACOBI) lag1_half_angle<L>(R, hc, hs);
     Sym<L> T;
     if (!normalised_T<L>(R, T)) {
         flag |= BM_FLAG_UNDEFINED;
         return;
     }
-    window_omega_T<L, JACOBI>(T, tmpl, full_roots, K, wprev, omega, flag, ls);
+    ls.counted += 1;
+    // ---- signal subspace (Eq. 6-11) ------------------------------------
+    float v[L];
+    bool have = false;
+    if (!JACOBI) {
+        float nu;
+        int steps = 0;
+        have = power_top_eigvec<L>(T, hc, hs, kPowerMinSteps, kPowerMaxSteps, kPowerTol, v, steps, nu);
+        if (have) {
+            ls.power += 1;
+            ls.eig_its += steps;
+        }
+    }
+    if (!have && !signal_eigvec_T<L, JACOBI>(T, v, flag, ls)) return;
+    window_omega_v<L>(v, tmpl, full_roots, wprev, omega, flag, ls);
 }
-
-template <int L>
-__device__ __forceinline__ void window_omega_v(const float (&v)[L], const RootTemplate& tmpl, bool full_roots,
-                                               float wprev, float& omega, unsigned& flag, LaneStats& ls);
 
 // The same from the trace-normalised real symmetric T of the window.
 template <int L, bool JACOBI>
@@ -1049,14 +1106,7 @@ __device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tm
     ls.counted += 1;
     // ---- signal subspace (Eq. 6-11) ------------------------------------
     float v[L];
-    float lam = 1.f;
-    bool degen = false;
-    if (JACOBI) top_eigvec_jacobi<L>(T, v, ls.eig_its, lam, degen);
-    else top_eigvec_tridiag<L>(T, v, ls.eig_its, lam, degen);
-    if (degen) {
-        flag |= BM_FLAG_DEGENERATE;
-        return;
-    }
+    if (!signal_eigvec_T<L, JACOBI>(T, v, flag, ls)) return;
     window_omega_v<L>(v, tmpl, full_roots, wprev, omega, flag, ls);
 }
 

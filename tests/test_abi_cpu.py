@@ -89,7 +89,7 @@ def test_struct_layout_matches_header():
     assert pkg.bosmusic_frame.omega_x.offset == 48
     assert ctypes.sizeof(pkg.bosmusic_config) == 32
     assert pkg.bosmusic_config.tune_cache.offset == 24
-    assert ctypes.sizeof(pkg.bosmusic_stats) == 80
+    assert ctypes.sizeof(pkg.bosmusic_stats) == 88
 
 
 def test_null_arguments_are_rejected_without_device_work():
