@@ -44,13 +44,13 @@ PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed), F
 # back to it when the two routes are mixed in one counter
 NEWTON_STEPS_TRIDIAG = 2.11
 PEAK_HBM = 8.0e12
-# HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=6, N=32, FP32 frames,
-# certified-pair path): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on four cfg2
-# frames (profiles/rootmusic_cfg2_counters.md).  Valid only for that kernel and configuration.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 = (36701.0 * 2.0 + 66146.0) * 1024 / (4 * 2 * 1024 * 1024)
-# The same for the L=8, N=32 line kernel on FP16 4096x4096 frames (profiles/rootmusic_cfg4_counters.md);
-# None until those counters are taken on the current kernel.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 = None
+# HBM bytes per pixel and direction of the line-window root-MUSIC launch (L=8, N=32, FP16 4096x4096
+# frames): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on two cfg4 frames
+# (profiles/rootmusic_surrogate_cfg4_counters.md).  Valid only for that kernel and configuration;
+# the other configurations report null.
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 = (287221.0 * 2.0 + 295399.0) * 1024 / (2 * 2 * 4096 * 4096)
+# The same for the surrogate kernel on those frames (same profile).
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4_SURROGATE = (287453.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
 
 
 def bairstow_flops(n: int) -> int:
@@ -550,11 +550,9 @@ def main():
         achieved = flops_step / rm_s
         kname = "surrogate_kernel" if surrogate else "rootmusic_kernel"
         traffic = None
-        if (args.workload == "cfg2" and not (args.block or args.full_roots or surrogate)):
-            traffic = TRAFFIC_BYTES_PER_PIXEL_DIR_CFG2 * 2 * total_px / max(1, st["rm_launches"] // args.steps)
-        elif (big and TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 is not None and
-              not (args.block or args.full_roots or surrogate)):
-            traffic = TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 * 2 * total_px / max(1, st["rm_launches"] // args.steps)
+        if big and not (args.block or args.full_roots or args.warm or args.predictor != "mlp"):
+            per_px = TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4_SURROGATE if surrogate else TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4
+            traffic = per_px * 2 * total_px / max(1, st["rm_launches"] // args.steps)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, scaled per pixel)",

@@ -13,11 +13,11 @@
 //               closed form from R without forming R_fb
 //   eigen-split the eigenvector v of the largest eigenvalue of T gives the
 //               signal subspace u1 = Q v (paper Eq. 6-11, one-dimensional
-//               signal subspace).  Line windows: power iteration on T from
+//               signal subspace).  Power iteration on T from
 //               the steering vector of the window's lag-1 phase, kept when
 //               an a-posteriori bound proves it within 1e-5 rad of the top
-//               eigenvector (2-3 steps at 10 dB).  Otherwise, and for block
-//               windows: Householder reduction to tridiagonal form, Newton's
+//               eigenvector (2-3 steps at 10 dB).  Otherwise: Householder
+//               reduction to tridiagonal form, Newton's
 //               method from above on the characteristic polynomial
 //               (monotone for real-rooted polynomials) for the largest
 //               eigenvalue, one shifted inverse iteration for its
@@ -161,14 +161,20 @@ __device__ __forceinline__ void rootmusic_block2d(const RmJob& J, int line, int 
     if (valid) {
         if (J.bdirs & BM_DIR_X) {
             Sym<L> T;
-            T_from_snapshots<L>(L, [&](int k, int i) { return sR[k][t + i]; }, T);
-            if (trace_normalise<L>(T)) window_omega_T<L, JACOBI>(T, tmpl, full_roots, L, __builtin_nanf(""), wx, fx, ls);
+            float c1r, c1i, hc, hs;
+            T_from_snapshots<L>(L, [&](int k, int i) { return sR[k][t + i]; }, T, c1r, c1i);
+            half_angle_of(c1r, c1i, hc, hs);
+            if (trace_normalise<L>(T))
+                window_omega_Ts<L, JACOBI>(T, hc, hs, tmpl, full_roots, __builtin_nanf(""), wx, fx, ls);
             else fx |= BM_FLAG_UNDEFINED;
         }
         if (J.bdirs & BM_DIR_Y) {
             Sym<L> T;
-            T_from_snapshots<L>(L, [&](int k, int i) { return sR[i][t + k]; }, T);
-            if (trace_normalise<L>(T)) window_omega_T<L, JACOBI>(T, tmpl, full_roots, L, __builtin_nanf(""), wy, fy, ls);
+            float c1r, c1i, hc, hs;
+            T_from_snapshots<L>(L, [&](int k, int i) { return sR[i][t + k]; }, T, c1r, c1i);
+            half_angle_of(c1r, c1i, hc, hs);
+            if (trace_normalise<L>(T))
+                window_omega_Ts<L, JACOBI>(T, hc, hs, tmpl, full_roots, __builtin_nanf(""), wy, fy, ls);
             else fy |= BM_FLAG_UNDEFINED;
         }
         if (J.phase && finitef(wx) && finitef(wy)) {

@@ -870,9 +870,10 @@ __device__ __forceinline__ bool normalised_T(const Cov<L>& R, Sym<L>& T) {
 // (Q^H s)_m = s_m.  The common factor sqrt2 is left in (y = sqrt2 Q^H s), which
 // scales T by 2; the trace normalisation removes it.  `snap(k, i)` returns
 // s_k[i].  About half the work of the complex upper triangle plus build_T,
-// and no complex L x L array in registers.
+// and no complex L x L array in registers.  (c1r, c1i) receives the lag-1
+// sum sum_k sum_i conj(s_k[i]) s_k[i+1], whose phase starts the power iteration.
 template <int L, typename F>
-__device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T) {
+__device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T, float& c1r, float& c1i) {
     constexpr int m = L / 2;
     constexpr int o = L - m;
     constexpr float kSqrt2 = 1.41421356237309515f;
@@ -880,6 +881,8 @@ __device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T) {
     for (int i = 0; i < L; ++i)
 #pragma unroll
         for (int j = i; j < L; ++j) T.a[i][j] = 0.f;
+    c1r = 0.f;
+    c1i = 0.f;
     // one snapshot at a time: unrolled, the loads of all snapshots would be
     // hoisted and held in registers
 #pragma unroll 1
@@ -887,6 +890,12 @@ __device__ __forceinline__ void T_from_snapshots(int K, F snap, Sym<L>& T) {
         float2 v[L];
 #pragma unroll
         for (int i = 0; i < L; ++i) v[i] = snap(k, i);
+        // lag-1 sum: sum_i conj(s[i]) s[i+1]
+#pragma unroll
+        for (int i = 0; i + 1 < L; ++i) {
+            c1r = fmaf(v[i].x, v[i + 1].x, fmaf(v[i].y, v[i + 1].y, c1r));
+            c1i = fmaf(v[i].x, v[i + 1].y, fmaf(-v[i].y, v[i + 1].x, c1i));
+        }
         float a[L], b[L];
 #pragma unroll
         for (int i = 0; i < m; ++i) {
@@ -1024,24 +1033,14 @@ __device__ __forceinline__ bool power_top_eigvec(const Sym<L>& T, float hc, floa
 // roots, pair selection, FP64 pair polish.  omega stays NaN with
 // BM_FLAG_UNDEFINED when the covariance is zero or not finite, and with
 // BM_FLAG_DEGENERATE when its signal subspace is not determined.
-template <int L, bool JACOBI>
-__device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tmpl, bool full_roots, int K,
-                                               float wprev, float& omega, unsigned& flag, LaneStats& ls);
-
 template <int L>
 __device__ __forceinline__ void window_omega_v(const float (&v)[L], const RootTemplate& tmpl, bool full_roots,
                                                float wprev, float& omega, unsigned& flag, LaneStats& ls);
 
 // e^{j w / 2} of the lag-1 direction of the covariance, w = arg sum_i
 // R[i][i+1]^* (the phase of the mean lag-1 product), for a power-iteration start.
-template <int L>
-__device__ __forceinline__ void lag1_half_angle(const Cov<L>& R, float& hc, float& hs) {
-    float sr = 0.f, si = 0.f;
-#pragma unroll
-    for (int i = 0; i + 1 < L; ++i) {
-        sr += R.re[i][i + 1];
-        si -= R.im[i][i + 1];
-    }
+// e^{j w / 2} for w = arg(sr + j si) (w = 0 when that is zero or not finite).
+__device__ __forceinline__ void half_angle_of(float sr, float si, float& hc, float& hs) {
     const float m2 = sr * sr + si * si;
     const bool ok = m2 > 0.f && finitef(m2);
     const float im = ok ? frsq(m2) : 0.f;
@@ -1051,15 +1050,23 @@ __device__ __forceinline__ void lag1_half_angle(const Cov<L>& R, float& hc, floa
     if (!(hc > 1e-3f)) hc = 0.f;
 }
 
-// Power iteration of the line windows: a start at the lag-1 direction, the
+template <int L>
+__device__ __forceinline__ void lag1_half_angle(const Cov<L>& R, float& hc, float& hs) {
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int i = 0; i + 1 < L; ++i) {
+        sr += R.re[i][i + 1];
+        si -= R.im[i][i + 1];
+    }
+    half_angle_of(sr, si, hc, hs);
+}
+
+// Power iteration of the windows: a start at the lag-1 direction, the
 // first test after two steps, at most eight, and a proven angle below 1e-5.
 constexpr int kPowerMinSteps = 2;
 constexpr int kPowerMaxSteps = 8;
 constexpr float kPowerTol = 1e-5f;
 
-// The signal eigenvector first by power iteration from the lag-1 direction
-// (power_top_eigvec: accepted only with a proven angle below 1e-5 rad and a
-// proven gap), else by the tridiagonal solver (or Jacobi with JACOBI).
 // The signal eigenvector of T by the tridiagonal solver (Jacobi with
 // JACOBI); false, with BM_FLAG_DEGENERATE, when the subspace is not determined.
 template <int L, bool JACOBI>
@@ -1072,16 +1079,15 @@ __device__ __forceinline__ bool signal_eigvec_T(Sym<L>& T, float (&v)[L], unsign
     return !degen;
 }
 
+// The window from its trace-normalised T and a start e^{j w/2} = (hc, hs) at
+// the window's lag-1 phase: the signal eigenvector first by power iteration
+// (power_top_eigvec: accepted only with a proven angle below 1e-5 rad and a
+// proven gap), else by the tridiagonal solver (Jacobi alone with JACOBI);
+// then the polynomial, the root pair and omega.
 template <int L, bool JACOBI>
-__device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots, int K,
-                                             float wprev, float& omega, unsigned& flag, LaneStats& ls) {
-    float hc = 1.f, hs = 0.f;
-    if (!JACOBI) lag1_half_angle<L>(R, hc, hs);
-    Sym<L> T;
-    if (!normalised_T<L>(R, T)) {
-        flag |= BM_FLAG_UNDEFINED;
-        return;
-    }
+__device__ __forceinline__ void window_omega_Ts(Sym<L>& T, float hc, float hs, const RootTemplate& tmpl,
+                                                bool full_roots, float wprev, float& omega, unsigned& flag,
+                                                LaneStats& ls) {
     ls.counted += 1;
     // ---- signal subspace (Eq. 6-11) ------------------------------------
     float v[L];
@@ -1099,15 +1105,18 @@ __device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate
     window_omega_v<L>(v, tmpl, full_roots, wprev, omega, flag, ls);
 }
 
-// The same from the trace-normalised real symmetric T of the window.
+// The window from its covariance (line windows).
 template <int L, bool JACOBI>
-__device__ __forceinline__ void window_omega_T(Sym<L>& T, const RootTemplate& tmpl, bool full_roots, int K,
-                                               float wprev, float& omega, unsigned& flag, LaneStats& ls) {
-    ls.counted += 1;
-    // ---- signal subspace (Eq. 6-11) ------------------------------------
-    float v[L];
-    if (!signal_eigvec_T<L, JACOBI>(T, v, flag, ls)) return;
-    window_omega_v<L>(v, tmpl, full_roots, wprev, omega, flag, ls);
+__device__ __forceinline__ void window_omega(const Cov<L>& R, const RootTemplate& tmpl, bool full_roots, int K,
+                                             float wprev, float& omega, unsigned& flag, LaneStats& ls) {
+    float hc = 1.f, hs = 0.f;
+    if (!JACOBI) lag1_half_angle<L>(R, hc, hs);
+    Sym<L> T;
+    if (!normalised_T<L>(R, T)) {
+        flag |= BM_FLAG_UNDEFINED;
+        return;
+    }
+    window_omega_Ts<L, JACOBI>(T, hc, hs, tmpl, full_roots, wprev, omega, flag, ls);
 }
 
 // The rest of the window from the top eigenvector v of T (unit, real form of
