@@ -253,6 +253,20 @@ bm_status bosmusic_surrogate_load(bosmusic_t h, const float* params, int64_t n);
 /* Copy the current FP32 parameters to host memory. Synchronous. */
 bm_status bosmusic_surrogate_save(bosmusic_t h, float* params, int64_t n);
 
+/* Training checkpoint for an exact resume: state[3 * BOSMUSIC_MLP_PARAMS]
+ * (host) = the FP32 parameters, then Adam's first and second moments, in
+ * the parameter order; *adam_step = the Adam step count.  A handle given
+ * the same state by bosmusic_surrogate_set_state and then the same training
+ * calls (same data, batch, steps, lr) reaches the same parameters bit for
+ * bit: the minibatches follow from those arguments, the training data from
+ * (first_line, seed) of bosmusic_surrogate_dataset, and the gradient sums
+ * are in a fixed order.  Both calls synchronise the device.  n must be
+ * 3 * BOSMUSIC_MLP_PARAMS; set_state refuses non-finite values, a negative
+ * second moment or a negative step count (BM_E_INVALID_ARG) before it
+ * changes anything. */
+bm_status bosmusic_surrogate_get_state(bosmusic_t h, float* state, int64_t n, int64_t* adam_step);
+bm_status bosmusic_surrogate_set_state(bosmusic_t h, const float* state, int64_t n, int64_t adam_step);
+
 /* Bound tau on the null spectrum at the prediction (default 0.25) and predictor:
  * 0 = the MLP, 1 = the lag-1 phase of the covariance (a non-learned
  * predictor, for comparison). */

@@ -33,7 +33,8 @@ ABI_FUNCTIONS = ("bosmusic_create", "bosmusic_destroy", "bosmusic_demodulate", "
                  "bosmusic_version", "bosmusic_surrogate_load", "bosmusic_surrogate_save",
                  "bosmusic_surrogate_config", "bosmusic_surrogate_forward", "bosmusic_surrogate_dataset",
                  "bosmusic_surrogate_grad", "bosmusic_surrogate_step", "bosmusic_surrogate_train",
-                 "bosmusic_integrate_many", "bosmusic_integrate_noalloc")
+                 "bosmusic_integrate_many", "bosmusic_integrate_noalloc", "bosmusic_surrogate_get_state",
+                 "bosmusic_surrogate_set_state")
 MLP_PARAMS = 6402
 
 
@@ -95,6 +96,10 @@ def lib():
         L.bosmusic_surrogate_load.restype = c_int32
         L.bosmusic_surrogate_save.argtypes = [c_void_p, c_void_p, c_int64]
         L.bosmusic_surrogate_save.restype = c_int32
+        L.bosmusic_surrogate_get_state.argtypes = [c_void_p, c_void_p, c_int64, POINTER(c_int64)]
+        L.bosmusic_surrogate_get_state.restype = c_int32
+        L.bosmusic_surrogate_set_state.argtypes = [c_void_p, c_void_p, c_int64, c_int64]
+        L.bosmusic_surrogate_set_state.restype = c_int32
         L.bosmusic_surrogate_config.argtypes = [c_void_p, ctypes.c_float, c_int32]
         L.bosmusic_surrogate_config.restype = c_int32
         L.bosmusic_surrogate_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
@@ -310,6 +315,23 @@ def bosmusic_surrogate_save(h):
     a = np.empty(MLP_PARAMS, np.float32)
     _check(lib().bosmusic_surrogate_save(h, a.ctypes.data_as(c_void_p), a.size), h)
     return a
+
+
+def bosmusic_surrogate_get_state(h):
+    """(state, adam_step): FP32 parameters, Adam first and second moments (3 x MLP_PARAMS)."""
+    import numpy as np
+    a = np.empty(3 * MLP_PARAMS, np.float32)
+    step = c_int64(0)
+    _check(lib().bosmusic_surrogate_get_state(h, a.ctypes.data_as(c_void_p), a.size, byref(step)), h)
+    return a, int(step.value)
+
+
+def bosmusic_surrogate_set_state(h, state, adam_step: int) -> None:
+    import numpy as np
+    a = np.ascontiguousarray(state, dtype=np.float32).reshape(-1)
+    if a.size != 3 * MLP_PARAMS:
+        raise ValueError(f"need {3 * MLP_PARAMS} state values, got {a.size}")
+    _check(lib().bosmusic_surrogate_set_state(h, a.ctypes.data_as(c_void_p), a.size, int(adam_step)), h)
 
 
 def bosmusic_surrogate_config(h, tau: float = 0.25, predictor: int = 0) -> None:

@@ -272,6 +272,205 @@ __global__ __launch_bounds__(T) void analytic_kernel(FftBatch B, int item0) {
     }
 }
 
+// ---- power-of-two lines of 512 ... 4096 samples: register-resident passes ----
+//
+// n = R0 * 256 with R0 in {2, 4, 8, 16} takes three Stockham passes of radices
+// R0, 16, 16 (the pass formulas of stockham_pass).  A line pair is n/16
+// threads, and in every pass thread j holds the 16 elements j + s n/16,
+// s < 16, of the transform in registers: the first pass reads them straight
+// from the frame, the last leaves X[j + s n/16] in natural order, which is
+// where the spectrum is multiplied and the inverse transform's first pass
+// starts, so only four exchanges per line pair go through LDS (one buffer of
+// 4096 elements, read fully before it is rewritten).  A block of 256 threads
+// takes 4096/n pairs.  LDS index i lives at i ^ ((i >> 5) & 31): the strided
+// writes of the first two passes then meet at most two lanes per bank.
+
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 5) & 31); }
+
+// forward DFT4 in place: x_k = sum_n x_n e^{-2 pi i n k / 4}
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+    const float2 t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3), t3 = csub(x1, x3);
+    x0 = cadd(t0, t2);
+    x2 = csub(t0, t2);
+    x1 = cadd(t1, mul_mi(t3));
+    x3 = cadd(t1, mul_pi(t3));
+}
+
+// a e^{-2 pi i m / 16}
+template <int M>
+__device__ __forceinline__ float2 w16(float2 a) {
+    constexpr int m = M & 15;
+    constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f, h = 0.707106781186547524f;
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 4) return mul_mi(a);
+    else if constexpr (m == 8) return make_float2(-a.x, -a.y);
+    else if constexpr (m == 12) return mul_pi(a);
+    else {
+        constexpr float c = m == 1 ? c1 : m == 2 ? h : m == 3 ? s1 : m == 5 ? -s1 : m == 6 ? -h : m == 7 ? -c1
+                          : m == 9 ? -c1 : m == 10 ? -h : m == 11 ? -s1 : m == 13 ? s1 : m == 14 ? h : c1;
+        constexpr float sn = m == 1 ? s1 : m == 2 ? h : m == 3 ? c1 : m == 5 ? c1 : m == 6 ? h : m == 7 ? s1
+                           : m == 9 ? -s1 : m == 10 ? -h : m == 11 ? -c1 : m == 13 ? -c1 : m == 14 ? -h : -s1;
+        // (a.x + i a.y)(c - i sn)
+        return make_float2(fmaf(a.x, c, a.y * sn), fmaf(a.y, c, -a.x * sn));
+    }
+}
+
+// forward DFT16 in place, as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);   // v[4 k1 + n2]
+    v[5] = w16<1>(v[5]);
+    v[6] = w16<2>(v[6]);
+    v[7] = w16<3>(v[7]);
+    v[9] = w16<2>(v[9]);
+    v[10] = w16<4>(v[10]);
+    v[11] = w16<6>(v[11]);
+    v[13] = w16<3>(v[13]);
+    v[14] = w16<6>(v[14]);
+    v[15] = w16<9>(v[15]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);  // v[4 k1 + k2]
+    float2 o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
+// forward DFT8 of v[i0 + r st], r < 8, in place, as 2 x 4: n = 2 n1 + n2, k = k1 + 4 k2
+template <int I0, int ST>
+__device__ __forceinline__ void dft8s(float2 (&v)[16]) {
+    float2 a[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = v[I0 + r * ST];
+    dft4(a[0], a[2], a[4], a[6]);    // a[2 k1]     = A[0][k1]
+    dft4(a[1], a[3], a[5], a[7]);    // a[2 k1 + 1] = A[1][k1]
+    a[3] = w16<2>(a[3]);
+    a[5] = w16<4>(a[5]);
+    a[7] = w16<6>(a[7]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        v[I0 + k1 * ST] = cadd(a[2 * k1], a[2 * k1 + 1]);
+        v[I0 + (k1 + 4) * ST] = csub(a[2 * k1], a[2 * k1 + 1]);
+    }
+}
+
+// First pass (radix R0, Ns = 1) on the registers of thread j: butterfly
+// j + T q (q < 16/R0) takes z[q + r 16/R0], r < R0, and writes element
+// (j + T q) R0 + r of the line pair's buffer.
+template <int R0, int T>
+__device__ __forceinline__ void pow2_first_pass(float2 (&z)[16], float2* buf, int base, int j) {
+    constexpr int Q = 16 / R0;
+    if constexpr (R0 == 16) {
+        dft16(z);
+    } else if constexpr (R0 == 8) {
+        dft8s<0, 2>(z);
+        dft8s<1, 2>(z);
+    } else if constexpr (R0 == 4) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) dft4(z[q], z[q + Q], z[q + 2 * Q], z[q + 3 * Q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float2 a = z[q], b = z[q + Q];
+            z[q] = cadd(a, b);
+            z[q + Q] = csub(a, b);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) buf[swz(base + (j + T * q) * R0 + r)] = z[q + r * Q];
+}
+
+// A radix-16 pass with stride Ns (power of two) on the registers of thread j:
+// twiddles tw[(s - 1) Ns + k], k = j mod Ns; the DFT16 result stays in v.
+__device__ __forceinline__ void pow2_pass16(float2 (&v)[16], const float2* __restrict__ tw, int Ns, int j) {
+    const int k = j & (Ns - 1);
+#pragma unroll
+    for (int s = 1; s < 16; ++s) v[s] = cmul(v[s], tw[(s - 1) * Ns + k]);
+    dft16(v);
+}
+
+// Forward transform of the pair held in z (thread j, pair buffer at base):
+// on return z[s] = Z[j + s T].  Starts and ends without a pending barrier.
+template <int R0>
+__device__ __forceinline__ void pow2_fft(float2 (&z)[16], float2* buf, int base, int j, const float2* tw) {
+    constexpr int T = R0 * 16;           // threads per line pair = n / 16
+    pow2_first_pass<R0, T>(z, buf, base, j);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) z[s] = buf[swz(base + j + s * T)];
+    __syncthreads();
+    const float2* tw1 = tw + 2 * (R0 - 1);
+    pow2_pass16(z, tw1, R0, j);
+    const int g = j / R0, k = j & (R0 - 1);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) buf[swz(base + g * 16 * R0 + k + s * R0)] = z[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) z[s] = buf[swz(base + j + s * T)];
+    const float2* tw2 = tw1 + 15 * (R0 + 1);
+    pow2_pass16(z, tw2, T, j);
+}
+
+// The analytic signal of analytic_kernel for n = 256 R0, per line pair:
+// Z = DFT(x_a + i x_b), V = sgn(k) (Im Z, Re Z) / n, Y = DFT(V); Im Gamma_a =
+// Y.x, Im Gamma_b = -Y.y, Re Gamma = x - DC - Nyquist (-1)^i.
+template <int R0>
+__global__ __launch_bounds__(256) void analytic_pow2_kernel(FftBatch B, int item0) {
+    constexpr int n = 256 * R0, T = 16 * R0, P = 4096 / n;
+    __shared__ float2 buf[4096];
+    const int w = item0 + blockIdx.x;
+    const int jb = find_job(B.prefix, B.njobs, w);
+    const FftJob& J = B.jobs[jb];
+    const int item = w - B.prefix[jb];
+    const int t = threadIdx.x, p = t / T, j = t - p * T;
+    const int base = p * n;
+    const int la = 2 * (item * P + p);
+    const bool has_a = la < J.nlines, has_b = la + 1 < J.nlines;
+    const int elem = J.elem;
+    const int64_t off = (int64_t)la * J.src_ls;
+    float2 z[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int i = j + s * T;
+        z[s] = make_float2(has_a ? load_real(J.src, off + i, elem) : 0.f,
+                           has_b ? load_real(J.src, off + J.src_ls + i, elem) : 0.f);
+    }
+    pow2_fft<R0>(z, buf, base, j, J.tw);
+    // z[s] = Z[j + s T]; DC at (j, s) = (0, 0), Nyquist at (0, 8)
+    const float2 z0 = z[0], zh = z[8];
+    constexpr float inv_n = 1.0f / (float)n;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int k = j + s * T;
+        const float sg = (k == 0 || 2 * k == n) ? 0.f : (2 * k < n ? inv_n : -inv_n);
+        z[s] = make_float2(sg * z[s].y, sg * z[s].x);
+    }
+    __syncthreads();
+    pow2_fft<R0>(z, buf, base, j, J.tw);
+    // the pair's DC and Nyquist terms, from thread 0 of the pair
+    __syncthreads();
+    if (j == 0) {
+        buf[base] = z0;
+        buf[base + 1] = zh;
+    }
+    __syncthreads();
+    const float2 dc = buf[base], ny = buf[base + 1];
+    const float dca = dc.x * inv_n, dcb = dc.y * inv_n, nqa = ny.x * inv_n, nqb = ny.y * inv_n;
+    float2* out = J.dst + (int64_t)la * n;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int i = j + s * T;
+        const float sgn = (i & 1) ? -1.f : 1.f;
+        if (has_a) out[i] = make_float2(load_real(J.src, off + i, elem) - dca - sgn * nqa, z[s].x);
+        if (has_b) out[n + i] = make_float2(load_real(J.src, off + J.src_ls + i, elem) - dcb - sgn * nqb, -z[s].y);
+    }
+}
+
 // One block of 256 threads per tile of any job: 64 x 64 for real input
 // (decoded to FP32, 16 elements per thread) and 32 x 32 float2 for C32 input
 // (4 per thread), both in the same LDS words.  Tiles are padded by one
@@ -322,7 +521,7 @@ __global__ __launch_bounds__(kTrThreads) void transpose_kernel(TrBatch B) {
 
 hipError_t analytic_set_attributes() {
     const int bytes = kFftLdsElems * (int)sizeof(float2);
-    const void* k[kFftClasses] = {(const void*)analytic_kernel<5, 256>, (const void*)analytic_kernel<13, 256>,
+    const void* k[4] = {(const void*)analytic_kernel<5, 256>, (const void*)analytic_kernel<13, 256>,
                                   (const void*)analytic_kernel<5, 1024>, (const void*)analytic_kernel<13, 1024>};
     for (const void* f : k) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -340,7 +539,11 @@ hipError_t launch_analytic(const FftBatch& b, hipStream_t s) {
             case 0: hipLaunchKernelGGL((analytic_kernel<5, 256>), dim3(cnt), dim3(256), shmem, s, b, i0); break;
             case 1: hipLaunchKernelGGL((analytic_kernel<13, 256>), dim3(cnt), dim3(256), shmem, s, b, i0); break;
             case 2: hipLaunchKernelGGL((analytic_kernel<5, 1024>), dim3(cnt), dim3(1024), shmem, s, b, i0); break;
-            default: hipLaunchKernelGGL((analytic_kernel<13, 1024>), dim3(cnt), dim3(1024), shmem, s, b, i0); break;
+            case 3: hipLaunchKernelGGL((analytic_kernel<13, 1024>), dim3(cnt), dim3(1024), shmem, s, b, i0); break;
+            case 4: hipLaunchKernelGGL((analytic_pow2_kernel<2>), dim3(cnt), dim3(256), 0, s, b, i0); break;
+            case 5: hipLaunchKernelGGL((analytic_pow2_kernel<4>), dim3(cnt), dim3(256), 0, s, b, i0); break;
+            case 6: hipLaunchKernelGGL((analytic_pow2_kernel<8>), dim3(cnt), dim3(256), 0, s, b, i0); break;
+            default: hipLaunchKernelGGL((analytic_pow2_kernel<16>), dim3(cnt), dim3(256), 0, s, b, i0); break;
         }
     }
     return hipGetLastError();

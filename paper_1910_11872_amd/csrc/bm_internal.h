@@ -103,7 +103,12 @@ struct FftJob {
     int nlines;
     int n;                 // line length
     FftPlan plan;          // plan of n, or of m under Bluestein (chirp != nullptr)
+    int pow2;              // R0 of the register-resident path (n = 256 R0, R0 in 2, 4, 8, 16;
+                           // plan = R0, 16, 16), 0 for the LDS Stockham path
 };
+
+// The register-resident path takes n = 256 R0, R0 in {2, 4, 8, 16}.
+inline int fft_pow2_r0(int n) { return (n == 512 || n == 1024 || n == 2048 || n == 4096) ? n / 256 : 0; }
 
 // LDS of the analytic kernel's block, in complex elements (132 KiB): two
 // buffers of up to 8192 samples (or of a Bluestein transform length).
@@ -112,8 +117,14 @@ constexpr int kFftLdsElems = 16896;
 // Transform lengths above this run 1024 threads per block, shorter ones 256.
 constexpr int kFftWideMin = 2049;
 
-// Work items (blocks) of one job: pairs of lines.
-inline int fft_items(const FftJob& j) { return (j.nlines + 1) / 2; }
+// Work items (blocks) of one job: pairs of lines, 4096/n pairs per block on
+// the register-resident path.
+inline int fft_items(const FftJob& j) {
+    const int pairs = (j.nlines + 1) / 2;
+    if (!j.pow2) return pairs;
+    const int per = 16 / j.pow2;
+    return (pairs + per - 1) / per;
+}
 
 // Entries of the per-pass twiddle tables of a plan: (R - 1)(Ns + 1) per pass,
 // at most plan.n + 64.
@@ -126,8 +137,9 @@ inline int fft_tw_len(const FftPlan& p) {
     return len;
 }
 
-// LDS of one job's block, in complex elements.
-inline int fft_lds_elems(const FftJob& j) { return 2 * j.plan.n; }
+// Dynamic LDS of one job's block, in complex elements (the register-resident
+// path has its own static buffer).
+inline int fft_lds_elems(const FftJob& j) { return j.pow2 ? 0 : 2 * j.plan.n; }
 
 // True when the job's plan has a radix above 5.
 inline bool fft_big_radix(const FftJob& j) {
@@ -136,9 +148,13 @@ inline bool fft_big_radix(const FftJob& j) {
     return false;
 }
 
-// Kernel variant of a job: radices up to 5, or up to 13; 256 or 1024 threads.
-constexpr int kFftClasses = 4;
-inline int fft_class(const FftJob& j) { return (fft_big_radix(j) ? 1 : 0) + (j.plan.n >= kFftWideMin ? 2 : 0); }
+// Kernel variant of a job: radices up to 5, or up to 13; 256 or 1024 threads;
+// or the register-resident path of R0 = 2, 4, 8, 16 (classes 4 .. 7).
+constexpr int kFftClasses = 8;
+inline int fft_class(const FftJob& j) {
+    if (j.pow2) return j.pow2 == 2 ? 4 : j.pow2 == 4 ? 5 : j.pow2 == 8 ? 6 : 7;
+    return (fft_big_radix(j) ? 1 : 0) + (j.plan.n >= kFftWideMin ? 2 : 0);
+}
 
 // Jobs are ordered by class: items [cls_from[c], cls_from[c+1]) run in the
 // kernel variant of class c, with lds[c] complex elements of LDS per block.

@@ -257,7 +257,10 @@ __device__ __forceinline__ void flush_stats(const LaneStats& ls, unsigned long l
 // certificate need up to 512 VGPRs.
 // WARM: line windows may read a previous-frame map (the other build folds the
 // warm-start branch away: four fewer spilled registers at L = 8).
-template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN, bool WARM = false>
+// LOOP = false (line windows): one block per work item (grid = total), no
+// grid-stride loop; the loop keeps values live across items that cost the
+// L = 6 and 8 line kernels 40-50 spilled registers.
+template <int L, int BLOCK, bool STATS, bool JACOBI, bool BLOCKWIN, bool WARM = false, bool LOOP = true>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu((!STATS && L <= kMaxL) ? (BLOCKWIN ? 4 : (L <= 6 ? 5 : 4)) : 1)))
 void rootmusic_kernel(RmBatch B) {
@@ -267,7 +270,10 @@ void rootmusic_kernel(RmBatch B) {
     __shared__ float2 sg[BLOCKWIN ? 1 : LineSpan<L, BLOCK>::span + kMaxN];
     __shared__ __align__(16) float2 sS[L][ROW];
     LaneStats ls;
-    for (int w = blockIdx.x; w < B.total; w += gridDim.x) {
+    // LOOP = false: exactly one item, blockIdx.x (a trip count of one the compiler sees)
+    const int wend = LOOP ? B.total : (int)blockIdx.x + 1;
+    const int wstep = LOOP ? (int)gridDim.x : 1;
+    for (int w = blockIdx.x; w < wend; w += wstep) {
         const int j = find_job(B.prefix, B.njobs, w);
         const RmJob J = B.jobs[j];
         const int local = w - B.prefix[j];
@@ -331,9 +337,12 @@ template <int L, int BLOCK, bool JACOBI, bool WARM>
 hipError_t launch_LBJW(const RmBatch& b, int grid, hipStream_t s) {
     if (b.stats)
         hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, true, JACOBI, false, WARM>), dim3(grid), dim3(BLOCK), 0, s, b);
-    else
+    else if (grid < b.total)
         hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI, false, WARM>), dim3(grid), dim3(BLOCK), 0, s,
                            b);
+    else
+        hipLaunchKernelGGL((rootmusic_kernel<L, BLOCK, false, JACOBI, false, WARM, false>), dim3(b.total),
+                           dim3(BLOCK), 0, s, b);
     return hipGetLastError();
 }
 

@@ -245,10 +245,20 @@ void make_template(int L, bm::RootTemplate& t) {
 // radix R and stride Ns, e^{-2 pi i r k / (Ns R)} at (r - 1) Ns + k (0 < r < R,
 // k < Ns), then the butterfly constants e^{-2 pi i r / R} (0 < r < R); the
 // angle is reduced exactly (r k mod Ns R) and evaluated in FP64, rounded once.
-bm_status get_twiddles(bosmusic_s* h, int n, const float2** out) {
+// The register-resident path's plan R0, 16, 16 has its own tables, cached
+// under -n.
+bm_status get_twiddles(bosmusic_s* h, int n, const float2** out, int pow2 = 0) {
     bm::FftPlan plan;
-    if (!plan_fft(n, plan)) return fail(h, BM_E_UNSUPPORTED, "twiddles of %d", n);
-    auto it = h->twiddles.find(n);
+    if (pow2) {
+        plan.n = n;
+        plan.passes = 3;
+        plan.radix[0] = pow2;
+        plan.radix[1] = plan.radix[2] = 16;
+    } else if (!plan_fft(n, plan)) {
+        return fail(h, BM_E_UNSUPPORTED, "twiddles of %d", n);
+    }
+    const int key = pow2 ? -n : n;
+    auto it = h->twiddles.find(key);
     if (it != h->twiddles.end()) {
         *out = it->second;
         return BM_OK;
@@ -273,7 +283,7 @@ bm_status get_twiddles(bosmusic_s* h, int n, const float2** out) {
         (void)hipFree(d);
         return fail(h, BM_E_DEVICE, "twiddle upload failed");
     }
-    h->twiddles[n] = d;
+    h->twiddles[key] = d;
     *out = d;
     return BM_OK;
 }
@@ -318,6 +328,14 @@ bm_status get_bluestein(bosmusic_s* h, int n, int m, const float2** chirp, const
 bm_status make_fft_job(bosmusic_s* h, int n, bm::FftJob& fj) {
     fj.n = n;
     fj.chirp = fj.kern = nullptr;
+    fj.pow2 = bm::fft_pow2_r0(n);
+    if (fj.pow2) {
+        fj.plan.n = n;
+        fj.plan.passes = 3;
+        fj.plan.radix[0] = fj.pow2;
+        fj.plan.radix[1] = fj.plan.radix[2] = 16;
+        return get_twiddles(h, n, &fj.tw, fj.pow2);
+    }
     if (plan_fft(n, fj.plan)) return get_twiddles(h, n, &fj.tw);
     const int m = bluestein_len(n);
     if (m == 0 || !plan_fft(m, fj.plan)) return fail(h, BM_E_UNSUPPORTED, "line length %d", n);
@@ -910,33 +928,51 @@ uint16_t to_bf16_bits(float f) {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+// Upload FP32 parameters and their bfloat16 copies (W1^T | W2^T | W3^T | W2);
+// the device is synchronised first (enqueued work may still read the old ones).
+bm_status upload_params(bosmusic_s* h, const float* params) {
+    const int64_t n = bm::kMlpParams;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(params[i])) return fail(h, BM_E_INVALID_ARG, "parameter %lld is not finite", (long long)i);
+    const int H = bm::kMlpHidden, I = bm::kMlpIn;
+    const float* W1 = params;
+    const float* W2 = params + I * H + H;
+    const float* W3 = W2 + H * H + H;
+    std::vector<uint16_t> w((size_t)H * I + 2 * (size_t)H * H + 16 * (size_t)H, 0);
+    for (int i = 0; i < I; ++i)
+        for (int o = 0; o < H; ++o) w[(size_t)o * I + i] = to_bf16_bits(W1[i * H + o]);
+    uint16_t* w2t = w.data() + (size_t)H * I;
+    for (int i = 0; i < H; ++i)
+        for (int o = 0; o < H; ++o) w2t[(size_t)o * H + i] = to_bf16_bits(W2[i * H + o]);
+    uint16_t* w3t = w2t + (size_t)H * H;
+    for (int i = 0; i < H; ++i)
+        for (int o = 0; o < bm::kMlpOut; ++o) w3t[(size_t)o * H + i] = to_bf16_bits(W3[i * bm::kMlpOut + o]);
+    uint16_t* w2 = w3t + 16 * (size_t)H;
+    for (int i = 0; i < H * H; ++i) w2[i] = to_bf16_bits(W2[i]);
+    bm_status r;
+    if ((r = check(h, hipDeviceSynchronize(), "sync")) ||
+        (r = check(h, hipMemcpy(h->sur_master, params, n * sizeof(float), hipMemcpyHostToDevice), "load")) ||
+        (r = check(h, hipMemcpy(h->sur_w, w.data(), w.size() * 2, hipMemcpyHostToDevice), "load")))
+        return r;
+    return BM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 bm_status bosmusic_surrogate_load(bosmusic_t h, const float* params, int64_t n) {
     if (!h) return BM_E_INVALID_ARG;
     try {
         h->err.clear();
         if (!params || n != bm::kMlpParams) return fail(h, BM_E_INVALID_ARG, "need %d parameters", bm::kMlpParams);
-        for (int64_t i = 0; i < n; ++i)
-            if (!std::isfinite(params[i])) return fail(h, BM_E_INVALID_ARG, "parameter %lld is not finite", (long long)i);
-        const int H = bm::kMlpHidden, I = bm::kMlpIn;
-        const float* W1 = params;
-        const float* W2 = params + I * H + H;
-        const float* W3 = W2 + H * H + H;
-        std::vector<uint16_t> w((size_t)H * I + 2 * (size_t)H * H + 16 * (size_t)H, 0);
-        for (int i = 0; i < I; ++i)
-            for (int o = 0; o < H; ++o) w[(size_t)o * I + i] = to_bf16_bits(W1[i * H + o]);
-        uint16_t* w2t = w.data() + (size_t)H * I;
-        for (int i = 0; i < H; ++i)
-            for (int o = 0; o < H; ++o) w2t[(size_t)o * H + i] = to_bf16_bits(W2[i * H + o]);
-        uint16_t* w3t = w2t + (size_t)H * H;
-        for (int i = 0; i < H; ++i)
-            for (int o = 0; o < bm::kMlpOut; ++o) w3t[(size_t)o * H + i] = to_bf16_bits(W3[i * bm::kMlpOut + o]);
-        uint16_t* w2 = w3t + 16 * (size_t)H;
-        for (int i = 0; i < H * H; ++i) w2[i] = to_bf16_bits(W2[i]);
         DeviceGuard dg(h->device);
         bm_status r;
-        if ((r = check(h, hipDeviceSynchronize(), "sync")) ||
-            (r = check(h, hipMemcpy(h->sur_master, params, n * sizeof(float), hipMemcpyHostToDevice), "load")) ||
-            (r = check(h, hipMemcpy(h->sur_w, w.data(), w.size() * 2, hipMemcpyHostToDevice), "load")) ||
+        if ((r = upload_params(h, params)) ||
             (r = check(h, hipMemset(h->adam_m, 0, n * sizeof(float)), "load")) ||
             (r = check(h, hipMemset(h->adam_v, 0, n * sizeof(float)), "load")))
             return r;
@@ -945,6 +981,47 @@ bm_status bosmusic_surrogate_load(bosmusic_t h, const float* params, int64_t n) 
         return BM_OK;
     } catch (...) {
         return fail(h, BM_E_NOMEM, "host exception in surrogate_load");
+    }
+}
+
+bm_status bosmusic_surrogate_get_state(bosmusic_t h, float* state, int64_t n, int64_t* adam_step) {
+    if (!h) return BM_E_INVALID_ARG;
+    h->err.clear();
+    if (!state || !adam_step || n != 3 * (int64_t)bm::kMlpParams)
+        return fail(h, BM_E_INVALID_ARG, "need a state of %d floats and a step pointer", 3 * bm::kMlpParams);
+    DeviceGuard dg(h->device);
+    const size_t b = bm::kMlpParams * sizeof(float);
+    bm_status r;
+    if ((r = check(h, hipDeviceSynchronize(), "sync")) ||
+        (r = check(h, hipMemcpy(state, h->sur_master, b, hipMemcpyDeviceToHost), "state")) ||
+        (r = check(h, hipMemcpy(state + bm::kMlpParams, h->adam_m, b, hipMemcpyDeviceToHost), "state")) ||
+        (r = check(h, hipMemcpy(state + 2 * bm::kMlpParams, h->adam_v, b, hipMemcpyDeviceToHost), "state")))
+        return r;
+    *adam_step = h->adam_t;
+    return BM_OK;
+}
+
+bm_status bosmusic_surrogate_set_state(bosmusic_t h, const float* state, int64_t n, int64_t adam_step) {
+    if (!h) return BM_E_INVALID_ARG;
+    try {
+        h->err.clear();
+        if (!state || n != 3 * (int64_t)bm::kMlpParams || adam_step < 0)
+            return fail(h, BM_E_INVALID_ARG, "need a state of %d floats and a step count >= 0", 3 * bm::kMlpParams);
+        for (int64_t i = bm::kMlpParams; i < n; ++i)
+            if (!std::isfinite(state[i]) || (i >= 2 * bm::kMlpParams && state[i] < 0.f))
+                return fail(h, BM_E_INVALID_ARG, "Adam moment %lld is not valid", (long long)i);
+        DeviceGuard dg(h->device);
+        const size_t b = bm::kMlpParams * sizeof(float);
+        bm_status r;
+        if ((r = upload_params(h, state)) ||
+            (r = check(h, hipMemcpy(h->adam_m, state + bm::kMlpParams, b, hipMemcpyHostToDevice), "state")) ||
+            (r = check(h, hipMemcpy(h->adam_v, state + 2 * bm::kMlpParams, b, hipMemcpyHostToDevice), "state")))
+            return r;
+        h->adam_t = adam_step;
+        h->sur_loaded = true;
+        return BM_OK;
+    } catch (...) {
+        return fail(h, BM_E_NOMEM, "host exception in surrogate_set_state");
     }
 }
 

@@ -98,6 +98,8 @@ def test_null_arguments_are_rejected_without_device_work():
     assert L.bosmusic_demodulate(None, None, 0, 0, None) == pkg.BM_E_INVALID_ARG
     assert L.bosmusic_integrate(None, None, None, 1, 1, 1, 1, 0.0, 0.0, None, None) == pkg.BM_E_INVALID_ARG
     assert L.bosmusic_get_stats(None, None, 0, None) == pkg.BM_E_INVALID_ARG
+    assert L.bosmusic_surrogate_get_state(None, None, 0, None) == pkg.BM_E_INVALID_ARG
+    assert L.bosmusic_surrogate_set_state(None, None, 0, 0) == pkg.BM_E_INVALID_ARG
     assert L.bosmusic_destroy(None) == pkg.BM_OK
     cfg = pkg.bosmusic_config(0, 0, 64, 0, 0, None)
     h = ctypes.c_void_p()

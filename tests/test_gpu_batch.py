@@ -135,6 +135,8 @@ def test_flags_with_both_directions_in_a_batch(bm, torch):
 
 
 def test_tile_shapes_do_not_change_results(bm, torch, tmp_path):
+    """Block sizes and grid shapes (one block per item, or a persistent grid) give
+    identical results."""
     cache = tmp_path / "tune.jsonl"
     specs, _ = make_batch(bm, torch)
     base = bm.Demodulator(0, max_width=1024, max_height=1024, max_batch_pixels=4 << 20)

@@ -148,6 +148,39 @@ def test_adam_steps_match_oracle(bm, torch):
     d.close()
 
 
+def test_training_resumes_exactly_from_a_checkpoint(bm, torch):
+    """Parameters, Adam moments and step count saved mid-training and restored into a
+    fresh handle give the same parameters after the same remaining steps, bit for bit."""
+    a = bm.Demodulator(0, max_width=64, max_height=64)
+    bm.bosmusic_surrogate_load(a.h, S.init_params(5))
+    X, T, _ = gpu_dataset(bm, torch, a.h, 0, 1 << 14, 77)
+    bm.bosmusic_surrogate_train(a.h, X, T, batch=1024, steps=40, lr=2e-3)
+    state, step = bm.bosmusic_surrogate_get_state(a.h)
+    assert step == 40 and state.shape == (3 * bm.MLP_PARAMS,)
+    assert np.any(state[bm.MLP_PARAMS:] != 0)                  # the moments are really there
+    bm.bosmusic_surrogate_train(a.h, X, T, batch=1024, steps=25, lr=2e-3)
+    want = bm.bosmusic_surrogate_save(a.h)
+    b = bm.Demodulator(0, max_width=64, max_height=64)
+    bm.bosmusic_surrogate_set_state(b.h, state, step)
+    np.testing.assert_array_equal(bm.bosmusic_surrogate_save(b.h), state[:bm.MLP_PARAMS])
+    bm.bosmusic_surrogate_train(b.h, X, T, batch=1024, steps=25, lr=2e-3)
+    np.testing.assert_array_equal(bm.bosmusic_surrogate_save(b.h), want)
+    assert bm.bosmusic_surrogate_get_state(b.h)[1] == 65
+    # a restart from the parameters alone (moments zeroed, step 0) does not reproduce it
+    c = bm.Demodulator(0, max_width=64, max_height=64)
+    bm.bosmusic_surrogate_load(c.h, state[:bm.MLP_PARAMS])
+    bm.bosmusic_surrogate_train(c.h, X, T, batch=1024, steps=25, lr=2e-3)
+    assert np.any(bm.bosmusic_surrogate_save(c.h) != want)
+    bad = state.copy()
+    bad[2 * bm.MLP_PARAMS] = -1.0
+    with pytest.raises(bm.BosmusicError) as ei:
+        bm.bosmusic_surrogate_set_state(b.h, bad, step)
+    assert ei.value.status == bm.BM_E_INVALID_ARG
+    np.testing.assert_array_equal(bm.bosmusic_surrogate_save(b.h), want)   # unchanged by the refusal
+    for d in (a, b, c):
+        d.close()
+
+
 def test_training_gain(bm, torch):
     """A network trained on the GPU predicts the labels far better than the
     untrained one, and lets the surrogate path accept most windows of fringe
