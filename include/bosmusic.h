@@ -180,7 +180,11 @@ typedef struct {
 } bosmusic_stats;
 
 /* Create a handle on cfg->device, allocating the workspace for frames up to
- * max_width x max_height.  *out receives the handle (NULL on failure). */
+ * max_width x max_height.  *out receives the handle (NULL on failure).
+ * Test hooks read here from the environment: BOSMUSIC_FAULT=alloc makes the
+ * workspace allocation fail (BM_E_NOMEM after the clean-up), BOSMUSIC_LOG=1
+ * makes the handle write one line per create, planned group and graph
+ * capture or replay to stderr. */
 bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out);
 
 /* Release the handle and its workspace (synchronises its device). NULL is OK. */

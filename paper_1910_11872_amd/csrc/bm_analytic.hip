@@ -386,11 +386,22 @@ __device__ __forceinline__ void pow2_first_pass(float2 (&z)[16], float2* buf, in
 }
 
 // A radix-16 pass with stride Ns (power of two) on the registers of thread j:
-// twiddles tw[(s - 1) Ns + k], k = j mod Ns; the DFT16 result stays in v.
+// twiddles w^s = tw[(s - 1) Ns + k], k = j mod Ns, of which six are read
+// (s = 1, 2, 3, 4, 8, 12) and the others formed as w^{4a} w^b (one more
+// rounding: fewer live registers than fifteen loads); the DFT16 result stays in v.
 __device__ __forceinline__ void pow2_pass16(float2 (&v)[16], const float2* __restrict__ tw, int Ns, int j) {
     const int k = j & (Ns - 1);
+    const float2 wb[4] = {make_float2(1.f, 0.f), tw[k], tw[Ns + k], tw[2 * Ns + k]};
+    const float2 wa[4] = {make_float2(1.f, 0.f), tw[3 * Ns + k], tw[7 * Ns + k], tw[11 * Ns + k]};
 #pragma unroll
-    for (int s = 1; s < 16; ++s) v[s] = cmul(v[s], tw[(s - 1) * Ns + k]);
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int s = 4 * a + b;
+            if (s == 0) continue;
+            const float2 w = (a == 0) ? wb[b] : (b == 0 ? wa[a] : cmul(wa[a], wb[b]));
+            v[s] = cmul(v[s], w);
+        }
     dft16(v);
 }
 

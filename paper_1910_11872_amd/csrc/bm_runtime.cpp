@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -74,6 +75,7 @@ struct bosmusic_s {
     bool sur_loaded = false;
     float sur_tau = 0.25f;
     int sur_predictor = 0;
+    bool log = false;              // BOSMUSIC_LOG=1 at create
     // surrogate training
     float* adam_m = nullptr;       // Adam moments (BOSMUSIC_MLP_PARAMS each)
     float* adam_v = nullptr;
@@ -112,9 +114,30 @@ bm_status fail(bosmusic_s* h, bm_status st, const char* fmt, ...) {
     return st;
 }
 
+// Test hooks read from the environment at each create: BOSMUSIC_FAULT=alloc makes
+// the workspace allocation of bosmusic_create fail after its first buffer is
+// allocated (the clean-up path, BM_E_NOMEM); BOSMUSIC_LOG=1 writes one line per
+// create, call plan and graph capture or replay to stderr.
+bool env_is(const char* name, const char* value) {
+    const char* v = std::getenv(name);
+    return v && std::strcmp(v, value) == 0;
+}
+
+void log_line(const bosmusic_s* h, const char* fmt, ...);
+
 bm_status check(bosmusic_s* h, hipError_t e, const char* what) {
     if (e == hipSuccess) return BM_OK;
     return fail(h, BM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void log_line(const bosmusic_s* h, const char* fmt, ...) {
+    if (!h || !h->log) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[bosmusic] %s\n", buf);
 }
 
 // Restores the caller's current device on scope exit.
@@ -539,6 +562,8 @@ bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1
             if (e == bm::Elem::C32) {
                 tj.dst = gy;
             } else {
+                // (decoded to FP32: an FP16 transposed frame halves the transpose's
+                // writes but made the analytic step's reads of it slower, 2.9 -> 3.4 ms on cfg4)
                 float* tr = (float*)(h->ws + cur);
                 cur += align_up(px * sizeof(float), 256);
                 tj.dst = tr;
@@ -885,6 +910,10 @@ bm_status run_graph(bosmusic_s* h, const bosmusic_frame* frames, int n,
             return r;
         }
         it = h->graphs.emplace(key, ge).first;
+        log_line(h, "graph captured: %d frames, %zu groups, mode %d (%zu cached)", n, groups.size(), mode,
+                 h->graphs.size());
+    } else {
+        log_line(h, "graph replayed: %d frames, mode %d", n, mode);
     }
     it->second.last_use = ++h->tick;
     h->last_graph_stream = st;
@@ -1347,7 +1376,7 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         const int64_t ws_px = std::max<int64_t>(cfg->max_batch_pixels, frame_px);
         // per pixel: x analytic (8) + y analytic (8) + transposed real (4), plus alignment slack
         h->ws_bytes = (size_t)ws_px * 20 + (size_t)3 * 256 * 1024;
-        if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess ||
+        if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess || env_is("BOSMUSIC_FAULT", "alloc") ||
             hipMalloc(&h->anchor, (size_t)cfg->max_height * sizeof(double)) != hipSuccess ||
             hipMalloc(&h->stats, bm::kStatFields * bm::kStatSlots * sizeof(unsigned long long)) != hipSuccess) {
             release(h);
@@ -1382,6 +1411,10 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
         for (int L = 2; L <= bm::kMaxBlockL; ++L) make_template(L, h->tmpl[L]);
         if (cfg->tune_cache) h->tune_path = cfg->tune_cache;
         load_tune_cache(h);
+        h->log = env_is("BOSMUSIC_LOG", "1");
+        log_line(h, "create: device %d (%s, %d CUs), frames up to %dx%d, workspace %zu bytes, options 0x%x",
+                 cfg->device, h->arch.c_str(), h->cu_count, cfg->max_width, cfg->max_height, h->ws_bytes,
+                 cfg->options);
         *out = h;
         return BM_OK;
     } catch (...) {
@@ -1441,6 +1474,14 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
         for (auto& g : groups) {
             GroupPlan gp;
             bm_status st = plan_group(h, frames, g.first, g.second, mode, gp);
+            if (st == BM_OK && h->log) {
+                std::string sets;
+                for (auto& rs : gp.rm)
+                    sets += " L" + std::to_string(rs.L) + (rs.block_win ? "b" : "") + ":" +
+                            std::to_string(rs.prefix.back()) + "x" + std::to_string(rs.tune.block);
+                log_line(h, "group frames %d..%d, mode %d: %d analytic items, root-MUSIC sets (items x lanes)%s",
+                         g.first, g.second - 1, mode, gp.fft_prefix.back(), sets.c_str());
+            }
             if (st == BM_OK) st = run_group_eager(h, gp, s);
             if (st != BM_OK) return st;
         }

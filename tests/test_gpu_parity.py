@@ -435,3 +435,35 @@ def test_certified_pair_agrees_with_all_roots(bm, torch, L, N, snr):
     assert frac > (0.5 if snr < 5 or L == 2 else 0.9)
     dc.close()
     df.close()
+
+
+def test_alloc_fault_in_create_reports_nomem_and_cleans_up(bm, torch, monkeypatch):
+    """BOSMUSIC_FAULT=alloc fails the workspace allocation of create after its first buffer:
+    BM_E_NOMEM with the reason, no handle, and a later create on the same device works."""
+    monkeypatch.setenv("BOSMUSIC_FAULT", "alloc")
+    with pytest.raises(bm.BosmusicError) as ei:
+        bm.Demodulator(0, max_width=256, max_height=256)
+    assert ei.value.status == bm.BM_E_NOMEM
+    assert "workspace" in bm.bosmusic_last_error(None)
+    monkeypatch.delenv("BOSMUSIC_FAULT")
+    d = bm.Demodulator(0, max_width=256, max_height=256)
+    img = torch.from_numpy(wl.random_frame(128, 16, seed=2)).cuda()
+    wx, _ = d.demodulate(img, 4, 16, "x")
+    torch.cuda.synchronize()
+    assert np.isfinite(wx.cpu().numpy()).any()
+    d.close()
+
+
+def test_log_lines_on_request(bm, torch, monkeypatch, capfd):
+    """BOSMUSIC_LOG=1 at create: one line for the handle and one per planned group."""
+    monkeypatch.setenv("BOSMUSIC_LOG", "1")
+    d = bm.Demodulator(0, max_width=256, max_height=256)
+    monkeypatch.delenv("BOSMUSIC_LOG")
+    img = torch.from_numpy(wl.random_frame(128, 16, seed=3)).cuda()
+    d.demodulate(img, 4, 16, "xy")
+    torch.cuda.synchronize()
+    d.close()
+    err = capfd.readouterr().err
+    assert "[bosmusic] create: device 0" in err
+    assert "[bosmusic] group frames 0..0" in err and "L4:" in err
+
