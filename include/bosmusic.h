@@ -235,7 +235,7 @@ bm_status bosmusic_get_stats(bosmusic_t h, bosmusic_stats* out, int32_t reset, v
  * An MLP 32 -> 64 -> 64 -> 2 (exact-erf GELU) maps the normalised window (16
  * central samples de-rotated by the central sample's phase, divided by the
  * window's RMS magnitude, [Re(16), Im(16)]) to (cos w, sin w); it runs on
- * one window in 16 of a line and its estimate w_hat serves those 16.  w_hat
+ * one window in 32 of a line and its estimate w_hat serves those 32.  w_hat
  * seeds a power iteration on the window's FB-averaged covariance (in its
  * real form, paper Eq. 6-11) for the signal eigenvector u1, accepted once an
  * a-posteriori bound proves it within 1e-5 rad of the top eigenvector and
