@@ -609,6 +609,114 @@ __device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const floa
     return false;
 }
 
+// The same count in FP32, decided only when every |gamma| exceeds
+// kCount32Margin of |a_0|^2 + |a_d|^2: -1 otherwise.  In numpy trials of the
+// certificate's polynomials (L = 4, 6, 8 at 0-30 dB, radius 0.8) the FP32
+// gamma of the windows so decided stayed within 1e-4 of the FP64 value, two
+// orders under the margin, and the counts agreed on every window.
+constexpr float kCount32Margin = 1e-2f;
+
+template <int m>
+__device__ __forceinline__ int zeros_inside_unit_disk32(float (&fr)[m + 1], float (&fi)[m + 1]) {
+    unsigned neg = 0;
+    bool ok = true;
+#pragma unroll
+    for (int d = m; d >= 1; --d) {
+        const float a0r = fr[0], a0i = fi[0], adr = fr[d], adi = fi[d];
+        const float p0 = fmaf(a0r, a0r, a0i * a0i), pd = fmaf(adr, adr, adi * adi);
+        const float g = p0 - pd;
+        ok = ok && (fabsf(g) > kCount32Margin * (p0 + pd));
+        neg |= (g < 0.f ? 1u : 0u) << d;
+        const float sc = frcp(p0 + pd);
+        const float br = a0r * sc, bi = a0i * sc, cr = adr * sc, ci = adi * sc;
+#pragma unroll
+        for (int i = 1; 2 * i <= d; ++i) {
+            const int k = d - i;
+            const float xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
+            fr[i] = fmaf(br, xr, fmaf(bi, xi, -fmaf(cr, yr, ci * yi)));
+            fi[i] = fmaf(br, xi, fmaf(-bi, xr, -fmaf(ci, yr, -cr * yi)));
+            fr[k] = fmaf(br, yr, fmaf(bi, yi, -fmaf(cr, xr, ci * xi)));
+            fi[k] = fmaf(br, yi, fmaf(-bi, yr, -fmaf(ci, xr, -cr * xi)));
+        }
+        fr[0] = g * sc;
+        fi[0] = 0.f;
+    }
+    int count = 0;
+#pragma unroll
+    for (int d = 1; d <= m; ++d)
+        if ((neg >> d) & 1u) count = d - count;
+    return ok ? count : -1;
+}
+
+// Quotient q_0 .. q_{n-2} of P (degree n) by z^2 - r z - s, in FP64,
+// stored as Q; returns the size |b_1| + |b_0| of the remainder b_1 (z - r) + b_0.
+template <int n, typename Q>
+__device__ __forceinline__ double pair_quotient(const float (&ar)[n + 1], const float (&ai)[n + 1], double rr, double ri,
+                                                double s_r, double s_i, Q (&fr)[n - 1], Q (&fi)[n - 1]) {
+    double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
+#pragma unroll
+    for (int k = n; k >= 0; --k) {
+        // the s b_{k+2} part first: only two dependent FMAs per step wait for b_{k+1}
+        const double tr = fma(s_r, b2r, fma(-s_i, b2i, (double)ar[k]));
+        const double ti = fma(s_r, b2i, fma(s_i, b2r, (double)ai[k]));
+        const double bkr = fma(rr, b1r, fma(-ri, b1i, tr));
+        const double bki = fma(rr, b1i, fma(ri, b1r, ti));
+        if (k >= 2) {
+            fr[k - 2] = (Q)bkr;
+            fi[k - 2] = (Q)bki;
+        }
+        b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
+    }
+    // here b2 = b_1 and b1 = b_0
+    return fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i);
+}
+
+// Q is self-inversive (P and the pair's factor are), q_{m-k} = conj(q_k) q_m / conj(q_0)
+// with m = 2L - 4, so the first Schur-Cohn step on f(z) = Q(rho z) has the closed form
+// T f = conj(q_0) sum_{k<m} q_k (rho^k - rho^{2m-k}) z^k, with a positive constant term:
+// f and T f have equally many zeros inside the unit disk.  rho^k - rho^{2m-k} =
+// rho^k (1 - rho^{2(m-k)}): ascending powers first, then the factor descending.
+// The conj(q_0) factor does not move zeros and is left out.
+template <int m, typename T>
+__device__ __forceinline__ void first_schur_step(const T (&fr)[m + 1], const T (&fi)[m + 1], T rho, T (&gr)[m],
+                                                 T (&gi)[m]) {
+    T pk = (T)1;
+#pragma unroll
+    for (int k = 0; k < m; ++k) {
+        gr[k] = pk;
+        pk *= rho;
+    }
+    const T rho2 = rho * rho;
+    T a = rho2;                                       // rho^{2(m-k)} at k = m - 1
+#pragma unroll
+    for (int k = m - 1; k >= 0; --k) {
+        const T w = gr[k] * ((T)1 - a);
+        gr[k] = fr[k] * w;
+        gi[k] = fi[k] * w;
+        a *= rho2;
+    }
+}
+
+// The L - 2 inner roots of the quotient (FP64 coefficients) strictly inside
+// |z| < |z_in| (1 - margin), by Schur-Cohn on Q(rho z).
+template <int L>
+__device__ __forceinline__ bool inner_roots_inside(const double (&fr)[2 * L - 3], const double (&fi)[2 * L - 3],
+                                                   double rin) {
+    constexpr int m = 2 * L - 4;
+    double gr[m], gi[m];
+    first_schur_step<m, double>(fr, fi, rin * (1.0 - kCertMargin), gr, gi);
+    return zeros_inside_unit_disk<m - 1>(gr, gi) == L - 2;
+}
+
+// Line-window sizes whose certificate first counts in FP32 at the fixed radius
+// kCertKappa: the other roots of the root-MUSIC polynomial of a window with a
+// tone sit well inside it (numpy trials, L = 4-8, N = 2L + 8 to 32, 0-30 dB:
+// the largest inner one at radius 0.58 at the median, 0.76 at most), where the
+// count is well conditioned; all inside kCertKappa <= rho means all inside rho.
+// Larger sizes (block windows, few snapshots) count at rho in FP64 only.
+constexpr int kCert32MaxL = 8;
+constexpr float kCertKappa = 0.8f;
+
 // True when the root z0 (with its mate 1/conj(z0)) is the root pair nearest
 // the unit circle, i.e. the pair the selection rule of Sec. 3 picks from all
 // roots.  Every root pair (z, 1/conj z) has its inner member at radius < 1,
@@ -616,8 +724,10 @@ __device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const floa
 // z_in the inner member of z0's pair: (z - z_in)(z - 1/conj z_in) must divide
 // P (remainder below kCertRemTol of the coefficients' size; a root on the circle,
 // its own mirror, fails here), and the quotient Q must have all its L - 2
-// inner roots strictly inside |z| < |z_in| (1 - margin), counted by
-// Schur-Cohn on Q(rho z).  On success (rr, ri) = z_in + 1/conj(z_in).
+// inner roots strictly inside |z| < |z_in| (1 - margin) = rho.  For L <= 8 a
+// decided FP32 count of L - 2 zeros of Q inside kCertKappa <= rho settles it;
+// otherwise Schur-Cohn on Q(rho z) in FP64 decides.  On success (rr, ri) =
+// z_in + 1/conj(z_in).
 template <int L>
 __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], const float (&ai)[2 * L - 1], double z0r,
                                                double z0i, double& rr, double& ri) {
@@ -638,53 +748,29 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     ri = z0i + z1i;
     // z^2 - r z - s with s = -z_in / conj(z_in)
     const double s_r = -(z0r * z1r - z0i * z1i), s_i = -(z0r * z1i + z0i * z1r);
-    double fr[n - 1], fi[n - 1];
     float scale = 0.f;                                // size of the (FP32) coefficients
-    double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
 #pragma unroll
-    for (int k = n; k >= 0; --k) {
-        // the s b_{k+2} part first: only two dependent FMAs per step wait for b_{k+1}
-        const double tr = fma(s_r, b2r, fma(-s_i, b2i, (double)ar[k]));
-        const double ti = fma(s_r, b2i, fma(s_i, b2r, (double)ai[k]));
-        const double bkr = fma(rr, b1r, fma(-ri, b1i, tr));
-        const double bki = fma(rr, b1i, fma(ri, b1r, ti));
-        scale += fabsf(ar[k]) + fabsf(ai[k]);
-        if (k >= 2) {
-            fr[k - 2] = bkr;
-            fi[k - 2] = bki;
-        }
-        b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
-    }
-    // remainder b1 (z - r) + b0: here b2 = b_1 and b1 = b_0
-    if (!(fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i) <= kCertRemTol * (double)scale)) return false;
+    for (int k = n; k >= 0; --k) scale += fabsf(ar[k]) + fabsf(ai[k]);
+    const double remtol = kCertRemTol * (double)scale;
     if constexpr (L == 2) {
-        return true;                                  // no other roots
+        double fr[1], fi[1];
+        return pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= remtol;   // no other roots
+    } else if constexpr (L <= kCert32MaxL) {
+        constexpr int m = n - 2;
+        float qr[n - 1], qi[n - 1];
+        if (!(pair_quotient<n, float>(ar, ai, rr, ri, s_r, s_i, qr, qi) <= remtol)) return false;
+        if (rin * (1.0 - kCertMargin) >= (double)kCertKappa) {
+            float gr[m], gi[m];
+            first_schur_step<m, float>(qr, qi, kCertKappa, gr, gi);
+            if (zeros_inside_unit_disk32<m - 1>(gr, gi) == L - 2) return true;
+        }
+        double fr[n - 1], fi[n - 1];                  // undecided: the quotient again, in FP64
+        pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi);
+        return inner_roots_inside<L>(fr, fi, rin);
     } else {
-    // Q is self-inversive (P and the pair's factor are), q_{m-k} = conj(q_k) q_m / conj(q_0)
-    // with m = 2L - 4, so the first Schur-Cohn step on f(z) = Q(rho z) has the closed form
-    // T f = conj(q_0) sum_{k<m} q_k (rho^k - rho^{2m-k}) z^k, with a positive constant term:
-    // f and T f have equally many zeros inside the unit disk.
-    constexpr int m = n - 2;
-    const double rho = rin * (1.0 - kCertMargin);
-    // rho^k - rho^{2m-k} = rho^k (1 - rho^{2(m-k)}): ascending powers first, then the
-    // factor descending, without a table of all 2m + 1 powers
-    double gr[m], gi[m];
-    double pk = 1.0;
-#pragma unroll
-    for (int k = 0; k < m; ++k) {
-        gr[k] = pk;
-        pk *= rho;
-    }
-    const double rho2 = rho * rho;
-    double a = rho2;                                  // rho^{2(m-k)} at k = m - 1
-#pragma unroll
-    for (int k = m - 1; k >= 0; --k) {
-        const double w = gr[k] * (1.0 - a);
-        gr[k] = fr[k] * w;
-        gi[k] = fi[k] * w;
-        a *= rho2;
-    }
-    return zeros_inside_unit_disk<m - 1>(gr, gi) == L - 2;
+        double fr[n - 1], fi[n - 1];
+        if (!(pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= remtol)) return false;
+        return inner_roots_inside<L>(fr, fi, rin);
     }
 }
 
