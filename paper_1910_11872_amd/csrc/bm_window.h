@@ -483,40 +483,67 @@ __device__ __forceinline__ bool bairstow(const float (&ar)[n + 1], const float (
     return true;
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rcp_est(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_est(double x) { return __builtin_amdgcn_rcp(x); }
+
 // Number of zeros of f(z) = sum_i (fr[i] + j fi[i]) z^i (formal degree m)
 // strictly inside the unit disk, by the Schur-Cohn recursion
 //     T f = conj(a_0) f - a_m f*,   f*(z) = z^m conj(f(1/conj(z))),
 // whose constant term gamma = |a_0|^2 - |a_m|^2 decides the count: when
 // gamma > 0, T f has as many zeros inside as f; when gamma < 0, as many as
 // f*, i.e. m minus those of f (Henrici, Applied and Computational Complex
-// Analysis I, Sec. 6.8).  Returns -1 when some |gamma| is too small to
-// decide, which is the case of a zero on or very near the unit circle.
-template <int m>
-__device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], double (&fi)[m + 1]) {
+// Analysis I, Sec. 6.8).  Returns -1 when some |gamma| is not above
+// `margin` (|a_0|^2 + |a_m|^2), which is the case of a zero on or very near
+// the unit circle.  From the second step on a_0 is that real gamma, which
+// takes a quarter of the products out of every coefficient update.
+template <int m, typename T>
+__device__ __forceinline__ int schur_cohn_count(T (&fr)[m + 1], T (&fi)[m + 1], T margin) {
     unsigned neg = 0;
     bool ok = true;
 #pragma unroll
     for (int d = m; d >= 1; --d) {
-        const double a0r = fr[0], a0i = fi[0], adr = fr[d], adi = fi[d];
-        const double p0 = a0r * a0r + a0i * a0i, pd = adr * adr + adi * adi;
-        const double g = p0 - pd;
-        ok = ok && (fabs(g) > 1e-9 * (p0 + pd));
-        neg |= (g < 0.0 ? 1u : 0u) << d;
+        const T a0r = fr[0], adr = fr[d], adi = fi[d];
+        const T a0i = d == m ? fi[0] : (T)0;
+        const T p0 = fma_t(a0r, a0r, a0i * a0i), pd = fma_t(adr, adr, adi * adi);
+        const T g = p0 - pd;
+        ok = ok && ((g < (T)0 ? -g : g) > margin * (p0 + pd));
+        neg |= (g < (T)0 ? 1u : 0u) << d;
         // any positive scale keeps the signs that are read; folded into a0 and a_d
-        const double sc = __builtin_amdgcn_rcp(p0 + pd);
-        const double br = a0r * sc, bi = a0i * sc, cr = adr * sc, ci = adi * sc;
+        const T sc = rcp_est(p0 + pd);
+        const T br = a0r * sc, cr = adr * sc, ci = adi * sc;
         // new_i = conj(a0) a_i - a_d conj(a_{d-i}) (times sc), in place over the pairs (i, d-i)
+        if (d == m) {
+            const T bi = a0i * sc;
 #pragma unroll
-        for (int i = 1; 2 * i <= d; ++i) {
-            const int k = d - i;
-            const double xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
-            fr[i] = fma(br, xr, fma(bi, xi, -fma(cr, yr, ci * yi)));
-            fi[i] = fma(br, xi, fma(-bi, xr, -fma(ci, yr, -cr * yi)));
-            fr[k] = fma(br, yr, fma(bi, yi, -fma(cr, xr, ci * xi)));
-            fi[k] = fma(br, yi, fma(-bi, yr, -fma(ci, xr, -cr * xi)));
+            for (int i = 1; 2 * i <= d; ++i) {
+                const int k = d - i;
+                const T xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
+                fr[i] = fma_t(br, xr, fma_t(bi, xi, -fma_t(cr, yr, ci * yi)));
+                fi[i] = fma_t(br, xi, fma_t(-bi, xr, -fma_t(ci, yr, -cr * yi)));
+                fr[k] = fma_t(br, yr, fma_t(bi, yi, -fma_t(cr, xr, ci * xi)));
+                fi[k] = fma_t(br, yi, fma_t(-bi, yr, -fma_t(ci, xr, -cr * xi)));
+            }
+        } else {
+#pragma unroll
+            for (int i = 1; 2 * i < d; ++i) {
+                const int k = d - i;
+                const T xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
+                fr[i] = fma_t(br, xr, -fma_t(cr, yr, ci * yi));
+                fi[i] = fma_t(br, xi, -fma_t(ci, yr, -cr * yi));
+                fr[k] = fma_t(br, yr, -fma_t(cr, xr, ci * xi));
+                fi[k] = fma_t(br, yi, -fma_t(ci, xr, -cr * xi));
+            }
+            if (d % 2 == 0) {                         // the middle coefficient is its own partner
+                const int i = d / 2;
+                const T xr = fr[i], xi = fi[i];
+                fr[i] = fma_t(br, xr, -fma_t(cr, xr, ci * xi));
+                fi[i] = fma_t(br, xi, -fma_t(ci, xr, -cr * xi));
+            }
         }
         fr[0] = g * sc;
-        fi[0] = 0.0;
+        fi[0] = (T)0;
     }
     int count = 0;
 #pragma unroll
@@ -525,6 +552,10 @@ __device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], doubl
     return ok ? count : -1;
 }
 
+template <int m>
+__device__ __forceinline__ int zeros_inside_unit_disk(double (&fr)[m + 1], double (&fi)[m + 1]) {
+    return schur_cohn_count<m, double>(fr, fi, 1e-9);
+}
 
 constexpr double kCertMargin = 1e-6;  // relative radius margin of the nearest-pair certificate
 
@@ -534,11 +565,61 @@ __device__ __forceinline__ double rcp64(double x) {
     return r * fma(-x, r, 2.0);
 }
 
-// Newton's iteration for a root z of the root-MUSIC polynomial (coefficients
-// ar, ai; paper Eq. 12) whose mate 1/conj(z) is a root as well -- every root
-// of this polynomial has its mate, c_{-k} = conj(c_k) -- with the mate divided
-// out (Maehly's correction), which keeps the convergence quadratic although
-// the two roots nearly coincide near the unit circle:
+// z^N for N >= 0 by squaring (N is a compile-time constant).
+template <int N, typename T>
+__device__ __forceinline__ void cpow(T xr, T xi, T& pr, T& pi) {
+    if constexpr (N == 0) {
+        pr = (T)1;
+        pi = (T)0;
+    } else if constexpr (N == 1) {
+        pr = xr;
+        pi = xi;
+    } else if constexpr (N % 2 == 0) {
+        T hr, hi;
+        cpow<N / 2, T>(xr, xi, hr, hi);
+        pr = fma_t(hr, hr, -hi * hi);
+        pi = (T)2 * hr * hi;
+    } else {
+        T hr, hi;
+        cpow<N - 1, T>(xr, xi, hr, hi);
+        pr = fma_t(hr, xr, -hi * xi);
+        pi = fma_t(hr, xi, hi * xr);
+    }
+}
+
+// The root-MUSIC polynomial and its derivative at z from the signal vector
+// itself.  With u conjugate-symmetric (u_{L-1-i} = conj(u_i), u = Q v) the
+// diagonal sums of u u^H are the coefficients of B(z)^2, B(z) = sum_i
+// conj(u_i) z^i, so P(z) = L z^{L-1} - B(z)^2 and P'(z) = L (L-1) z^{L-2} -
+// 2 B(z) B'(z): Horner over the L coefficients of B instead of the 2L - 1 of
+// P (the same polynomial; its rounded FP32 coefficients serve the
+// certificate and the all-roots path).
+template <int L, typename T>
+__device__ __forceinline__ void music_poly_eval(const float (&ur)[L], const float (&ui)[L], T xr, T xi, T& Pr, T& Pi,
+                                                T& Dr, T& Di) {
+    T Br = (T)ur[L - 1], Bi = -(T)ui[L - 1], Er = (T)0, Ei = (T)0;   // B and B'
+#pragma unroll
+    for (int j = L - 2; j >= 0; --j) {
+        const T nEr = fma_t(Er, xr, fma_t(-Ei, xi, Br)), nEi = fma_t(Er, xi, fma_t(Ei, xr, Bi));
+        const T nBr = fma_t(Br, xr, fma_t(-Bi, xi, (T)ur[j]));
+        const T nBi = fma_t(Br, xi, fma_t(Bi, xr, -(T)ui[j]));
+        Er = nEr; Ei = nEi; Br = nBr; Bi = nBi;
+    }
+    T qr, qi;                                          // z^{L-2}
+    cpow<L - 2, T>(xr, xi, qr, qi);
+    const T wr = fma_t(qr, xr, -qi * xi), wi = fma_t(qr, xi, qi * xr);   // z^{L-1}
+    // P = L z^{L-1} - B^2,  P' = L (L-1) z^{L-2} - 2 B B'
+    Pr = fma_t((T)L, wr, -fma_t(Br, Br, -Bi * Bi));
+    Pi = fma_t((T)L, wi, -(T)2 * Br * Bi);
+    Dr = fma_t((T)(L * (L - 1)), qr, -(T)2 * fma_t(Br, Er, -Bi * Ei));
+    Di = fma_t((T)(L * (L - 1)), qi, -(T)2 * fma_t(Br, Ei, Bi * Er));
+}
+
+// Newton's iteration for a root z of the root-MUSIC polynomial (paper
+// Eq. 12) whose mate 1/conj(z) is a root as well -- every root of this
+// polynomial has its mate, c_{-k} = conj(c_k) -- with the mate divided out
+// (Maehly's correction), which keeps the convergence quadratic although the
+// two roots nearly coincide near the unit circle:
 //   z <- z - P(z) / (P'(z) - P(z) / (z - 1/conj(z)))
 // FP32 approach to the same root: at most `iters` steps of the iteration
 // above in FP32, ending at the first step below 1e-3 |z|.  Per-phase counters
@@ -547,24 +628,18 @@ __device__ __forceinline__ double rcp64(double x) {
 // steps below stop after about one step (numpy trials: FP64 steps of a
 // wave's slowest lane 3.4 -> 1.3 at 10 dB, plus 2.5 FP32 steps).  A
 // non-finite step leaves z at the last finite iterate.
-template <int n>
-__device__ __forceinline__ void pair_newton32(const float (&ar)[n + 1], const float (&ai)[n + 1], double& zr,
-                                              double& zi, int iters, int* its) {
+template <int L>
+__device__ __forceinline__ void pair_newton32(const float (&ur)[L], const float (&ui)[L], double& zr, double& zi,
+                                              int iters, int* its) {
     float xr = (float)zr, xi = (float)zi;
     for (int it = 0; it < iters; ++it) {
         if (its) ++*its;
-        float Pr = ar[n], Pi = ai[n], Dr = 0.f, Di = 0.f;
-#pragma unroll
-        for (int j = n - 1; j >= 0; --j) {
-            const float nDr = fmaf(Dr, xr, fmaf(-Di, xi, Pr)), nDi = fmaf(Dr, xi, fmaf(Di, xr, Pi));
-            const float nPr = fmaf(Pr, xr, fmaf(-Pi, xi, ar[j]));
-            const float nPi = fmaf(Pr, xi, fmaf(Pi, xr, ai[j]));
-            Dr = nDr; Di = nDi; Pr = nPr; Pi = nPi;
-        }
+        float Pr, Pi, Dr, Di;
+        music_poly_eval<L, float>(ur, ui, xr, xi, Pr, Pi, Dr, Di);
         const float f = 1.f - frcp(fmaf(xr, xr, xi * xi));
-        const float ur = xr * f, ui = xi * f;
-        const float nr = fmaf(Pr, ur, -Pi * ui), ni = fmaf(Pr, ui, Pi * ur);
-        const float dr = fmaf(Dr, ur, -Di * ui) - Pr, di = fmaf(Dr, ui, Di * ur) - Pi;
+        const float ur_ = xr * f, ui_ = xi * f;
+        const float nr = fmaf(Pr, ur_, -Pi * ui_), ni = fmaf(Pr, ui_, Pi * ur_);
+        const float dr = fmaf(Dr, ur_, -Di * ui_) - Pr, di = fmaf(Dr, ui_, Di * ur_) - Pi;
         const float q = frcp(fmaf(dr, dr, di * di));
         const float sr = fmaf(nr, dr, ni * di) * q, si = fmaf(ni, dr, -nr * di) * q;
         if (!(finitef(sr) && finitef(si))) break;
@@ -580,31 +655,25 @@ __device__ __forceinline__ void pair_newton32(const float (&ar)[n + 1], const fl
 
 // At most `iters` steps; true once a step meets the stop rule above, false
 // when none did or a step is not finite.
-template <int n>
-__device__ __forceinline__ bool pair_newton(const float (&ar)[n + 1], const float (&ai)[n + 1], double& zr, double& zi,
+template <int L>
+__device__ __forceinline__ bool pair_newton(const float (&ur)[L], const float (&ui)[L], double& zr, double& zi,
                                             int iters, int* its) {
     for (int it = 0; it < iters; ++it) {
         if (its) ++*its;
-        double Pr = ar[n], Pi = ai[n], Dr = 0.0, Di = 0.0;
-#pragma unroll
-        for (int j = n - 1; j >= 0; --j) {
-            const double nDr = fma(Dr, zr, fma(-Di, zi, Pr)), nDi = fma(Dr, zi, fma(Di, zr, Pi));
-            const double nPr = fma(Pr, zr, fma(-Pi, zi, (double)ar[j]));
-            const double nPi = fma(Pr, zi, fma(Pi, zr, (double)ai[j]));
-            Dr = nDr; Di = nDi; Pr = nPr; Pi = nPi;
-        }
+        double Pr, Pi, Dr, Di;
+        music_poly_eval<L, double>(ur, ui, zr, zi, Pr, Pi, Dr, Di);
         // u = z - 1/conj(z) = z (1 - 1/|z|^2); step = P u / (P' u - P)
         const double f = 1.0 - rcp64(fma(zr, zr, zi * zi));
-        const double ur = zr * f, ui = zi * f;
-        const double nr = fma(Pr, ur, -Pi * ui), ni = fma(Pr, ui, Pi * ur);
-        const double dr = fma(Dr, ur, -Di * ui) - Pr, di = fma(Dr, ui, Di * ur) - Pi;
+        const double ur_ = zr * f, ui_ = zi * f;
+        const double nr = fma(Pr, ur_, -Pi * ui_), ni = fma(Pr, ui_, Pi * ur_);
+        const double dr = fma(Dr, ur_, -Di * ui_) - Pr, di = fma(Dr, ui_, Di * ur_) - Pi;
         const double q = rcp64(fma(dr, dr, di * di));
         const double sr = fma(nr, dr, ni * di) * q, si = fma(ni, dr, -nr * di) * q;
         if (!(__builtin_isfinite(sr) && __builtin_isfinite(si))) return false;
         zr -= sr;
         zi -= si;
         const double st = fabs(sr) + fabs(si);
-        if (st <= kPairStepTol * (fabs(zr) + fabs(zi)) && st <= kPairMateTol * (fabs(ur) + fabs(ui))) return true;
+        if (st <= kPairStepTol * (fabs(zr) + fabs(zi)) && st <= kPairMateTol * (fabs(ur_) + fabs(ui_))) return true;
     }
     return false;
 }
@@ -618,34 +687,7 @@ constexpr float kCount32Margin = 1e-2f;
 
 template <int m>
 __device__ __forceinline__ int zeros_inside_unit_disk32(float (&fr)[m + 1], float (&fi)[m + 1]) {
-    unsigned neg = 0;
-    bool ok = true;
-#pragma unroll
-    for (int d = m; d >= 1; --d) {
-        const float a0r = fr[0], a0i = fi[0], adr = fr[d], adi = fi[d];
-        const float p0 = fmaf(a0r, a0r, a0i * a0i), pd = fmaf(adr, adr, adi * adi);
-        const float g = p0 - pd;
-        ok = ok && (fabsf(g) > kCount32Margin * (p0 + pd));
-        neg |= (g < 0.f ? 1u : 0u) << d;
-        const float sc = frcp(p0 + pd);
-        const float br = a0r * sc, bi = a0i * sc, cr = adr * sc, ci = adi * sc;
-#pragma unroll
-        for (int i = 1; 2 * i <= d; ++i) {
-            const int k = d - i;
-            const float xr = fr[i], xi = fi[i], yr = fr[k], yi = fi[k];
-            fr[i] = fmaf(br, xr, fmaf(bi, xi, -fmaf(cr, yr, ci * yi)));
-            fi[i] = fmaf(br, xi, fmaf(-bi, xr, -fmaf(ci, yr, -cr * yi)));
-            fr[k] = fmaf(br, yr, fmaf(bi, yi, -fmaf(cr, xr, ci * xi)));
-            fi[k] = fmaf(br, yi, fmaf(-bi, yr, -fmaf(ci, xr, -cr * xi)));
-        }
-        fr[0] = g * sc;
-        fi[0] = 0.f;
-    }
-    int count = 0;
-#pragma unroll
-    for (int d = 1; d <= m; ++d)
-        if ((neg >> d) & 1u) count = d - count;
-    return ok ? count : -1;
+    return schur_cohn_count<m, float>(fr, fi, kCount32Margin);
 }
 
 // Quotient q_0 .. q_{n-2} of P (degree n) by z^2 - r z - s, in FP64,
@@ -740,8 +782,8 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
         z0i *= im;
         m2 = fma(z0r, z0r, z0i * z0i);
     }
-    const double rin = sqrt(m2);
-    if (!(1.0 - rin > 1e-9)) return false;
+    constexpr double kInnerMax2 = (1.0 - 1e-9) * (1.0 - 1e-9);
+    if (!(m2 < kInnerMax2)) return false;             // |z_in| within 1e-9 of the circle
     const double im2 = rcp64(m2);
     const double z1r = z0r * im2, z1i = z0i * im2;   // 1/conj(z_in)
     rr = z0r + z1r;
@@ -759,18 +801,19 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
         constexpr int m = n - 2;
         float qr[n - 1], qi[n - 1];
         if (!(pair_quotient<n, float>(ar, ai, rr, ri, s_r, s_i, qr, qi) <= remtol)) return false;
-        if (rin * (1.0 - kCertMargin) >= (double)kCertKappa) {
+        constexpr double kKappaIn = (double)kCertKappa / (1.0 - kCertMargin);
+        if (m2 >= kKappaIn * kKappaIn) {              // rho = |z_in| (1 - margin) >= kappa
             float gr[m], gi[m];
             first_schur_step<m, float>(qr, qi, kCertKappa, gr, gi);
             if (zeros_inside_unit_disk32<m - 1>(gr, gi) == L - 2) return true;
         }
         double fr[n - 1], fi[n - 1];                  // undecided: the quotient again, in FP64
         pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi);
-        return inner_roots_inside<L>(fr, fi, rin);
+        return inner_roots_inside<L>(fr, fi, sqrt(m2));
     } else {
         double fr[n - 1], fi[n - 1];
         if (!(pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= remtol)) return false;
-        return inner_roots_inside<L>(fr, fi, rin);
+        return inner_roots_inside<L>(fr, fi, sqrt(m2));
     }
 }
 
@@ -1232,8 +1275,8 @@ __device__ __forceinline__ void window_omega_v(const float (&v)[L], const RootTe
     if (!full_roots) {
         double zr0, zi0, rr = 0.0, ri = 0.0;
         pair_start<L>(v, cw0, sw0, zr0, zi0);
-        pair_newton32<n>(ar, ai, zr0, zi0, kCertIters32, &ls.pair_its32);
-        cert = pair_newton<n>(ar, ai, zr0, zi0, kCertIters, &ls.pair_its) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
+        pair_newton32<L>(ur, ui, zr0, zi0, kCertIters32, &ls.pair_its32);
+        cert = pair_newton<L>(ur, ui, zr0, zi0, kCertIters, &ls.pair_its) && certified_root<L>(ar, ai, zr0, zi0, rr, ri);
         if (cert) omega = atan2f((float)ri, (float)rr);
     }
     ls.accepted += cert ? 1 : 0;
