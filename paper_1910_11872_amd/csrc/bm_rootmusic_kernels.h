@@ -51,22 +51,33 @@
 namespace bm {
 namespace {
 
-// Line windows per lane: the lag sums of a lane's second start are slid from
-// its first, so each start costs about half the direct sum.  Blocks start at
-// even pixels, so which window starts are summed directly and which are slid
-// depends on the start alone, not on the tile size: results are the same for
-// every tiling.  (Four starts per lane halve the lag-sum work again but
-// double the lag sums a block keeps in LDS, which halves the blocks resident
-// per CU: twice slower on 1024-wide lines.)
+// Line windows per lane (two window starts per lane).  For L <= 6 a lane sums
+// the lags of its two starts, the second slid from the first (lag_sums_pair);
+// for L >= 7 a lane pair sums the lags of four consecutive starts, one half of
+// the lags each, the first start directly and the next three slid by one
+// sample (lag_sums_quad), so each start costs about a quarter of a direct sum
+// over all lags while the block keeps the same 2 x 256 starts in LDS.  (At
+// L = 6 the quarter-cost form measured 3-6% slower: with three lags per lane
+// its two LDS reads per snapshot weigh more than the FMAs it saves.)  Blocks
+// start at multiples of two (four) pixels, so which window starts are summed
+// directly and which are slid depends on the start alone, not on the tile
+// size: results are the same for every tiling.  (Four starts per lane, each
+// lane with all lags, double the lag sums a block keeps in LDS, which halves
+// the blocks resident per CU: twice slower on 1024-wide lines.)
 constexpr int kLineSpan = 2;
 
-constexpr int line_windows_per_block(int L, int block) { return (kLineSpan * block - (L - 1)) & ~1; }
+constexpr bool line_quad(int L) { return L >= 7; }
+constexpr int line_windows_per_block(int L, int block) {
+    return (kLineSpan * block - (L - 1)) & (line_quad(L) ? ~3 : ~1);
+}
 
 template <int L, int BLOCK>
 struct LineSpan {
     static constexpr int span = kLineSpan * BLOCK;                  // window starts per block
-    static constexpr int wpb = line_windows_per_block(L, BLOCK);    // output pixels per block (even)
+    static constexpr int wpb = line_windows_per_block(L, BLOCK);    // output pixels per block (even; L >= 7: x4)
+    static constexpr bool quad = line_quad(L);                      // lag_sums_quad (else lag_sums_pair)
     static constexpr int row = span + 8;                            // lag-sum row: >= span, 16-byte multiple
+    static constexpr int quarter = sg_quarter(span + kMaxN);        // staged samples, de-interleaved
 };
 
 // One block of windows: SPAN-(L-1) consecutive pixels p0.. of one line of job J.
@@ -85,13 +96,22 @@ __device__ __forceinline__ void rootmusic_block(const RmJob& J, int line, int p0
 
     // window of pixel p0+s starts at base+s
     const int base = p0 - half;
-    for (int i = t; i < SPAN + N - 1; i += BLOCK) {
-        const int q = base + i;
-        sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
+    // ---- lag sums S_d(base + s), s < SPAN, d < L -----------------------------
+    if constexpr (LineSpan<L, BLOCK>::quad) {
+        for (int i = t; i < SPAN + N; i += BLOCK) {        // one sample more for the odd-L dummy lag
+            const int q = base + i;
+            sg[sg_slot(i, LineSpan<L, BLOCK>::quarter)] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        lag_sums_quad<L, LineSpan<L, BLOCK>::row, LineSpan<L, BLOCK>::quarter>(sg, t, K, sS);
+    } else {
+        for (int i = t; i < SPAN + N - 1; i += BLOCK) {
+            const int q = base + i;
+            sg[i] = (q >= 0 && q < len) ? g[q] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        lag_sums_pair<L, LineSpan<L, BLOCK>::row>(sg, kLineSpan * t, K, sS);
     }
-    __syncthreads();
-    // ---- lag sums S_d(base+2t), S_d(base+2t+1), d < L ---------------------
-    lag_sums_pair<L, LineSpan<L, BLOCK>::row>(sg, kLineSpan * t, K, sS);
     __syncthreads();
 
 #pragma unroll 1
@@ -267,7 +287,7 @@ void rootmusic_kernel(RmBatch B) {
     // line windows: staged signal + lag sums; block windows: the block's staged rows
     constexpr int ROW = BLOCKWIN ? BLOCK + L : LineSpan<L, BLOCK>::row;
     constexpr int WPB = BLOCKWIN ? BLOCK - (L - 1) : LineSpan<L, BLOCK>::wpb;
-    __shared__ float2 sg[BLOCKWIN ? 1 : LineSpan<L, BLOCK>::span + kMaxN];
+    __shared__ float2 sg[BLOCKWIN ? 1 : 4 * LineSpan<L, BLOCK>::quarter];
     __shared__ __align__(16) float2 sS[L][ROW];
     LaneStats ls;
     // LOOP = false: exactly one item, blockIdx.x (a trip count of one the compiler sees)

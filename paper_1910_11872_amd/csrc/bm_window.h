@@ -967,6 +967,99 @@ __device__ __forceinline__ void lag_sums_pair(const float2* g, int q, int K, flo
     }
 }
 
+// Staged line samples in LDS, de-interleaved by index mod 4: sample i sits in
+// slot (i & 3) Q + (i >> 2), Q = the quarter length.  The lane pairs below
+// read samples four starts apart; in a plain layout a wave's 32 distinct
+// addresses would fall on a quarter of the LDS banks, de-interleaved they are
+// consecutive slots.
+constexpr int sg_quarter(int n) { return (n + 3) / 4; }
+__device__ __forceinline__ int sg_slot(int i, int quarter) { return (i & 3) * quarter + (i >> 2); }
+
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+
+// Lag sums S_d(q) = sum_{k<K} g[q+k] conj(g[q+k+d]), d < L, of the four
+// window starts q .. q+3, q = 4 (t / 2), computed by the lane pair (t, t ^ 1):
+// lane h = t & 1 takes the lags d0 .. d0 + LH - 1, d0 = h LH, LH = ceil(L/2)
+// (for odd L the second lane's last lag is a dummy, not stored; its sums read
+// one sample past the last window's, which is staged as well).  The first
+// start's sums are direct over its K snapshots, with the b-samples g[q+k+d]
+// in a circular register buffer indexed by k mod LH (unrolled lcm(LH, 4)
+// steps at a time, so that neither register moves nor run-time slot
+// arithmetic are needed); the next three are slid by one sample each,
+//   S_d(s+1) = S_d(s) - g[s] conj(g[s+d]) + g[s+K] conj(g[s+K+d]),
+// so each start costs about a quarter of a direct sum over all lags.  Blocks
+// start at multiples of four pixels, so which starts are summed directly
+// depends on the start alone, not on the tile size.  g is in the
+// de-interleaved layout above (quarter length QUARTER): the slot of sample
+// q + off + 4a + r is base[r] + a for per-lane bases of the offsets 0, d0, K
+// and K + d0.  Stored as two 16-byte pairs per lag to sS[d][q .. q+3]
+// (16-byte aligned rows).  S_0's imaginary part is not meaningful (readers
+// take the zero lag as real).
+template <int L, int STRIDE, int QUARTER>
+__device__ __forceinline__ void lag_sums_quad(const float2* g, int t, int K, float2 (*sS)[STRIDE]) {
+    constexpr int LH = (L + 1) / 2;
+    constexpr int U = LH * 4 / gcd_int(LH, 4);
+    const int jq = t >> 1;                               // q / 4
+    const int q = 4 * jq;
+    const int d0 = (t & 1) * LH;
+    int ba[4], bb[4], bk[4], bkd[4];                      // slot bases of q + {0, d0, K, K + d0} + r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        ba[r] = r * QUARTER + jq;
+        bb[r] = ((d0 + r) & 3) * QUARTER + jq + ((d0 + r) >> 2);
+        bk[r] = ((K + r) & 3) * QUARTER + jq + ((K + r) >> 2);
+        bkd[r] = ((K + d0 + r) & 3) * QUARTER + jq + ((K + d0 + r) >> 2);
+    }
+    float sr[LH], si[LH];
+#pragma unroll
+    for (int e = 0; e < LH; ++e) { sr[e] = 0.f; si[e] = 0.f; }
+    float2 win[LH];                      // win[(k + e) mod LH] = g[q + d0 + k + e]
+#pragma unroll
+    for (int e = 0; e < LH - 1; ++e) win[e] = g[bb[e & 3] + (e >> 2)];
+    // k = k0 + u with k0 a multiple of U: every slot index below is a base plus a constant
+    auto term = [&](int a4, int u) {
+        const int c = u + LH - 1;
+        win[(u + LH - 1) % LH] = g[bb[c & 3] + a4 + (c >> 2)];
+        const float2 a = g[ba[u & 3] + a4 + (u >> 2)];
+#pragma unroll
+        for (int e = 0; e < LH; ++e) {
+            const float2 b = win[(u + e) % LH];
+            sr[e] = fmaf(a.x, b.x, fmaf(a.y, b.y, sr[e]));
+            si[e] = fmaf(a.y, b.x, fmaf(-a.x, b.y, si[e]));
+        }
+    };
+    int k0 = 0;
+    for (; k0 + U <= K; k0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) term(k0 >> 2, u);
+    }
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u)
+        if (k0 + u < K) term(k0 >> 2, u);
+    auto slide = [&](int st) {                          // S(q + st) -> S(q + st + 1), st compile-time
+        const float2 a0 = g[ba[st & 3] + (st >> 2)], a1 = g[bk[st & 3] + (st >> 2)];
+#pragma unroll
+        for (int e = 0; e < LH; ++e) {
+            const int c = st + e;
+            const float2 b0 = g[bb[c & 3] + (c >> 2)], b1 = g[bkd[c & 3] + (c >> 2)];
+            sr[e] = fmaf(a1.x, b1.x, fmaf(a1.y, b1.y, fmaf(-a0.x, b0.x, fmaf(-a0.y, b0.y, sr[e]))));
+            si[e] = fmaf(a1.y, b1.x, fmaf(-a1.x, b1.y, fmaf(-a0.y, b0.x, fmaf(a0.x, b0.y, si[e]))));
+        }
+    };
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float pr[LH], pi[LH];
+#pragma unroll
+        for (int e = 0; e < LH; ++e) { pr[e] = sr[e]; pi[e] = si[e]; }
+        slide(2 * h);
+#pragma unroll
+        for (int e = 0; e < LH; ++e)
+            if (d0 + e < L)
+                *reinterpret_cast<float4*>(&sS[d0 + e][q + 2 * h]) = make_float4(pr[e], pi[e], sr[e], si[e]);
+        if (h == 0) slide(1);
+    }
+}
+
 // Divide T by its trace; false when the trace is zero or not finite (no
 // signal subspace).
 template <int L>
