@@ -514,6 +514,40 @@ __global__ __launch_bounds__(kTrThreads) void transpose_kernel(TrBatch B) {
     constexpr int T = kTrTile, S = kTrThreads / kTrTile;
     float (*tile)[T + 1] = reinterpret_cast<float (*)[T + 1]>(smem);
     const int bx = (tid % J.tiles_x) * T, by = (tid / J.tiles_x) * T;
+    // Whole FP32/FP16 tiles with 16-byte aligned rows on both sides: each thread
+    // moves four runs of four elements (one 16- or 8-byte load, one 16-byte
+    // store each) instead of sixteen single elements.
+    const bool vec = (elem == (int)Elem::F32 || elem == (int)Elem::F16) && bx + T <= cols && by + T <= rows &&
+                     (J.src_ls & 3) == 0 && (rows & 3) == 0 && ((uintptr_t)J.src & 15) == 0 &&
+                     ((uintptr_t)J.dst & 15) == 0;
+    if (vec) {
+        constexpr int G = T / 4, RS = kTrThreads / G;        // 16 groups of four columns, 16 rows a round
+        const int c4 = (threadIdx.x % G) * 4, r0 = threadIdx.x / G;
+#pragma unroll
+        for (int jj = 0; jj < T; jj += RS) {
+            const int64_t idx = (int64_t)(by + r0 + jj) * J.src_ls + bx + c4;
+            float4 v;
+            if (elem == (int)Elem::F32) {
+                v = *reinterpret_cast<const float4*>(static_cast<const float*>(J.src) + idx);
+            } else {
+                typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+                const h4 h = *reinterpret_cast<const h4*>(static_cast<const _Float16*>(J.src) + idx);
+                v = make_float4((float)h[0], (float)h[1], (float)h[2], (float)h[3]);
+            }
+            tile[r0 + jj][c4] = v.x;
+            tile[r0 + jj][c4 + 1] = v.y;
+            tile[r0 + jj][c4 + 2] = v.z;
+            tile[r0 + jj][c4 + 3] = v.w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < T; jj += RS) {
+            const int c = r0 + jj;                             // destination row bx + c, elements by + c4 ..
+            const float4 v = make_float4(tile[c4][c], tile[c4 + 1][c], tile[c4 + 2][c], tile[c4 + 3][c]);
+            *reinterpret_cast<float4*>(static_cast<float*>(J.dst) + (int64_t)(bx + c) * rows + by + c4) = v;
+        }
+        return;
+    }
     const int tx = threadIdx.x % T, ty = threadIdx.x / T;
 #pragma unroll
     for (int jj = 0; jj < T; jj += S) {
