@@ -276,11 +276,19 @@ struct IntJob {
     double cx, cy;
     int64_t anchor_off;
     int W, H, x0, x1, y0, y1;
+    int vec;               // 16-byte loads and stores (integrate_row_vec)
 };
 // Anchors of every job (one block each), then every row of every job (rows
-// job j own prefix[j] .. prefix[j+1]-1); max_w sizes the row LDS.
-hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njobs, int total_rows, int max_w,
-                                 double* anchors, hipStream_t s);
+// job j own prefix[j] .. prefix[j+1]-1) by blocks of `threads` (at least
+// integrate_row_threads of every job); lds_w sizes the row LDS (the widest
+// job whose rows go through LDS, 0 if none).
+hipError_t launch_integrate_many(const IntJob* jobs, const int* prefix, int njobs, int total_rows, int threads,
+                                 int lds_w, double* anchors, hipStream_t s);
+// Whether a map's rows load and store 16 bytes at a time (width a multiple of
+// 4, at most 4096, omega_x and phi 16-byte aligned), and the threads a row
+// needs; neither changes the arithmetic.
+bool integrate_row_vec(int W, const void* wx, const void* phi);
+int integrate_row_threads(int W);
 
 // Allocation-free integration: the anchor column lives in a fixed device array
 // of kNoAllocMaxHeight doubles (512 KiB); its address on the current device.

@@ -1573,7 +1573,7 @@ bm_status bosmusic_integrate_many(bosmusic_t h, const bosmusic_integrate_job* jo
         std::vector<bm::IntJob> tab((size_t)n);
         std::vector<int> prefix(1, 0);
         int64_t anchors = 0;
-        int max_w = 1;
+        int threads = 1, lds_w = 0;
         for (int i = 0; i < n; ++i) {
             const bosmusic_integrate_job& q = jobs[i];
             if (!q.omega_x || !q.phi) return fail(h, BM_E_INVALID_ARG, "job %d: omega_x/phi is NULL", i);
@@ -1598,7 +1598,9 @@ bm_status bosmusic_integrate_many(bosmusic_t h, const bosmusic_integrate_job* jo
             J.y1 = q.omega_y ? q.height - q.Ny + q.Ny / 2 : q.height - 1;
             J.anchor_off = anchors;
             anchors += q.height;
-            max_w = std::max(max_w, q.width);
+            J.vec = bm::integrate_row_vec(q.width, q.omega_x, q.phi) ? 1 : 0;
+            threads = std::max(threads, bm::integrate_row_threads(q.width));
+            if (!J.vec) lds_w = std::max(lds_w, q.width);
             prefix.push_back(prefix.back() + q.height);
         }
         if (n == 0) return BM_OK;
@@ -1643,7 +1645,7 @@ bm_status bosmusic_integrate_many(bosmusic_t h, const bosmusic_integrate_job* jo
         h->int_pending = true;
         const char* dev = (const char*)h->int_dev;
         return check(h, bm::launch_integrate_many((const bm::IntJob*)(dev + toff), (const int*)(dev + poff), n,
-                                                  prefix.back(), max_w, h->int_anchor, st),
+                                                  prefix.back(), threads, lds_w, h->int_anchor, st),
                      "integrate_many");
     } catch (...) {
         return fail(h, BM_E_NOMEM, "host exception in integrate_many");
