@@ -48,9 +48,9 @@ PEAK_HBM = 8.0e12
 # frames): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on two cfg4 frames
 # (profiles/rootmusic_surrogate_cfg4_counters.md).  Valid only for that kernel and configuration;
 # the other configurations report null.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 = (287141.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 = (287190.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
 # The same for the surrogate kernel on those frames (same profile).
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4_SURROGATE = (287457.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4_SURROGATE = (287541.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
 
 
 def bairstow_flops(n: int) -> int:
@@ -59,20 +59,37 @@ def bairstow_flops(n: int) -> int:
     return 32 * (n + 1) + 60
 
 
-def pair_newton_flops(n: int) -> int:
-    """One FP64 Newton step for the signal root with its mate divided out: Horner for P and P'
-    (16 flops per coefficient) and the corrected step (two refined reciprocals, ~62 flops)."""
-    return 16 * n + 62
+def cpow_flops(k: int) -> int:
+    """z^k by squaring (complex square 5 flops, complex product 6)."""
+    if k <= 1:
+        return 0
+    return cpow_flops(k // 2) + 5 + (6 if k % 2 else 0)
 
 
-def certificate_flops(L: int) -> int:
-    """Inner member and mate of the root, division by the pair's factor with the remainder test,
-    the closed-form first Schur-Cohn step on the degree 2L-4 quotient (powers of rho and the
-    scaling) and the recursion on the degree 2L-5 remainder of it (FP64)."""
+def pair_newton_flops(L: int) -> int:
+    """One Newton step for the signal root with its mate divided out, P = L z^(L-1) - B(z)^2
+    evaluated from the signal vector: Horner for B and B' over its L coefficients (16 flops per
+    step), z^(L-2) and z^(L-1), P and P' (16), and the corrected step (two reciprocals, ~62)."""
+    return 16 * (L - 1) + cpow_flops(L - 2) + 6 + 16 + 62
+
+
+def certificate_flops(L: int) -> tuple:
+    """(FP64, FP32) flops of the certificate: the inner member and mate of the root and the
+    division by the pair's factor with the remainder test (FP64), then the root count of the
+    degree m = 2L-4 quotient at the fixed radius 0.8 (FP32): the closed-form first Schur-Cohn
+    step (constant factors, two products per coefficient), the next step with a complex
+    constant term (28 flops per coefficient pair), and the steps after it with the real one
+    (20 per pair, 10 for a middle coefficient), 14 flops of pivots each.  The FP64 recount of
+    the undecided windows is not counted."""
     n = 2 * L - 2
     m = n - 2
-    schur = sum(20 * (d // 2) + 16 for d in range(1, m))
-    return 40 + 18 * (n + 1) + 5 * m + schur
+    division = 36 + 18 * (n + 1)
+    if m <= 0:
+        return division, 0
+    d0 = m - 1
+    schur = 28 * ((d0 + 1) // 2) + 16 if d0 >= 1 else 0
+    schur += sum(20 * ((d - 1) // 2) + (10 if d % 2 == 0 else 0) + 14 for d in range(1, d0))
+    return division, 2 * m + schur
 
 
 def power_route_flops(L: int, steps: float) -> float:
@@ -88,7 +105,7 @@ def power_route_flops(L: int, steps: float) -> float:
 
 def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: float = 0.0,
                      cert_frac: float = 0.0, block: bool = False, pair_iters32: float = 0.0,
-                     power_frac: float = 0.0, power_steps: float = 0.0) -> dict:
+                     power_frac: float = 0.0, power_steps: float = 0.0, quad_lags: bool = True) -> dict:
     """Algorithmic flop count of one window of the root-MUSIC kernel.
 
     FMA = 2 flops; add, sub, mul, rcp, sqrt, rsq = 1 each.  `newton` is the
@@ -98,7 +115,9 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     finished by the certificate, and `iters` the mean simultaneous root
     iterations of the windows whose roots were all found.  Certificate work
     of a window that fails it is not counted.  `block`: the L x L block
-    window, whose covariance is summed directly from its L snapshots.
+    window, whose covariance is summed directly from its L snapshots.  `quad_lags`: the line
+    kernel's lane-pair lag sums of four starts for L >= 7 (the surrogate kernel keeps two starts
+    per lane).
     The eigenvalue Newton steps cost 8L flops each (the characteristic
     polynomial and its derivative), after a 7L + 2 flop start bound.  `power_frac` of
     the windows take the verified power iteration (`power_steps` steps each) instead of
@@ -110,9 +129,12 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
         # block window: T summed straight from the L snapshots, a_k + j b_k = sqrt2 Q^H s_k
         # (2 L adds) and the upper triangle of a a^T + b b^T (two FMAs per entry)
         lag = L * (2 * L + 4 * (L * (L + 1) // 2))
+    elif L >= 7 and quad_lags:
+        # lag sums (complex MAC = 4 FMA; the zero lag is real, 2 FMA): a lane pair sums the
+        # first of four starts directly (K L MACs) and slides to the next three (2 L MACs each)
+        lag = (K * (8 * L - 4) + 3 * (16 * L - 8)) / 4
     else:
-        # lag sums (complex MAC = 4 FMA; the zero lag is real, 2 FMA): a lane sums its first
-        # start directly (K L MACs) and slides to its second (2 L MACs), so per window half of that
+        # a lane sums its first start directly (K L MACs) and slides to its second (2 L MACs)
         lag = (K * (8 * L - 4) + 16 * L - 8) / 2
     # T from R (line windows) and the trace normalisation
     build_t = (0 if block else 3 * L * L) + L + L * (L + 1) // 2
@@ -129,8 +151,9 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     start = 4 * n + 40
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
-    fp32 = common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(n)
-    fp64 = pair_iters * pair_newton_flops(n) + cert_frac * certificate_flops(L) + full * 3 * bairstow_flops(n)
+    cert64, cert32 = certificate_flops(L)
+    fp32 = common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(L) + cert_frac * cert32
+    fp64 = pair_iters * pair_newton_flops(L) + cert_frac * cert64 + full * 3 * bairstow_flops(n)
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
 
@@ -530,7 +553,8 @@ def main():
                 else:
                     wins += H * max(0, W - N + 1) + W * max(0, H - N + 1)
             fl = flops_per_window(L, fr[idx[0]].N, newton, iters, pair_its, cert, block=bool(args.block),
-                                  pair_iters32=pair_its32, power_frac=power_frac, power_steps=psteps)
+                                  pair_iters32=pair_its32, power_frac=power_frac, power_steps=psteps,
+                                  quad_lags=not surrogate)
             per_win = fl["total"]
             entry = {"newton": round(newton, 2), "power_fraction": round(power_frac, 5),
                      "power_steps": round(psteps, 2), "root_iters": round(iters, 2), "windows_per_step": wins,
