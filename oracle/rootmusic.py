@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY -- never imported by the library.
 What is computed, in the paper's order:
 
   * analytic fringe signal Gamma (Eq. 1) from a real frame, by the
-    "bandpass filtering" the paper names in Sec. 2 (reading R1 below);
+    band-pass step of Sec. 2 (reading R1 below);
   * per pixel, a window of N samples along one direction (Sec. 3, moving
     window; reading R2);
   * the autocorrelation matrix R of the window's length-L sub-snapshots
