@@ -22,6 +22,7 @@ MIX = [
     (270, 100, 5, 14, np.float64, "xy"),
     (700, 56, 5, 15, np.uint8, "xy"),       # radix-7 lengths both ways, 8-bit samples
     (263, 40, 4, 16, np.float32, "xy"),     # prime width: Bluestein
+    (700, 40, 7, 20, np.float32, "xy"),     # odd L of the lane-pair lag sums, lines over two blocks
 ]
 
 

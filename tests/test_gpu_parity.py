@@ -71,6 +71,9 @@ CASES = [
     (512, 32, 8, 32, np.float16),
     (360, 60, 8, 64, np.float32),
     (384, 50, 7, 15, np.uint8),
+    (1100, 20, 7, 24, np.float32),   # lane-pair lag sums over three blocks and a ragged tail
+    (700, 22, 7, 9, np.float32),     # K = 3 snapshots: fewer than one unrolled step of the sums
+    (1030, 18, 8, 10, np.float16),
 ]
 
 
