@@ -74,8 +74,9 @@ def pair_newton_flops(L: int) -> int:
 
 
 def certificate_flops(L: int) -> tuple:
-    """(FP64, FP32) flops of the certificate: the inner member and mate of the root and the
-    division by the pair's factor with the remainder test (FP64), then the root count of the
+    """(FP64, FP32) flops of the certificate: the inner member and mate of the root (FP64) and
+    the division by the pair's factor with the remainder test (FP32 for L <= 8, FP64 above), then
+    the root count of the
     degree m = 2L-4 quotient at the fixed radius 0.8 (FP32): the closed-form first Schur-Cohn
     step (constant factors, two products per coefficient), the next step with a complex
     constant term (28 flops per coefficient pair), and the steps after it with the real one
@@ -86,10 +87,15 @@ def certificate_flops(L: int) -> tuple:
     division = 36 + 18 * (n + 1)
     if m <= 0:
         return division, 0
+    if L <= 8:          # the division in FP32 too; the inner member and its mate stay FP64
+        division32 = 18 * (n + 1)
+        division, count0 = 36, division32
+    else:
+        count0 = 0
     d0 = m - 1
     schur = 28 * ((d0 + 1) // 2) + 16 if d0 >= 1 else 0
     schur += sum(20 * ((d - 1) // 2) + (10 if d % 2 == 0 else 0) + 14 for d in range(1, d0))
-    return division, 2 * m + schur
+    return division, count0 + 2 * m + schur
 
 
 def power_route_flops(L: int, steps: float) -> float:

@@ -51,6 +51,12 @@ constexpr int kCertIters = 8;     // then at most this many FP64 Newton steps be
 constexpr double kPairStepTol = 1e-4;
 constexpr double kPairMateTol = 1e-2;
 constexpr double kCertRemTol = 1e-5;
+// The same test with the division in FP32 (line windows of L <= 8): its own
+// rounding leaves up to 2.2e-5 of the coefficients' size at L = 8 (numpy
+// trials over 0-30 dB, N = 16-32; 1e-6 at the median), against remainders
+// of the roots that pass in FP64 below 1e-5 and O(1e-2 .. 1) for one that is
+// not a root, so FP32 allows 1e-4.
+constexpr float kCertRemTol32 = 1e-4f;
 constexpr int kNewtonIters = BM_NEWTON_ITERS;
 constexpr int kInverseIters = BM_INVERSE_ITERS;
 // The one-dimensional signal subspace of Eq. 6-11 needs lambda_1 to stand
@@ -713,6 +719,26 @@ __device__ __forceinline__ double pair_quotient(const float (&ar)[n + 1], const 
     return fabs(b2r) + fabs(b2i) + fabs(b1r) + fabs(b1i);
 }
 
+// The same division in FP32 (the pair's factor rounded to FP32), for the FP32 root count.
+template <int n>
+__device__ __forceinline__ float pair_quotient32(const float (&ar)[n + 1], const float (&ai)[n + 1], float rr, float ri,
+                                                 float s_r, float s_i, float (&fr)[n - 1], float (&fi)[n - 1]) {
+    float b1r = 0.f, b1i = 0.f, b2r = 0.f, b2i = 0.f;
+#pragma unroll
+    for (int k = n; k >= 0; --k) {
+        const float tr = fmaf(s_r, b2r, fmaf(-s_i, b2i, ar[k]));
+        const float ti = fmaf(s_r, b2i, fmaf(s_i, b2r, ai[k]));
+        const float bkr = fmaf(rr, b1r, fmaf(-ri, b1i, tr));
+        const float bki = fmaf(rr, b1i, fmaf(ri, b1r, ti));
+        if (k >= 2) {
+            fr[k - 2] = bkr;
+            fi[k - 2] = bki;
+        }
+        b2r = b1r; b2i = b1i; b1r = bkr; b1i = bki;
+    }
+    return fabsf(b2r) + fabsf(b2i) + fabsf(b1r) + fabsf(b1i);
+}
+
 // Q is self-inversive (P and the pair's factor are), q_{m-k} = conj(q_k) q_m / conj(q_0)
 // with m = 2L - 4, so the first Schur-Cohn step on f(z) = Q(rho z) has the closed form
 // T f = conj(q_0) sum_{k<m} q_k (rho^k - rho^{2m-k}) z^k, with a positive constant term:
@@ -764,7 +790,8 @@ constexpr float kCertKappa = 0.8f;
 // roots.  Every root pair (z, 1/conj z) has its inner member at radius < 1,
 // and the nearest pair is the one with the largest inner radius, so with
 // z_in the inner member of z0's pair: (z - z_in)(z - 1/conj z_in) must divide
-// P (remainder below kCertRemTol of the coefficients' size; a root on the circle,
+// P (remainder below kCertRemTol of the coefficients' size, kCertRemTol32 with the
+// division in FP32 for L <= 8; a root on the circle,
 // its own mirror, fails here), and the quotient Q must have all its L - 2
 // inner roots strictly inside |z| < |z_in| (1 - margin) = rho.  For L <= 8 a
 // decided FP32 count of L - 2 zeros of Q inside kCertKappa <= rho settles it;
@@ -793,14 +820,15 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
     float scale = 0.f;                                // size of the (FP32) coefficients
 #pragma unroll
     for (int k = n; k >= 0; --k) scale += fabsf(ar[k]) + fabsf(ai[k]);
-    const double remtol = kCertRemTol * (double)scale;
     if constexpr (L == 2) {
         double fr[1], fi[1];
-        return pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= remtol;   // no other roots
+        return pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= kCertRemTol * (double)scale;  // no other roots
     } else if constexpr (L <= kCert32MaxL) {
         constexpr int m = n - 2;
         float qr[n - 1], qi[n - 1];
-        if (!(pair_quotient<n, float>(ar, ai, rr, ri, s_r, s_i, qr, qi) <= remtol)) return false;
+        if (!(pair_quotient32<n>(ar, ai, (float)rr, (float)ri, (float)s_r, (float)s_i, qr, qi) <=
+              kCertRemTol32 * scale))
+            return false;
         constexpr double kKappaIn = (double)kCertKappa / (1.0 - kCertMargin);
         if (m2 >= kKappaIn * kKappaIn) {              // rho = |z_in| (1 - margin) >= kappa
             float gr[m], gi[m];
@@ -812,7 +840,7 @@ __device__ __forceinline__ bool certified_root(const float (&ar)[2 * L - 1], con
         return inner_roots_inside<L>(fr, fi, sqrt(m2));
     } else {
         double fr[n - 1], fi[n - 1];
-        if (!(pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= remtol)) return false;
+        if (!(pair_quotient<n, double>(ar, ai, rr, ri, s_r, s_i, fr, fi) <= kCertRemTol * (double)scale)) return false;
         return inner_roots_inside<L>(fr, fi, sqrt(m2));
     }
 }
