@@ -158,8 +158,10 @@ def flops_per_window(L: int, N: int, newton: float, iters: float, pair_iters: fl
     aberth = iters * (n * (30 + 16 * n) + 12 * n * (n - 1) // 2 + 27 * n)
     select = 11 * n
     cert64, cert32 = certificate_flops(L)
-    fp32 = common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(L) + cert_frac * cert32
-    fp64 = pair_iters * pair_newton_flops(L) + cert_frac * cert64 + full * 3 * bairstow_flops(n)
+    # the FP64 Newton stage: P and P' in FP64, the corrected step from them in FP32 (~62 flops)
+    fp32 = (common32 + full * (start + aberth + select) + pair_iters32 * pair_newton_flops(L) + cert_frac * cert32
+            + pair_iters * 62)
+    fp64 = pair_iters * (pair_newton_flops(L) - 62) + cert_frac * cert64 + full * 3 * bairstow_flops(n)
     return {"fp32": fp32, "fp64": fp64, "total": fp32 + fp64}
 
 

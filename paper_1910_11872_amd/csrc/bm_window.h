@@ -666,20 +666,28 @@ __device__ __forceinline__ bool pair_newton(const float (&ur)[L], const float (&
                                             int iters, int* its) {
     for (int it = 0; it < iters; ++it) {
         if (its) ++*its;
-        double Pr, Pi, Dr, Di;
-        music_poly_eval<L, double>(ur, ui, zr, zi, Pr, Pi, Dr, Di);
-        // u = z - 1/conj(z) = z (1 - 1/|z|^2); step = P u / (P' u - P)
-        const double f = 1.0 - rcp64(fma(zr, zr, zi * zi));
-        const double ur_ = zr * f, ui_ = zi * f;
-        const double nr = fma(Pr, ur_, -Pi * ui_), ni = fma(Pr, ui_, Pi * ur_);
-        const double dr = fma(Dr, ur_, -Di * ui_) - Pr, di = fma(Dr, ui_, Di * ur_) - Pi;
-        const double q = rcp64(fma(dr, dr, di * di));
-        const double sr = fma(nr, dr, ni * di) * q, si = fma(ni, dr, -nr * di) * q;
-        if (!(__builtin_isfinite(sr) && __builtin_isfinite(si))) return false;
-        zr -= sr;
-        zi -= si;
-        const double st = fabs(sr) + fabs(si);
-        if (st <= kPairStepTol * (fabs(zr) + fabs(zi)) && st <= kPairMateTol * (fabs(ur_) + fabs(ui_))) return true;
+        double Pr64, Pi64, Dr64, Di64;
+        music_poly_eval<L, double>(ur, ui, zr, zi, Pr64, Pi64, Dr64, Di64);
+        // The residual P (and P') needs FP64; the step formed from them does not: its
+        // relative rounding in FP32 (1e-7) only scales the error left after the step,
+        // and z itself is updated in FP64.  u = z - 1/conj(z) = z (|z|^2 - 1)/|z|^2,
+        // the difference taken in FP64; step = P u / (P' u - P).
+        const double m2 = fma(zr, zr, zi * zi);
+        const float m2f = (float)m2;
+        const float f = (float)(m2 - 1.0) * frcp(m2f);
+        const float xr = (float)zr, xi = (float)zi;
+        const float ur_ = xr * f, ui_ = xi * f;
+        const float Pr = (float)Pr64, Pi = (float)Pi64, Dr = (float)Dr64, Di = (float)Di64;
+        const float nr = fmaf(Pr, ur_, -Pi * ui_), ni = fmaf(Pr, ui_, Pi * ur_);
+        const float dr = fmaf(Dr, ur_, -Di * ui_) - Pr, di = fmaf(Dr, ui_, Di * ur_) - Pi;
+        const float q = frcp(fmaf(dr, dr, di * di));
+        const float sr = fmaf(nr, dr, ni * di) * q, si = fmaf(ni, dr, -nr * di) * q;
+        if (!(finitef(sr) && finitef(si))) return false;
+        zr -= (double)sr;
+        zi -= (double)si;
+        const float st = fabsf(sr) + fabsf(si);
+        if (st <= (float)kPairStepTol * (float)(fabs(zr) + fabs(zi)) && st <= (float)kPairMateTol * (fabsf(ur_) + fabsf(ui_)))
+            return true;
     }
     return false;
 }
