@@ -48,9 +48,9 @@ PEAK_HBM = 8.0e12
 # frames): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from rocprofv3 --pmc on two cfg4 frames
 # (profiles/rootmusic_surrogate_cfg4_counters.md).  Valid only for that kernel and configuration;
 # the other configurations report null.
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 = (287190.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4 = (287208.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
 # The same for the surrogate kernel on those frames (same profile).
-TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4_SURROGATE = (287541.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
+TRAFFIC_BYTES_PER_PIXEL_DIR_CFG4_SURROGATE = (287417.0 * 2.0 + 262144.0) * 1024 / (2 * 2 * 4096 * 4096)
 
 
 def bairstow_flops(n: int) -> int:
