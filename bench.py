@@ -598,18 +598,14 @@ def main():
     results = {}
     for mname in modes:
         mode = bm.BM_SURROGATE if mname == "surrogate" else bm.BM_PLAIN
-        # the production path (graph replay for the uneven batch), then the same
-        # steps with HIP events around every root-MUSIC launch for the roofline
-        if use_graph:
-            gdem = make(mode, graph=True)
-            ms, _ = timed(gdem, mode)
-            gdem.close()
-            dem = make(mode, timing=True)
-            ms_ev, st = timed(dem, mode)
-        else:
-            dem = make(mode, timing=True)
-            ms, st = timed(dem, mode)
-            ms_ev = ms
+        # the production path (graph replay for the uneven batch; otherwise a batch's
+        # two halves pipelined on two streams), then the same steps with HIP events
+        # around every root-MUSIC launch, each launch alone on the chip, for the roofline
+        pdem = make(mode, graph=True) if use_graph else make(mode)
+        ms, _ = timed(pdem, mode)
+        pdem.close()
+        dem = make(mode, timing=True)
+        ms_ev, st = timed(dem, mode)
         dem.close()
         mpx = total_px / (ms / 1e3) / 1e6
         print(f"# {mname}: {args.steps} steps, {ms:.2f} ms/step, {mpx:.1f} Mpixel/s (event-timed pass "

@@ -95,7 +95,8 @@ enum { BM_PLAIN = 0, BM_SURROGATE = 1 };
 /* handle options */
 enum {
     BM_OPT_STATS = 1u,  /* count Jacobi sweeps and root iterations per call */
-    BM_OPT_TIMING = 2u, /* time every root-MUSIC kernel launch with HIP events on its stream */
+    BM_OPT_TIMING = 2u, /* time every root-MUSIC kernel launch with HIP events on its stream
+                           (each launch alone on the device: no two-stream pipelining) */
     BM_OPT_JACOBI = 4u, /* signal subspace by cyclic Jacobi for every window (no power
                            iteration, no tridiagonal solver) */
     BM_OPT_GRAPH = 8u,  /* capture each distinct batch once into a hipGraph and replay it;
@@ -196,7 +197,13 @@ bm_status bosmusic_destroy(bosmusic_t h);
  * group fits the workspace; per group the work runs as one batched transpose
  * launch, one batched analytic-signal launch and one root-MUSIC launch per
  * distinct L (with BM_OPT_GRAPH: one replay of a cached hipGraph holding them,
- * the per-L launches on forked streams).  The job tables of a group are
+ * the per-L launches on forked streams).  Without BM_OPT_GRAPH and
+ * BM_OPT_TIMING, a group of two or more frames runs as two halves on
+ * `stream` and a second stream of the handle: the second half's transpose and
+ * analytic launches run beside the first half's root-MUSIC launch, its
+ * root-MUSIC launch after the first half's; `stream` waits for the second
+ * stream before the call returns, so every output is ordered on `stream`
+ * as if the work had been enqueued there alone.  The job tables of a group are
  * uploaded from pinned host memory on `stream`; the call may wait for the
  * previous call's upload to finish before reusing that buffer.
  * mode: BM_PLAIN, or BM_SURROGATE (needs loaded parameters unless the

@@ -68,6 +68,7 @@ struct bosmusic_s {
     hipStream_t cap[kMaxForks] = {};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kMaxForks] = {};
+    hipEvent_t pipe_ev[3] = {};    // eager two-stream pipeline of a group's halves
     hipStream_t last_graph_stream = nullptr;
     // surrogate
     float* sur_master = nullptr;   // FP32 parameters (BOSMUSIC_MLP_PARAMS)
@@ -458,8 +459,9 @@ size_t append(std::vector<char>& blob, const std::vector<T>& v) {
     return off;
 }
 
-bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1, int mode, GroupPlan& gp) {
-    size_t cur = 0;
+bm_status plan_group(bosmusic_s* h, const bosmusic_frame* frames, int i0, int i1, int mode, GroupPlan& gp,
+                     size_t ws_base = 0) {
+    size_t cur = ws_base;   // the group's workspace starts here
     std::map<std::pair<int, int>, RmSet> sets;   // (L, pass + 2 * block) -> set
     bool any_flags = false;
     for (int i = i0; i < i1; ++i) any_flags |= frames[i].flags != nullptr;
@@ -798,6 +800,50 @@ bm_status run_group_eager(bosmusic_s* h, GroupPlan& gp, hipStream_t st) {
     for (auto& s : gp.rm)
         if ((r = launch_rm(h, s, st, timing, gp.mode))) return r;
     return launch_back(h, gp, st);
+}
+
+// `to` waits for the work enqueued on `from` so far.
+bm_status stream_after(bosmusic_s* h, hipEvent_t ev, hipStream_t from, hipStream_t to) {
+    bm_status r;
+    if ((r = check(h, hipEventRecord(ev, from), "pipeline event"))) return r;
+    return check(h, hipStreamWaitEvent(to, ev, 0), "pipeline wait");
+}
+
+// A group in two halves a, b (disjoint frames and workspace) on two streams,
+// so that one half's transposes and analytic step, bound by memory latency,
+// run beside the other half's root-MUSIC launch, bound by VALU issue.  st runs
+// a's front, a's root-MUSIC, a's back; the second stream runs b's front once
+// a's front is done, b's root-MUSIC once a's is done (the two root-MUSIC
+// launches never share the chip), then b's back; st waits for the second
+// stream before this returns, so the caller sees one stream-ordered call.
+bm_status run_pair_eager(bosmusic_s* h, GroupPlan& a, GroupPlan& b, hipStream_t st) {
+    bm_status r;
+    const size_t boff = align_up(a.blob.size(), 256);
+    const size_t bytes = boff + b.blob.size();
+    if ((r = ensure_upload_buffers(h, bytes, st))) return r;
+    if (h->pin_pending && (r = check(h, hipEventSynchronize(h->pin_ev), "upload wait"))) return r;
+    std::memcpy(h->pin, a.blob.data(), a.blob.size());
+    std::memcpy(h->pin + boff, b.blob.data(), b.blob.size());
+    if ((r = check(h, hipMemcpyAsync(h->djobs, h->pin, bytes, hipMemcpyHostToDevice, st), "job upload"))) return r;
+    if ((r = check(h, hipEventRecord(h->pin_ev, st), "upload event"))) return r;
+    h->pin_pending = true;
+    bind_group(h, a, (const char*)h->djobs);
+    bind_group(h, b, (const char*)h->djobs + boff);
+    hipStream_t s1 = h->cap[1];
+    const bool timing = (h->options & BM_OPT_TIMING) != 0;
+    if ((r = launch_front(h, a, st)) || (r = stream_after(h, h->pipe_ev[0], st, s1))) return r;
+    // from here on the second stream holds work: join it on every return
+    if (!(r = launch_front(h, b, s1)))
+        for (auto& s : a.rm)
+            if ((r = launch_rm(h, s, st, timing, a.mode))) break;
+    if (!r && !(r = stream_after(h, h->pipe_ev[1], st, s1))) {
+        for (auto& s : b.rm)
+            if ((r = launch_rm(h, s, s1, timing, b.mode))) break;
+        if (!r) r = launch_back(h, b, s1);
+    }
+    if (!r) r = launch_back(h, a, st);
+    const bm_status j = stream_after(h, h->pipe_ev[2], s1, st);
+    return r ? r : j;
 }
 
 // Signature of a call: every frame field, mode-relevant options and tuning.
@@ -1315,6 +1361,8 @@ void release(bosmusic_s* h) {
         }
     if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
     if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    for (auto& e : h->pipe_ev)
+        if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < kMaxForks; ++i) {
         if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
         if (h->cap[i]) (void)hipStreamDestroy(h->cap[i]);
@@ -1388,6 +1436,8 @@ bm_status bosmusic_create(const bosmusic_config* cfg, bosmusic_t* out) {
                   hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&h->int_ev, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; ok && i < 3; ++i)
+            ok = hipEventCreateWithFlags(&h->pipe_ev[i], hipEventDisableTiming) == hipSuccess;
         for (int i = 0; ok && i < kMaxForks; ++i)
             ok = hipStreamCreateWithFlags(&h->cap[i], hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming) == hipSuccess;
@@ -1472,6 +1522,23 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
         const bool graph = (h->options & BM_OPT_GRAPH) && !(h->options & BM_OPT_TIMING);
         if (graph) return run_graph(h, frames, n_frames, groups, mode, s);
         for (auto& g : groups) {
+            if (g.second - g.first >= 2 && !(h->options & BM_OPT_TIMING)) {
+                // two halves pipelined on two streams (results do not depend on the split);
+                // with BM_OPT_TIMING each root-MUSIC launch runs alone, timed by its events
+                const int mid = g.first + (g.second - g.first + 1) / 2;
+                GroupPlan ga, gb;
+                size_t used_a = 0;
+                for (int i = g.first; i < mid; ++i) used_a += frame_ws_bytes(frames[i]) + 3 * 256;
+                bm_status st = plan_group(h, frames, g.first, mid, mode, ga);
+                if (st == BM_OK) st = plan_group(h, frames, mid, g.second, mode, gb, align_up(used_a, 256));
+                if (st == BM_OK) {
+                    log_line(h, "group frames %d..%d, mode %d: halves %d..%d and %d..%d on two streams", g.first,
+                             g.second - 1, mode, g.first, mid - 1, mid, g.second - 1);
+                    st = run_pair_eager(h, ga, gb, s);
+                }
+                if (st != BM_OK) return st;
+                continue;
+            }
             GroupPlan gp;
             bm_status st = plan_group(h, frames, g.first, g.second, mode, gp);
             if (st == BM_OK && h->log) {

@@ -96,6 +96,32 @@ def test_workspace_chunking_gives_identical_results(bm, torch):
     small.close()
 
 
+def test_pipelined_halves_on_a_side_stream(bm, torch):
+    """A batch of two or more frames runs as two halves on two streams; the call stays
+    ordered on the caller's stream: work enqueued on it before the call (poisoned
+    outputs) is seen, back-to-back calls without a host wait give the single-frame
+    results, and the caller's stream holds the finished maps when the call returns."""
+    d = bm.Demodulator(0, max_width=1024, max_height=1024, max_batch_pixels=4 << 20)
+    specs, _ = make_batch(bm, torch, flags=True)
+    for s in specs:
+        bm.bosmusic_demodulate(d.h, [s])
+    ref = outputs(torch, specs)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for rep in range(3):
+            for s in specs:
+                for t in (s.omega_x, s.omega_y):
+                    if t is not None:
+                        t.fill_(123.0 + rep)
+                s.flags.fill_(7)
+            bm.bosmusic_demodulate(d.h, specs, stream=side)
+            bm.bosmusic_demodulate(d.h, specs[::-1], stream=side)
+        snap = [None if t is None else t.clone() for s in specs for t in (s.omega_x, s.omega_y, s.flags)]
+    side.synchronize()
+    same(ref, [None if t is None else t.cpu().numpy() for t in snap])
+    d.close()
+
+
 def test_graph_replays_match_eager(bm, torch):
     eager = bm.Demodulator(0, max_width=1024, max_height=1024, max_batch_pixels=4 << 20)
     graph = bm.Demodulator(0, max_width=1024, max_height=1024, max_batch_pixels=4 << 20, graph=True)
