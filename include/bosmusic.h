@@ -20,8 +20,9 @@
  *   - signal/noise eigen-split with a one-dimensional signal subspace
  *     (Eq. 6-11): the top eigenvector of the real form of the covariance,
  *     by power iteration where an a-posteriori bound proves it within
- *     1e-5 rad, else by a tridiagonal solver (line windows; block windows
- *     always take the solver);
+ *     1e-5 rad, else by a tridiagonal solver (the power iteration starts
+ *     at a line window's lag-1 phase, at a block window's summed lag-1
+ *     phase, or at the surrogate's prediction);
  *   - root-MUSIC polynomial a(z)^H Un Un^H a(z) (Eq. 12) from the diagonal
  *     sums of the noise projector, degree 2L-2;
  *   - the root pair nearest the unit circle (Sec. 3, selection rule): found
