@@ -151,6 +151,9 @@ inline bool fft_big_radix(const FftJob& j) {
 // Kernel variant of a job: radices up to 5, or up to 13; 256 or 1024 threads;
 // or the register-resident path of R0 = 2, 4, 8, 16 (classes 4 .. 7).
 constexpr int kFftClasses = 8;
+// A job of the 1024-thread kernel variants (classes 2 and 3).
+inline bool fft_wide(const FftJob& j) { return !j.pow2 && j.plan.n >= kFftWideMin; }
+
 inline int fft_class(const FftJob& j) {
     if (j.pow2) return j.pow2 == 2 ? 4 : j.pow2 == 4 ? 5 : j.pow2 == 8 ? 6 : 7;
     return (fft_big_radix(j) ? 1 : 0) + (j.plan.n >= kFftWideMin ? 2 : 0);

@@ -1531,13 +1531,18 @@ bm_status bosmusic_demodulate(bosmusic_t h, const bosmusic_frame* frames, int32_
                 for (int i = g.first; i < mid; ++i) used_a += frame_ws_bytes(frames[i]) + 3 * 256;
                 bm_status st = plan_group(h, frames, g.first, mid, mode, ga);
                 if (st == BM_OK) st = plan_group(h, frames, mid, g.second, mode, gb, align_up(used_a, 256));
-                if (st == BM_OK) {
+                if (st != BM_OK) return st;
+                // a 1024-thread analytic block needs a whole CU's wave slots, so it waits
+                // for the root-MUSIC launch to drain (measured slower on the 19-frame
+                // 1850 x 700 series): a second half with such lines runs after the first
+                bool wide = false;
+                for (auto& f : gb.fft) wide |= bm::fft_wide(f);
+                if (!wide) {
                     log_line(h, "group frames %d..%d, mode %d: halves %d..%d and %d..%d on two streams", g.first,
                              g.second - 1, mode, g.first, mid - 1, mid, g.second - 1);
-                    st = run_pair_eager(h, ga, gb, s);
+                    if ((st = run_pair_eager(h, ga, gb, s)) != BM_OK) return st;
+                    continue;
                 }
-                if (st != BM_OK) return st;
-                continue;
             }
             GroupPlan gp;
             bm_status st = plan_group(h, frames, g.first, g.second, mode, gp);
