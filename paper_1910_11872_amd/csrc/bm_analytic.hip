@@ -215,6 +215,11 @@ __device__ __forceinline__ float load_real(const void* base, int64_t idx, int el
 
 __device__ __forceinline__ float2 conjf2(float2 v) { return make_float2(v.x, -v.y); }
 
+// Gamma is stored with streaming (nontemporal) stores: a later launch reads it,
+// long after it has left the caches, while the samples that the analytic
+// kernels read a second time should stay there.
+typedef float f2v __attribute__((ext_vector_type(2)));
+
 // One block per pair of lines (2i, 2i+1; a lone last line pairs with zeros).
 // With z = x_a + i x_b and Z = DFT(z), the analytic signal of each real line
 // is Gamma = IFFT(H X) (reading of Sec. 2 / Eq. 1: H[0] = 0, H[k] = 2 for
@@ -267,8 +272,11 @@ __global__ __launch_bounds__(T) void analytic_kernel(FftBatch B, int item0) {
     for (int i = threadIdx.x; i < n; i += T) {
         const float sgn = (i & 1) ? -1.f : 1.f;
         const float2 y = Y[i];
-        out[i] = make_float2(load_real(J.src, off + i, elem) - dca - sgn * nqa, y.x);
-        if (two) out[n + i] = make_float2(load_real(J.src, off + J.src_ls + i, elem) - dcb - sgn * nqb, -y.y);
+        __builtin_nontemporal_store(f2v{load_real(J.src, off + i, elem) - dca - sgn * nqa, y.x},
+                                    reinterpret_cast<f2v*>(out + i));
+        if (two)
+            __builtin_nontemporal_store(f2v{load_real(J.src, off + J.src_ls + i, elem) - dcb - sgn * nqb, -y.y},
+                                        reinterpret_cast<f2v*>(out + n + i));
     }
 }
 
@@ -477,8 +485,10 @@ __global__ __launch_bounds__(256) void analytic_pow2_kernel(FftBatch B, int item
     for (int s = 0; s < 16; ++s) {
         const int i = j + s * T;
         const float sgn = (i & 1) ? -1.f : 1.f;
-        if (has_a) out[i] = make_float2(load_real(J.src, off + i, elem) - dca - sgn * nqa, z[s].x);
-        if (has_b) out[n + i] = make_float2(load_real(J.src, off + J.src_ls + i, elem) - dcb - sgn * nqb, -z[s].y);
+        if (has_a) __builtin_nontemporal_store(f2v{load_real(J.src, off + i, elem) - dca - sgn * nqa, z[s].x},
+                                               reinterpret_cast<f2v*>(out + i));
+        if (has_b) __builtin_nontemporal_store(f2v{load_real(J.src, off + J.src_ls + i, elem) - dcb - sgn * nqb, -z[s].y},
+                                               reinterpret_cast<f2v*>(out + n + i));
     }
 }
 
