@@ -200,14 +200,14 @@ bm_status bosmusic_destroy(bosmusic_t h);
  * distinct L (with BM_OPT_GRAPH: one replay of a cached hipGraph holding them,
  * the per-L launches on forked streams).  Without BM_OPT_GRAPH and
  * BM_OPT_TIMING, a group of two or more frames runs as two halves on
- * `stream` and a second stream of the handle (unless the second half has a
- * real line longer than 2048 samples whose length is not a power of two:
- * its analytic step's 1024-thread blocks cannot run beside the root-MUSIC
- * launch): the second half's transpose and
- * analytic launches run beside the first half's root-MUSIC launch, its
+ * `stream` and a second stream of the handle: the second half's transpose
+ * and analytic launches run beside the first half's root-MUSIC launch, its
  * root-MUSIC launch after the first half's; `stream` waits for the second
  * stream before the call returns, so every output is ordered on `stream`
- * as if the work had been enqueued there alone.  The job tables of a group are
+ * as if the work had been enqueued there alone.  (Not when the second half
+ * has a real line longer than 2048 samples whose length is not a power of
+ * two: the analytic step's 1024-thread blocks for it cannot run beside a
+ * root-MUSIC launch, so the group runs in `stream` alone.)  The job tables of a group are
  * uploaded from pinned host memory on `stream`; the call may wait for the
  * previous call's upload to finish before reusing that buffer.
  * mode: BM_PLAIN, or BM_SURROGATE (needs loaded parameters unless the
